@@ -1,0 +1,302 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: an
+independently built constant, the determinant form of the Wick sum, a
+library DFT, an exact symmetry of Eq. (1), or a closed form.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from tests import physics_ref as ref
+
+RTOL = 1e-12
+
+
+def rel(a, b):
+    return np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300)
+
+
+def F(L, S, chans, mode="direct"):
+    return oracle.correlators(L, S, chans, mode=mode)
+
+
+# --- constants -----------------------------------------------------------
+
+def test_cg5_is_dirac_representation():
+    """C gamma_5 of the oracle equals C gamma_5 built from the Dirac matrices."""
+    np.testing.assert_array_equal(oracle.cg5(), np.real(ref.dirac_cg5()))
+    assert np.allclose(np.imag(ref.dirac_cg5()), 0)
+
+
+@pytest.mark.parametrize("op", sorted(ref.OPERATORS))
+def test_operator_content(op):
+    """Flavour content and weights of Eqs. (2)-(3)."""
+    got = oracle.expand_op(op)
+    want = ref.OPERATORS[op]
+    assert len(got) == len(want)
+    for (gf, gw), (wf, ww) in zip(got, want):
+        assert gf == wf and math.isclose(gw, ww, rel_tol=1e-15)
+
+
+def test_naive_iteration_count_pLambda():
+    """Sec. 2: the naive count (Nc! Na)^B Nu! Nd! Ns! 2^(NL+NS0-B) = 3456 for
+    <p Lambda pbar Xu-bar>; the Wick enumeration yields Nu! Nd! Ns! = 12
+    flavour-respecting permutations for each of the three Lambda terms."""
+    n_terms, n_perms = oracle.count_perms(("p", "Lambda", "p", "Xu"))
+    assert (n_terms, n_perms) == (3, 3 * 12)
+    Nc, Na, B = 3, 4, 2
+    naive = (math.factorial(Nc) * Na) ** B * math.factorial(3) * math.factorial(2) * 2.0 ** (1 + 0 - B)
+    assert naive == 3456
+
+
+@pytest.mark.parametrize("chan,expected", [
+    (("p", "p", "p", "p"), 4 * 3 * 2 * 2),             # 4 u, 2 d
+    (("Xi0", "Xi-", "Xi0", "Xi-"), 1 * 1 * 24),         # 1 u, 1 d, 4 s
+    (("Lambda", "Lambda", "Sigma+", "Sigma-"), 9 * 2 * 2 * 2),
+])
+def test_wick_permutation_counts(chan, expected):
+    assert oracle.count_perms(chan)[1] == expected
+
+
+# --- normal blocks -------------------------------------------------------
+
+def test_normal_block_diquark_exchange():
+    """eps and C gamma_5 are both antisymmetric, so exchanging the first two
+    quarks of a block leaves it unchanged: N_{f1 f2 f3}[a][j1][j2][j3] =
+    N_{f2 f1 f3}[a][j2][j1][j3] (Eq. (5))."""
+    rng = np.random.default_rng(1)
+    L = (2, 2, 1)
+    S = ref.random_props(rng, L)
+    A = oracle.normal_blocks(L, S, 0, 2, 1)
+    B = oracle.normal_blocks(L, S, 2, 0, 1)
+    np.testing.assert_allclose(A, B.transpose(0, 1, 3, 2, 4), rtol=0, atol=1e-13)
+
+
+def test_normal_block_single_term():
+    """With delta-like propagators only one (colour, spin) term survives."""
+    L = (1, 1, 1)
+    S = [np.zeros((1, 12, 12), complex) for _ in range(3)]
+    for f in range(3):
+        S[f][0] = np.eye(12)
+    N = oracle.normal_blocks(L, S, 0, 1, 2)[0]
+    cg5 = np.real(ref.dirac_cg5())
+    for al in range(2):
+        for j1 in range(12):
+            for j2 in range(12):
+                for j3 in range(12):
+                    (b1, a), (b2, b), (b3, c) = divmod(j1, 3), divmod(j2, 3), divmod(j3, 3)
+                    want = ref.levi_civita(a, b, c) * cg5[b1, b2] * (b3 == al)
+                    assert N[al, j1, j2, j3] == want
+
+
+# --- the Wick sum against its determinant form --------------------------
+
+@pytest.mark.parametrize("chan,spins", [
+    (("p", "p", "p", "p"), (0, 1, 0, 1)),
+    (("p", "p", "p", "p"), (1, 1, 1, 0)),
+    (("n", "Sigma+", "p", "Sigma0"), (0, 1, 1, 0)),
+    (("Xi0", "Xi-", "Xi0", "Xi-"), (1, 0, 0, 1)),
+    (("p", "Xu", "Xs", "p"), (1, 1, 0, 1)),
+])
+def test_wick_sum_equals_determinant_form(chan, spins):
+    """Eq. (1) evaluated by expanding the operators into quark fields and
+    taking <q1 .. q6 qbar'6 .. qbar'1> as a determinant (the signed sum over
+    all pairings) matches the oracle's permutation enumeration (Eq. (4)).
+    Lattice 3x1x1 so that r and -r differ."""
+    rng = np.random.default_rng(7)
+    L = (3, 1, 1)
+    S = ref.random_props(rng, L)
+    Fo = F(L, S, [chan], mode="direct")[0].reshape(16, -1)
+    s = 8 * spins[0] + 4 * spins[1] + 2 * spins[2] + spins[3]
+    for r in (1,):
+        want = ref.brute_force_correlator(L, S, chan, spins, (r, 0, 0))
+        got = Fo[s, r]
+        assert abs(got - want) <= 1e-11 * max(1.0, abs(want)), (got, want)
+        assert abs(want) > 1e-3
+
+
+# --- Sigma_X: direct vs DFT, and the DFT itself --------------------------
+
+def test_dft_matches_numpy_fft():
+    rng = np.random.default_rng(3)
+    L = (4, 3, 5)
+    data = rng.standard_normal((60, 7)) + 1j * rng.standard_normal((60, 7))
+    got = oracle.dft3(data, L, -1).reshape(5, 3, 4, 7)
+    want = np.fft.fftn(data.reshape(5, 3, 4, 7), axes=(0, 1, 2))
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-12)
+    back = oracle.dft3(got.reshape(60, 7), L, +1) / 60
+    np.testing.assert_allclose(back, data, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("L", [(2, 2, 2), (4, 2, 3)])
+def test_direct_sum_equals_fft_correlation(L):
+    """Eq. (4) (direct sum over X) and Eq. (6) (DFT correlation) agree."""
+    rng = np.random.default_rng(11)
+    S = ref.random_props(rng, L)
+    chans = [("p", "p", "p", "p"), ("p", "Lambda", "p", "Xu"), ("Lambda", "Lambda", "Sigma+", "Sigma-")]
+    Fd = F(L, S, chans, "direct")
+    Ff = F(L, S, chans, "fft")
+    for c in range(len(chans)):
+        assert rel(Ff[c], Fd[c]) < 1e-13
+
+
+def test_correlator_at_q_and_sum_rule():
+    """F~(q) at single momenta equals the DFT of F(r); q = 0 gives the sum
+    rule sum_r F(r) = F~(0)."""
+    rng = np.random.default_rng(5)
+    L = (4, 2, 2)
+    S = ref.random_props(rng, L)
+    chans = [("p", "Sigma0", "n", "Sigma+"), ("Xi0", "Lambda", "Xi0", "Sigma0")]
+    Fr = F(L, S, chans, "fft")
+    Fq = np.fft.fftn(Fr, axes=(2, 3, 4))  # [c, s, qz, qy, qx]
+    for q in [(0, 0, 0), (1, 0, 1), (3, 1, 0)]:
+        got = oracle.correlators_at_q(L, S, chans, q)
+        want = Fq[:, :, q[2], q[1], q[0]]
+        assert rel(got, want) < 1e-12
+    np.testing.assert_allclose(oracle.correlators_at_q(L, S, chans, (0, 0, 0)),
+                               Fr.sum(axis=(2, 3, 4)), rtol=1e-12, atol=1e-9)
+
+
+# --- exact symmetries of Eq. (1) ------------------------------------------
+
+def _neg_r(Fc):
+    """G(r) -> G(-r) on [..., Lz, Ly, Lx] arrays."""
+    return np.roll(np.flip(Fc, axis=(-3, -2, -1)), shift=1, axis=(-3, -2, -1))
+
+
+def _swap_sink_spins(Fc):
+    out = np.empty_like(Fc)
+    for s in range(16):
+        a1, a2, a3, a4 = (s >> 3) & 1, (s >> 2) & 1, (s >> 1) & 1, s & 1
+        out[8 * a2 + 4 * a1 + 2 * a3 + a4] = Fc[s]
+    return out
+
+
+def _swap_source_spins(Fc):
+    out = np.empty_like(Fc)
+    for s in range(16):
+        a1, a2, a3, a4 = (s >> 3) & 1, (s >> 2) & 1, (s >> 1) & 1, s & 1
+        out[8 * a1 + 4 * a2 + 2 * a4 + a3] = Fc[s]
+    return out
+
+
+def test_sink_exchange_antisymmetry():
+    """B1(X+r) B2(X) = -B2(X) B1(X+r): F^{B1B2}_{a1a2}(r) = -F^{B2B1}_{a2a1}(-r)."""
+    rng = np.random.default_rng(13)
+    L = (3, 2, 2)
+    S = ref.random_props(rng, L)
+    A, B = F(L, S, [("p", "Lambda", "p", "Xu"), ("Lambda", "p", "p", "Xu")], "fft")
+    assert rel(A, -_neg_r(_swap_sink_spins(B))) < 1e-13
+
+
+def test_source_exchange_antisymmetry():
+    rng = np.random.default_rng(17)
+    L = (2, 3, 2)
+    S = ref.random_props(rng, L)
+    A, B = F(L, S, [("Sigma+", "Xi-", "p", "Xi-"), ("Sigma+", "Xi-", "Xi-", "p")], "fft")
+    assert rel(A, -_swap_source_spins(B)) < 1e-13
+
+
+def test_identical_source_baryons_vanish_on_equal_spins():
+    rng = np.random.default_rng(19)
+    L = (2, 2, 2)
+    S = ref.random_props(rng, L)
+    Fc = F(L, S, [("p", "p", "p", "p")], "fft")[0]
+    for s in range(16):
+        a3, a4 = (s >> 1) & 1, s & 1
+        if a3 == a4:
+            assert np.abs(Fc[s]).max() < 1e-12 * np.abs(Fc).max()
+    assert np.abs(Fc).max() > 1.0
+
+
+def test_flavour_relabelling_with_equal_propagators():
+    """With S_u = S_d = S_s the pp, Sigma+Sigma+ and Xi0Xi0 correlators coincide."""
+    rng = np.random.default_rng(23)
+    L = (2, 2, 2)
+    S1 = ref.random_props(rng, L, n=1)[0]
+    S = [S1, S1, S1]
+    pp, ss, xx = F(L, S, [("p", "p", "p", "p"), ("Sigma+", "Sigma+", "Sigma+", "Sigma+"),
+                          ("Xi0", "Xi0", "Xi0", "Xi0")], "fft")
+    assert rel(ss, pp) < 1e-13
+    assert rel(xx, pp) < 1e-13
+
+
+def test_translation_invariance():
+    rng = np.random.default_rng(29)
+    L = (4, 2, 3)
+    S = ref.random_props(rng, L)
+    shift = (1, 1, 2)
+    Sh = [np.roll(s.reshape(L[2], L[1], L[0], 12, 12), shift=(shift[2], shift[1], shift[0]),
+                  axis=(0, 1, 2)).reshape(-1, 12, 12) for s in S]
+    chans = [("p", "Sigma0", "n", "Sigma+"), ("Lambda", "Lambda", "p", "Xi-")]
+    assert rel(F(L, Sh, chans, "fft"), F(L, S, chans, "fft")) < 1e-13
+
+
+def test_colour_gauge_invariance():
+    """A local SU(3) rotation at the sink (same for all flavours) and a global
+    one at the source leave F unchanged (eps Omega Omega Omega = det Omega eps)."""
+    rng = np.random.default_rng(31)
+    L = (2, 2, 1)
+    V = 4
+    S = ref.random_props(rng, L)
+    src = ref.colour_matrix(ref.random_su3(rng))
+    sink = [ref.colour_matrix(ref.random_su3(rng)) for _ in range(V)]
+    Sg = [np.stack([sink[x] @ s[x] @ src.T for x in range(V)]) for s in S]
+    chans = [("p", "Lambda", "p", "Xu"), ("Xi0", "Sigma-", "n", "Xi-")]
+    assert rel(F(L, Sg, chans, "fft"), F(L, S, chans, "fft")) < 1e-12
+
+
+def test_scale_covariance():
+    """S_f -> lambda_f S_f multiplies F by prod_f lambda_f^(n_f)."""
+    rng = np.random.default_rng(37)
+    L = (2, 2, 2)
+    S = ref.random_props(rng, L)
+    lam = (0.5, 3.0, 1.25)
+    Ss = [lam[f] * S[f] for f in range(3)]
+    n = (3, 2, 1)  # quark content of p Lambda: u u u d d s
+    fac = lam[0] ** n[0] * lam[1] ** n[1] * lam[2] ** n[2]
+    chan = [("p", "Lambda", "p", "Xu")]
+    assert rel(F(L, Ss, chan, "fft"), fac * F(L, S, chan, "fft")) < 1e-13
+
+
+def test_source_linearity_lambda_sigma0():
+    rng = np.random.default_rng(41)
+    L = (2, 2, 2)
+    S = ref.random_props(rng, L)
+    ch = [("p", "Lambda", "p", x) for x in ("Lambda", "Sigma0", "Xu", "Xd", "Xs")]
+    fl, fs, fu, fd, fs_ = F(L, S, ch, "fft")
+    assert rel(fl, (fu + fd - 2 * fs_) / math.sqrt(6)) < 1e-13
+    assert rel(fs, (fu - fd) / math.sqrt(2)) < 1e-13
+
+
+# --- closed forms ---------------------------------------------------------
+
+@pytest.mark.parametrize("chan", [("p", "p", "p", "p"), ("p", "Lambda", "p", "Xu"),
+                                  ("Xi0", "Xi-", "Xi0", "Xi-")])
+def test_unit_and_scalar_field_propagators(chan):
+    """S_f(x) = 1: F(r) = V K_c for every r, with K_c the single-site value of
+    the determinant form.  S_f(x) = phi(x) 1: F(r) = K_c sum_X phi(X+r)^3
+    phi(X)^3, which fixes the orientation of r."""
+    L = (3, 2, 1)
+    V = 6
+    one = [np.broadcast_to(np.eye(12, dtype=complex), (V, 12, 12)).copy() for _ in range(3)]
+    F1 = F(L, one, [chan], "fft")[0].reshape(16, V)
+    rng = np.random.default_rng(43)
+    phi = rng.standard_normal(V) + 1j * rng.standard_normal(V)
+    Sphi = [phi[:, None, None] * s for s in one]
+    Fphi = F(L, Sphi, [chan], "direct")[0].reshape(16, V)
+    single = [np.eye(12, dtype=complex)[None] for _ in range(3)]
+    for s in range(16):
+        spins = ((s >> 3) & 1, (s >> 2) & 1, (s >> 1) & 1, s & 1)
+        K = ref.brute_force_correlator((1, 1, 1), single, chan, spins, (0, 0, 0))
+        w = math.sqrt(6.0) if "Lambda" in chan else 1.0
+        assert abs(K * w - round((K * w).real)) < 1e-9  # an integer count times the weights
+        np.testing.assert_allclose(F1[s], V * K, rtol=0, atol=1e-9)
+        for r in range(V):
+            rx, ry = r % 3, r // 3
+            want = sum(phi[ref.site_index(L, X % 3 + rx, X // 3 + ry, 0)] ** 3 * phi[X] ** 3
+                       for X in range(V)) * K
+            assert abs(Fphi[s, r] - want) <= 1e-10 * max(1.0, abs(want))
