@@ -1,0 +1,163 @@
+"""Benchmark of the NBS hot path on one MI355X.
+
+A step is one pass of the whole path over one window of time slices:
+nbs_build_blocks (normal blocks + forward 3-D FFT), nbs_contract_channels
+(effective blocks and their products) and nbs_relative_sum (inverse FFT),
+on synthetic seeded propagators already resident in HBM.
+
+Default workload: plain FP64 form, 16^3 x 32 lattice, all 52 channels of the
+R52 table, u, d, s propagators with decay rates 0.4 / 0.4 / 0.55.
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+CONFIGS = {
+    # name: (L, T, t_begin, t_count, prec, decay, label)
+    "fp64_16c32": ((16, 16, 16), 32, 0, 32, 0, {"u": 0.4, "d": 0.4, "s": 0.55},
+                   "plain FP64, 16^3x32, 52 channels (R52), u/d/s decay 0.4/0.4/0.55"),
+    "fp32_32c64": ((32, 32, 32), 64, 0, 16, 1, {"u": 0.4, "d": 0.4, "s": 0.55},
+                   "precision form (FP32 blocks/contractions, FP64 FFT), 32^3x64, 52 channels, "
+                   "window of 16 slices"),
+}
+
+PEAK = {"hbm": 8.0e12, "fp64": 78.6e12, "fp32_vector": 157.3e12}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="fp64_16c32", choices=sorted(CONFIGS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def program_work(plan):
+    """Algorithmic work per momentum site of the contraction program:
+    (EBB flops, MEB flops).  EBB: 4 flops per (real coefficient x complex
+    block entry) accumulation; MEB: 8 flops per complex multiply-add."""
+    import numpy as np
+    terms = len(plan.table("terms"))
+    K = plan.table("meb_kn").astype(np.int64)
+    rows1 = plan.table("meb_rows1")
+    macs = int((K * 16).sum())
+    del rows1
+    return 4.0 * terms, 8.0 * macs
+
+
+def cpu_baseline():
+    """The oracle (FFT mode, all 52 channels) on one time slice of an 8^3
+    lattice with the same generator: a bounded sample of the per-site work."""
+    import numpy as np
+    import oracle
+    from paper_1604_07983_amd import channels, runner
+    L = (8, 8, 8)
+    props = runner.host_props(L, 32, [5])
+    S = [np.ascontiguousarray(p[0].reshape(-1, 12, 12)) for p in props]
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    omp = os.environ.get("OMP_NUM_THREADS")
+    if omp:
+        cores = min(cores, int(omp))
+    t = time.perf_counter()
+    oracle.correlators(L, S, channels.r52(), mode="fft")
+    dt = time.perf_counter() - t
+    return {"value": 512 * 52 / dt, "unit": "site-channels/s", "cores": cores, "kind": "oracle",
+            "sample": "oracle DFT-correlation mode, all 52 channels, one slice of an 8^3 lattice "
+                      "(512 sites), %.1f s" % dt}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(a time-slice split would need no communication; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1604_07983_amd import binding, channels, runner
+
+    L, T, tb, tc, prec, decay, label = CONFIGS[args.config]
+    chans = channels.r52()
+    V = L[0] * L[1] * L[2]
+    dt = np.complex128 if prec == 0 else np.complex64
+    print("[bench] generating propagators %s" % (L,), file=sys.stderr, flush=True)
+    props = runner.host_props(L, T, range(tb, tb + tc), decay=decay, dtype=dt)
+    dp = runner.device_props(props, prec)
+    del props
+    r = runner.Runner(L, T, chans, prec=prec, t_begin=tb, t_count=tc)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        if ev:
+            ev[0].record(stream)
+        r.build(*dp)
+        if ev:
+            ev[1].record(stream)
+        r.contract()
+        if ev:
+            ev[2].record(stream)
+        r.relative_sum()
+        if ev:
+            ev[3].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stage = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(3)] for e in evs])  # ms
+    ms_step = wall * 1e3 / args.steps
+    sites = V * tc
+    value = sites * len(chans) / (ms_step * 1e-3)
+
+    ebb_f, meb_f = program_work(r.plan)
+    contract_ms = float(stage[:, 1].mean())
+    contract_flops = (ebb_f + meb_f) * sites
+    # FFT traffic: three passes, each reads and writes every block entry
+    el = 16 if prec == 0 else 8
+    n_types = r.plan.info()["n_types"]
+    build_bytes = sites * (3 * 144 * el + n_types * 3456 * el * (1 + 2 * 3))
+    total_flops = contract_flops + sites * (n_types * 3456 * 3 * 8 + n_types * 3456 * 5 * np.log2(V) * 1.0)
+    roof = {"bound": "alu", "achieved": contract_flops / (contract_ms * 1e-3) / 1e12,
+            "peak": PEAK["fp64"] / 1e12 if prec == 0 else PEAK["fp32_vector"] / 1e12,
+            "unit": "TFLOP/s", "traffic": None,
+            "kernel": "k_contract (effective blocks + products)"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    out = {
+        "metric": "NBS site-channels/sec + GFLOP/s, FP32-MFMA batched vs FP64 plain at stated rel err",
+        "value": value, "unit": "site-channels/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == 0 else "f32", "data": "synthetic",
+        "config": {"workload": label, "lattice": list(L), "T": T, "slices": tc, "channels": len(chans),
+                   "sites_per_step": sites},
+        "gflops": total_flops / (ms_step * 1e-3) / 1e9,
+        "stage_ms": {"build_blocks": float(stage[:, 0].mean()), "contract_channels": contract_ms,
+                     "relative_sum": float(stage[:, 2].mean())},
+        "build_hbm_gbs": build_bytes / (stage[:, 0].mean() * 1e-3) / 1e9,
+        "roofline": roof,
+    }
+    r.close()
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,178 @@
+/*
+ * nbs.h -- C ABI of libnbs: two-baryon Nambu-Bethe-Salpeter four-point
+ * functions by the effective baryon block algorithm, on AMD Instinct MI355X
+ * (gfx950).
+ *
+ * The three compute calls follow the three stages of Eq. (6) of Nemura,
+ * "An implementation of hybrid parallel CUDA code for the hyperonic nuclear
+ * forces" (LATTICE 2015):
+ *
+ *   nbs_build_blocks       normal baryon blocks [B^(0)](x; xi1, xi2, xi3) of
+ *                          Eq. (5) / Sec. 3(i) Eq. (8) on every sink site, then
+ *                          their 3-D Fourier transform to momentum space
+ *                          ("replaced by its in momentum space", Sec. 3(i));
+ *   nbs_contract_channels  effective baryon blocks in momentum space
+ *                          (Sec. 3(ii), Eq. (9)) and their products summed
+ *                          over the shared source indices and diagrams
+ *                          (Sec. 3(iii), Eq. (10)), giving F~_c(q) per channel;
+ *   nbs_relative_sum       inverse Fourier transform with the 1/L^3 of
+ *                          Eq. (6): the sum over X at every relative r, i.e.
+ *                          F_c(r, t - t0) of Eq. (1).
+ *
+ * Every step runs in HIP kernels on the device; there is no host fallback.
+ *
+ * Conventions
+ *   - Propagator of flavour f (u, d, s) on one time slice: 12 x 12 complex
+ *     per site, row = 3 * spin + colour at the sink, column = 3 * spin +
+ *     colour at the wall source.  Sites are ordered x + Lx * (y + Ly * z).
+ *   - Spin components alpha_1..alpha_4 take the upper Dirac components
+ *     {0, 1} (Dirac representation, C gamma_5 = diag(i s2, i s2)).
+ *   - Output index s = 8 alpha_1 + 4 alpha_2 + 2 alpha_3 + alpha_4, and
+ *     r = x_{B1} - x_{B2} mod L.
+ *
+ * Error behaviour: every call returns an nbs_status; nothing throws across
+ * the ABI.  Arguments are validated on the host before any launch.  A HIP
+ * failure maps to NBS_ERR_DEVICE and the message is kept per plan
+ * (nbs_last_error).  A plan is not thread-safe; separate plans are
+ * independent.
+ */
+#ifndef NBS_H
+#define NBS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NBS_OK = 0,
+  NBS_ERR_INVALID = 1,     /* bad argument (geometry, channel, pointer) */
+  NBS_ERR_UNSUPPORTED = 2, /* valid request this build does not handle */
+  NBS_ERR_NOMEM = 3,       /* device workspace does not fit */
+  NBS_ERR_DEVICE = 4,      /* a HIP call failed */
+  NBS_ERR_STATE = 5        /* calls out of order, or compute on a host-only plan */
+} nbs_status;
+
+typedef enum {
+  NBS_FP64 = 0,     /* plain form: complex128 propagators, FP64 throughout */
+  NBS_FP32_MFMA = 1 /* precision form: complex64 propagators, per-slice
+                       power-of-two scale, FP32 blocks and contractions,
+                       FP64 Fourier transforms and normalisation */
+} nbs_precision;
+
+/* Interpolating fields of Eqs. (2)-(3). */
+typedef enum {
+  NBS_P = 0, NBS_N, NBS_LAMBDA, NBS_SIGMA_P, NBS_SIGMA_0, NBS_SIGMA_M,
+  NBS_XI_0, NBS_XI_M, NBS_X_U, NBS_X_D, NBS_X_S, NBS_NUM_OPS
+} nbs_op;
+
+/* One lattice and one source slice.  The plan processes the window of
+ * t_count consecutive sink slices starting at t_begin (absolute time);
+ * t0 is the source slice.  L[0..2] = (Lx, Ly, Lz), each >= 2 and a product
+ * of powers of 2, 3 and 5, at most 128. */
+typedef struct {
+  int32_t L[3];
+  int32_t T, t0, t_begin, t_count;
+} nbs_geometry;
+
+/* Channel <B1 B2 | B3bar B4bar>: sink operators then source operators.
+ * Flavour must be conserved (same u, d, s content on both sides). */
+typedef struct {
+  int32_t sink[2], src[2];
+} nbs_channel;
+
+typedef struct nbs_plan_s* nbs_plan;
+
+/* Compile the channel table (Sec. 3(ii)-(iii): diagram classification into
+ * structure-of-arrays tables, done once on the host) and allocate device
+ * workspace.  g: n_geom geometries (this build: n_geom == 1).
+ * device >= 0: the HIP device to use; device == -1: host-only plan that
+ * holds the compiled tables for inspection (nbs_plan_info, nbs_plan_diagrams,
+ * nbs_plan_table, nbs_plan_params)
+ * and rejects the compute calls with NBS_ERR_STATE.
+ * On failure *out is NULL and nothing stays allocated. */
+nbs_status nbs_plan_create(nbs_plan* out, const nbs_geometry* g, int32_t n_geom,
+                           const nbs_channel* ch, int32_t n_ch,
+                           nbs_precision prec, int32_t device);
+
+/* Device bytes the plan owns (workspace + tables). */
+nbs_status nbs_workspace_bytes(const nbs_plan plan, size_t* bytes);
+
+/* Stage 1 (Eq. (5)/(8), then the forward transform of Eq. (6)).
+ * prop_u/d/s[g]: device pointers, one per geometry, each
+ * [t_count][Lz][Ly][Lx][12][12] complex (complex128 for NBS_FP64,
+ * complex64 for NBS_FP32_MFMA), owned by the caller and read-only.
+ * prop_d / prop_s may alias prop_u.  stream: a hipStream_t (NULL = the
+ * default stream); the call is asynchronous on it. */
+nbs_status nbs_build_blocks(nbs_plan plan, const void* const* prop_u,
+                            const void* const* prop_d, const void* const* prop_s,
+                            void* stream);
+
+/* Stage 2 (Eqs. (9)-(10)): effective blocks and their products, F~_c(q).
+ * Must follow nbs_build_blocks on the same plan. */
+nbs_status nbs_contract_channels(nbs_plan plan, void* stream);
+
+/* Stage 3 (inverse transform of Eq. (6), 1/L^3, undo of the per-slice
+ * scale in FP64).  F_out[g]: device pointer, complex128
+ * [n_ch][t_count][16][Lz][Ly][Lx], owned by the caller.  Must follow
+ * nbs_contract_channels. */
+nbs_status nbs_relative_sum(nbs_plan plan, void* const* F_out, void* stream);
+
+/* Release everything the plan owns (waits for its device work). NULL is ok. */
+nbs_status nbs_plan_destroy(nbs_plan plan);
+
+const char* nbs_status_string(nbs_status s);
+/* Message of the last failure on this plan ("" if none). */
+const char* nbs_last_error(const nbs_plan plan);
+
+/* ---- inspection of the compiled channel table (host-only) -------------- */
+
+typedef struct {
+  int32_t n_channels;
+  int32_t n_types;        /* distinct flavour triplets whose blocks are built */
+  int32_t n_diagrams;     /* (channel, source term, quark split) with both blocks non-empty */
+  int32_t n_blocks;       /* distinct effective blocks (per momentum side) */
+  int32_t n_products;     /* distinct block products after sharing across channels */
+  int64_t sum_k;          /* sum over diagrams of |xi~_d| (shared-index count) */
+  int64_t n_entries;      /* effective-block entries per momentum */
+  int64_t n_terms;        /* normal-block reads per momentum to build them */
+  int64_t n_wick_perms;   /* flavour-respecting Wick permutations covered */
+} nbs_plan_info_t;
+
+nbs_status nbs_plan_info(const nbs_plan plan, nbs_plan_info_t* info);
+
+/* One diagram of one channel, in the paper's convention (Eq. (7)): the
+ * source quarks given to the first sink baryon (bit k = source quark k+1),
+ * the sign of the permutation that gives them in ascending order,
+ * |xi~_d|, which of the labels alpha_3 / alpha_4 sit on the first block,
+ * and the open (shared) source indices as a bit set over
+ * (c'_k, alpha'_k): bit 2k = c'_{k+1}, bit 2k+1 = alpha'_{k+1}. */
+typedef struct {
+  int32_t channel, src_term, set1_mask, sign, k, labels1, open_mask;
+  double coef;            /* full coefficient used (weights x sign) */
+} nbs_diagram_t;
+
+/* Copy up to cap diagrams of channel ch (ch = -1: all) into out; *n gets
+ * the total count. */
+nbs_status nbs_plan_diagrams(const nbs_plan plan, int32_t ch, nbs_diagram_t* out,
+                             int32_t cap, int32_t* n);
+
+/* Copy one table of the compiled structure-of-arrays program (the tables
+ * the contraction kernel interprets; Sec. 3(ii)-(iii) ship such tables to
+ * the device) into buf: int32 tables by name ("group_chunk", "terms",
+ * "meb_e1", ...), "acc_coef" as double, "type_code" as int32.  *n gets the
+ * element count; at most cap elements are written.  Unknown name:
+ * NBS_ERR_INVALID. */
+nbs_status nbs_plan_table(const nbs_plan plan, const char* name, void* buf, int64_t cap, int64_t* n);
+
+/* Parameters of the program: LDS budgets the tables were packed for.
+ * out[0] = e_budget, out[1] = item_budget, out[2] = k_chunk,
+ * out[3] = max channels per group. */
+nbs_status nbs_plan_params(const nbs_plan plan, int32_t out[4]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NBS_H */

@@ -1,0 +1,51 @@
+"""Channel tables (data): operator names and the 52-channel reading R52.
+
+The paper computes 52 octet two-baryon channels but only cites the
+companion paper's Tables 1-4 for the list (Sec. 3(iii)).  R52 is a reading:
+particle-basis operators, isospin-symmetric coupled sectors at I_z = I, and
+u<->d-independent representatives of the S = -2, I_z = 0 block.  A corrected
+list drops in here without code changes.
+"""
+from __future__ import annotations
+
+# Operator codes of include/nbs.h (Eqs. (2)-(3)).
+OPS = {
+    "p": 0, "n": 1, "Lambda": 2, "Sigma+": 3, "Sigma0": 4, "Sigma-": 5,
+    "Xi0": 6, "Xi-": 7, "Xu": 8, "Xd": 9, "Xs": 10,
+}
+
+
+def _block(sinks, sources):
+    return [(a, b, c, d) for (a, b) in sinks for (c, d) in sources]
+
+
+def r52():
+    """The 52 channels (B1, B2, B3, B4) = <B1 B2 | B3bar B4bar>."""
+    ch = []
+    # S = 0
+    ch += [("p", "p", "p", "p"), ("p", "n", "p", "n")]
+    # S = -1
+    s1 = [("p", "Lambda"), ("p", "Sigma0"), ("n", "Sigma+")]
+    ch += _block(s1, s1)
+    ch += [("p", "Sigma+", "p", "Sigma+")]
+    # S = -2
+    ch += [("Sigma+", "Sigma+", "Sigma+", "Sigma+")]
+    s2 = [("p", "Xi0"), ("Lambda", "Sigma+"), ("Sigma0", "Sigma+")]
+    ch += _block(s2, s2)
+    ch += _block([("Lambda", "Lambda"), ("Sigma0", "Sigma0")],
+                 [("Lambda", "Lambda"), ("Sigma0", "Sigma0"), ("Sigma+", "Sigma-"), ("p", "Xi-")])
+    ch += _block([("p", "Xi-"), ("Sigma+", "Sigma-")],
+                 [("Lambda", "Lambda"), ("Sigma0", "Sigma0"), ("Sigma+", "Sigma-"), ("p", "Xi-"),
+                  ("n", "Xi0")])
+    # S = -3
+    s3 = [("Xi0", "Lambda"), ("Xi0", "Sigma0"), ("Xi-", "Sigma+")]
+    ch += _block(s3, s3)
+    ch += [("Xi0", "Sigma+", "Xi0", "Sigma+")]
+    # S = -4
+    ch += [("Xi0", "Xi0", "Xi0", "Xi0"), ("Xi0", "Xi-", "Xi0", "Xi-")]
+    assert len(ch) == 52
+    return ch
+
+
+# The paper's worked example, Eq. (7): <p Lambda | pbar Xu-bar>.
+WORKED_EXAMPLE = ("p", "Lambda", "p", "Xu")

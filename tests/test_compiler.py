@@ -1,0 +1,152 @@
+"""Host tests of the channel-table compiler and the C ABI (no GPU work).
+
+The compiled diagrams are checked against the paper's worked example, and
+the compiled SoA program is executed on the CPU by tests/program_emulator.py
+against the oracle's momentum-space correlators.
+"""
+import ctypes
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1604_07983_amd import binding, channels
+from tests import physics_ref as ref
+from tests import program_emulator as emu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def host_plan(chans, L=(4, 4, 4), T=8):
+    return binding.Plan(L, T, chans, device=-1)
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "nbs.h")).read()
+    declared = set(re.findall(r"^\s*(?:nbs_status|const char\*)\s+(nbs_\w+)\s*\(", hdr, re.M))
+    assert declared == set(binding.SYMBOLS)
+    lib = ctypes.CDLL(binding._LIB_PATH)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def _open_names(mask):
+    names = []
+    for k in range(6):
+        if (mask >> (2 * k)) & 1:
+            names.append("c%d" % (k + 1))
+        if (mask >> (2 * k + 1)) & 1:
+            names.append("alpha%d" % (k + 1))
+    return names
+
+
+def test_worked_example_diagrams_match_paper():
+    g = json.load(open(os.path.join(GOLDEN, "worked_example_pLambda_pXu.json")))
+    p = host_plan([tuple(g["channel"])])
+    ds = p.diagrams()
+    got = sorted((tuple(sorted(_open_names(d["open_mask"]))),
+                  tuple(l for b, l in ((1, "alpha3"), (2, "alpha4")) if d["labels1"] & b),
+                  d["sign"]) for d in ds)
+    want = sorted((tuple(sorted(x["open"])), tuple(x["first_block_labels"]), x["sign"])
+                  for x in g["diagrams"])
+    assert got == want
+    info = p.info()
+    assert info["sum_k"] == g["effective_iterations"]
+    assert info["n_diagrams"] == 6
+    # naive count (Nc! Na)^B Nu! Nd! Ns! 2^(NLambda+NSigma0-B) of Sec. 2
+    assert 576 * info["n_wick_perms"] // 3 // 2 == g["naive_iterations"]
+
+
+def test_r52_table_counts():
+    """Regression values of the R52 reading (derived by enumeration)."""
+    ch = channels.r52()
+    assert len(ch) == 52 and len(set(ch)) == 52
+    info = host_plan(ch).info()
+    assert info["n_diagrams"] == 640
+    assert info["sum_k"] == 41920
+    assert info["n_wick_perms"] == 3376
+    assert info["n_types"] == 9
+    # every channel's Wick permutation count agrees with the oracle's enumeration
+    total = sum(oracle.count_perms(c)[1] for c in ch)
+    assert total == info["n_wick_perms"]
+
+
+@pytest.mark.parametrize("chan", [("p", "p", "p", "p"), ("Lambda", "Lambda", "Sigma+", "Sigma-"),
+                                  ("Xi0", "Sigma0", "Xi-", "Sigma+")])
+def test_per_channel_wick_counts(chan):
+    p = host_plan([chan])
+    assert p.info()["n_wick_perms"] == oracle.count_perms(chan)[1]
+
+
+def _momentum_blocks(L, S, type_codes):
+    V = int(np.prod(L))
+    out = []
+    for code in type_codes:
+        f1, f2, f3 = code // 9, (code // 3) % 3, code % 3
+        N = oracle.normal_blocks(L, S, f1, f2, f3).reshape(V, 3456)
+        out.append(oracle.dft3(N, L, -1))
+    return out
+
+
+def _neg(L, q):
+    x, y, z = q % L[0], (q // L[0]) % L[1], q // (L[0] * L[1])
+    return ((-x) % L[0]) + L[0] * (((-y) % L[1]) + L[1] * ((-z) % L[2]))
+
+
+@pytest.mark.parametrize("chans,L,qs", [
+    ([channels.WORKED_EXAMPLE, ("p", "p", "p", "p")], (2, 2, 2), None),
+    (channels.r52(), (2, 3, 2), [0, 1, 7]),
+])
+def test_compiled_program_reproduces_oracle(chans, L, qs):
+    rng = np.random.default_rng(101)
+    S = ref.random_props(rng, L)
+    p = host_plan(chans, L=L, T=4)
+    T = emu.tables(p)
+    params = p.params()
+    Nt = _momentum_blocks(L, S, T["type_code"])
+    V = int(np.prod(L))
+    for q in (qs if qs is not None else range(V)):
+        mq = _neg(L, q)
+        got = emu.emulate_q(T, params, [n[q] for n in Nt], [n[mq] for n in Nt], len(chans))
+        qv = (q % L[0], (q // L[0]) % L[1], q // (L[0] * L[1]))
+        want = oracle.correlators_at_q(L, S, chans, qv)
+        err = np.linalg.norm(got - want, axis=1) / np.linalg.norm(want, axis=1)
+        assert err.max() < 1e-12, (q, err.max(), int(err.argmax()))
+
+
+# ---- ABI argument checking (host only) -------------------------------------
+
+def _create(L=(4, 4, 4), T=8, chans=(("p", "p", "p", "p"),), prec=0, device=-1, n_geom=1, **kw):
+    h = ctypes.c_void_p()
+    g = binding.make_geometry(L, T, **kw)
+    ch = binding.make_channels(list(chans))
+    st = binding.lib().nbs_plan_create(ctypes.byref(h), ctypes.byref(g), n_geom, ch, len(chans), prec, device)
+    return st, h
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(L=(7, 4, 4)), 1), (dict(L=(1, 4, 4)), 1), (dict(L=(256, 4, 4)), 1),
+    (dict(T=8, t_begin=6, t_count=4), 1), (dict(T=8, t0=8), 1), (dict(prec=5), 1),
+    (dict(chans=(("p", "p", "p", "n"),)), 1), (dict(chans=((0, 0, 0, 11),)), 1),
+    (dict(n_geom=2), 2), (dict(device=-7), 1),
+])
+def test_plan_create_rejects_bad_arguments(kw, status):
+    st, h = _create(**kw)
+    assert st == status
+    assert not h.value
+
+
+def test_compute_calls_on_host_only_plan_are_state_errors():
+    p = host_plan([("p", "p", "p", "p")])
+    L = binding.lib()
+    z = (ctypes.c_void_p * 1)(1)
+    assert L.nbs_build_blocks(p.handle, z, z, z, None) == 5
+    assert L.nbs_contract_channels(p.handle, None) == 5
+    assert L.nbs_relative_sum(p.handle, z, None) == 5
+    assert b"host-only" in L.nbs_last_error(p.handle)
+    assert L.nbs_plan_destroy(None) == 0
+    assert L.nbs_status_string(3) == b"out of device memory"

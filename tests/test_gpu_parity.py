@@ -1,0 +1,105 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Tolerances (norm-wise relative error per channel, max over slices):
+1e-12 for the plain FP64 form and 1e-5 for the precision form.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1604_07983_amd import binding, channels, runner
+from tests.parity_util import flat_props, rel_err_per_channel
+
+pytestmark = pytest.mark.gpu
+
+TOL = {binding.NBS_FP64: 1e-12, binding.NBS_FP32_MFMA: 1e-5}
+
+
+def announce(msg):
+    print("[case] " + msg, flush=True)
+
+
+def run_gpu(L, T, chans, props_np, prec, t0=0, t_begin=0, t_count=None):
+    import torch
+    dp = runner.device_props(props_np, prec)
+    r = runner.Runner(L, T, chans, prec=prec, t0=t0, t_begin=t_begin, t_count=t_count)
+    F = r.run(*dp)
+    torch.cuda.synchronize()
+    out = F.cpu().numpy()
+    r.close()
+    return out
+
+
+def oracle_F(L, props_np, chans, mode="fft"):
+    """[c, t, 16, Lz, Ly, Lx] from the oracle, slice by slice."""
+    nt = props_np[0].shape[0]
+    return np.stack([oracle.correlators(L, flat_props(props_np, i), chans, mode=mode) for i in range(nt)],
+                    axis=1)
+
+
+def test_config1_pp_fp64_direct_sum():
+    """4^3 x 8, pp only, u = d, decay 0.5, every slice against the O(V^2) direct sum."""
+    announce("config1 pp 4^3x8 fp64")
+    L, T = (4, 4, 4), 8
+    props = runner.host_props(L, T, range(T), decay={"u": 0.5, "d": 0.5, "s": 0.5}, same_ud=True)
+    chans = [("p", "p", "p", "p")]
+    Fg = run_gpu(L, T, chans, props, binding.NBS_FP64)
+    Fo = oracle_F(L, props, chans, mode="direct")
+    err = rel_err_per_channel(Fg, Fo)
+    assert err.max() <= 1e-12, err
+
+
+@pytest.mark.parametrize("prec", [binding.NBS_FP64, binding.NBS_FP32_MFMA])
+def test_all_r52_channels_small_lattice(prec):
+    """Every R52 channel on a non-cubic 4x2x3 lattice, three slices."""
+    announce("r52 4x2x3 prec=%d" % prec)
+    L, T = (4, 2, 3), 3
+    dt = np.complex128 if prec == binding.NBS_FP64 else np.complex64
+    props = runner.host_props(L, T, range(T), dtype=dt)
+    chans = channels.r52()
+    Fg = run_gpu(L, T, chans, props, prec)
+    Fo = oracle_F(L, props, chans)
+    err = rel_err_per_channel(Fg, Fo)
+    assert err.max() <= TOL[prec], (err.max(), int(err.argmax()))
+
+
+@pytest.mark.parametrize("prec", [binding.NBS_FP64, binding.NBS_FP32_MFMA])
+def test_window_and_source_slice(prec):
+    """A window t_begin = 3, t_count = 2 of T = 6 with the source at t0 = 2."""
+    announce("window 6x4x2 prec=%d" % prec)
+    L, T, t0, tb, tc = (6, 4, 2), 6, 2, 3, 2
+    dt = np.complex128 if prec == binding.NBS_FP64 else np.complex64
+    props = runner.host_props(L, T, range(tb, tb + tc), t0=t0, dtype=dt)
+    chans = [channels.WORKED_EXAMPLE, ("Xi0", "Xi-", "Xi0", "Xi-"), ("Lambda", "Lambda", "p", "Xi-")]
+    Fg = run_gpu(L, T, chans, props, prec, t0=t0, t_begin=tb, t_count=tc)
+    Fo = oracle_F(L, props, chans)
+    err = rel_err_per_channel(Fg, Fo)
+    assert err.max() <= TOL[prec], err
+
+
+def test_repeat_runs_are_bit_identical():
+    announce("determinism 4^3 r52 fp64")
+    L, T = (4, 4, 4), 2
+    props = runner.host_props(L, T, range(T))
+    chans = channels.r52()
+    a = run_gpu(L, T, chans, props, binding.NBS_FP64)
+    b = run_gpu(L, T, chans, props, binding.NBS_FP64)
+    assert np.array_equal(a.view(np.float64), b.view(np.float64))
+
+
+def test_state_errors_on_device_plan():
+    announce("state errors")
+    import torch
+    r = runner.Runner((2, 2, 2), 2, [("p", "p", "p", "p")])
+    with pytest.raises(binding.NbsError) as e:
+        r.contract()
+    assert e.value.status == 5
+    with pytest.raises(binding.NbsError) as e:
+        r.relative_sum()
+    assert e.value.status == 5
+    with pytest.raises(binding.NbsError) as e:
+        r.plan.build_blocks(0, 0, 0, r.stream())
+    assert e.value.status == 1
+    assert r.plan.workspace_bytes() > 0
+    r.close()
+    torch.cuda.synchronize()
