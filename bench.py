@@ -43,16 +43,15 @@ def parse():
 
 
 def program_work(plan):
-    """Algorithmic work per momentum site of the contraction program:
-    (EBB flops, MEB flops).  EBB: 4 flops per (real coefficient x complex
-    block entry) accumulation; MEB: 8 flops per complex multiply-add."""
+    """Algorithmic work per momentum site of the contraction: (EBB flops,
+    MEB flops).  EBB: every distinct effective-block entry is a sum of
+    (real coefficient x complex block entry) terms, 4 flops each; MEB: each
+    block product costs 16 complex multiply-adds per shared index, 8 flops
+    each (products shared by several channels counted once)."""
     import numpy as np
-    terms = len(plan.table("terms"))
-    K = plan.table("meb_kn").astype(np.int64)
-    rows1 = plan.table("meb_rows1")
-    macs = int((K * 16).sum())
-    del rows1
-    return 4.0 * terms, 8.0 * macs
+    info = plan.info()
+    desc = plan.table("prod_desc").reshape(-1, 20)
+    return 4.0 * info["n_terms"], 8.0 * 16 * float(desc[:, 16].astype(np.int64).sum())
 
 
 def cpu_baseline():

@@ -131,7 +131,7 @@ const char* nbs_last_error(const nbs_plan plan);
 
 typedef struct {
   int32_t n_channels;
-  int32_t n_types;        /* distinct flavour triplets whose blocks are built */
+  int32_t n_types;        /* sink-operator blocks built (Lambda, Sigma0 from X_u, X_d, X_s) */
   int32_t n_diagrams;     /* (channel, source term, quark split) with both blocks non-empty */
   int32_t n_blocks;       /* distinct effective blocks (per momentum side) */
   int32_t n_products;     /* distinct block products after sharing across channels */
@@ -160,16 +160,18 @@ nbs_status nbs_plan_diagrams(const nbs_plan plan, int32_t ch, nbs_diagram_t* out
                              int32_t cap, int32_t* n);
 
 /* Copy one table of the compiled structure-of-arrays program (the tables
- * the contraction kernel interprets; Sec. 3(ii)-(iii) ship such tables to
- * the device) into buf: int32 tables by name ("group_chunk", "terms",
- * "meb_e1", ...), "acc_coef" as double, "type_code" as int32.  *n gets the
+ * the kernels interpret; Sec. 3(ii)-(iii) ship such tables to the device)
+ * into buf.  int32 tables: "op_code", "op_nterm", "op_term_trip",
+ * "op_term_perm", "group_op1", "group_op2", "group_prod", "group_task",
+ * "group_ch", "group_channels", "ch_contrib", "contrib_prod", "prod_desc",
+ * "task_lanes"; double tables: "contrib_coef", "op_term_w".  *n gets the
  * element count; at most cap elements are written.  Unknown name:
- * NBS_ERR_INVALID. */
+ * NBS_ERR_INVALID.  Layouts are described in the compiler's header. */
 nbs_status nbs_plan_table(const nbs_plan plan, const char* name, void* buf, int64_t cap, int64_t* n);
 
-/* Parameters of the program: LDS budgets the tables were packed for.
- * out[0] = e_budget, out[1] = item_budget, out[2] = k_chunk,
- * out[3] = max channels per group. */
+/* Program parameters: out[0] = ints per product descriptor, out[1] = lanes
+ * per task, out[2] = most products in one group (LDS result buffer),
+ * out[3] = most channels in one group. */
 nbs_status nbs_plan_params(const nbs_plan plan, int32_t out[4]);
 
 #ifdef __cplusplus

@@ -171,7 +171,7 @@ class Plan:
         import numpy as np
         n = ctypes.c_int64()
         self._check(lib().nbs_plan_table(self._h, name.encode(), None, 0, ctypes.byref(n)), "nbs_plan_table")
-        arr = np.zeros(max(1, n.value), dtype=np.float64 if name == "acc_coef" else np.int32)
+        arr = np.zeros(max(1, n.value), dtype=np.float64 if name in ("contrib_coef", "op_term_w") else np.int32)
         self._check(lib().nbs_plan_table(self._h, name.encode(), arr.ctypes.data_as(ctypes.c_void_p), n.value,
                                          ctypes.byref(n)), "nbs_plan_table")
         return arr[:n.value]
@@ -179,7 +179,8 @@ class Plan:
     def params(self):
         out = (ctypes.c_int32 * 4)()
         self._check(lib().nbs_plan_params(self._h, out), "nbs_plan_params")
-        return {"e_budget": out[0], "item_budget": out[1], "k_chunk": out[2], "max_group_channels": out[3]}
+        return {"prod_ints": out[0], "lanes_per_task": out[1], "max_group_products": out[2],
+                "max_group_channels": out[3]}
 
     def close(self):
         if self._h:

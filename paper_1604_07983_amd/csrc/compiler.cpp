@@ -10,10 +10,6 @@
 namespace nbs {
 namespace {
 
-// eps_abc on {0,1,2} and C g5 = diag(i s2, i s2) (Dirac representation).
-int levi(int a, int b, int c) { return (a - b) * (b - c) * (c - a) / 2; }
-const int kCg5[4][4] = {{0, 1, 0, 0}, {-1, 0, 0, 0}, {0, 0, 0, 1}, {0, 0, -1, 0}};
-
 int popcount(unsigned v) { int n = 0; for (; v; v &= v - 1) ++n; return n; }
 
 int seq_sign(const int* s, int n) {
@@ -23,22 +19,9 @@ int seq_sign(const int* s, int n) {
   return (inv & 1) ? -1 : 1;
 }
 
-// One term of an effective block: sink slot i of `type` is contracted with
-// source quark m[i]; w carries the operator's integer weight and the sign of
-// m as an ordering of the block's source set.
-struct BlockTerm {
-  int type, m[3], w;
-  bool operator<(const BlockTerm& o) const {
-    return std::tie(type, m[0], m[1], m[2], w) < std::tie(o.type, o.m[0], o.m[1], o.m[2], o.w);
-  }
-  bool operator==(const BlockTerm& o) const {
-    return type == o.type && m[0] == o.m[0] && m[1] == o.m[1] && m[2] == o.m[2] && w == o.w;
-  }
-};
-
 // Shape of a block determined by its source set S (bit k = source quark k).
 struct Shape {
-  int kA, kB;      // quarks of source baryon A (0,1,2) / B (3,4,5) inside S
+  int kA, kB;        // quarks of source baryon A (0,1,2) / B (3,4,5) inside S
   int loneA, loneB;  // the quark of a split baryon that sits alone in one block (-1: no split)
   int KA, KB;
   bool lbl3, lbl4;   // alpha_3 / alpha_4 carried by this block
@@ -58,126 +41,50 @@ Shape shape_of(int mask) {
       for (int k = 0; k < 3; ++k) if ((mask >> (base + k)) & 1) lone = base + k;
     }
     const int Kp = lone < 0 ? 1 : (lone == base + 2 ? 3 : 12);
-    // the label (spin of quark base+2) sits where quark base+2 is
-    const bool lbl = (mask >> (base + 2)) & 1;
+    const bool lbl = (mask >> (base + 2)) & 1;  // spin label sits with quark base+2
     if (half == 0) { s.kA = in; s.loneA = lone; s.KA = Kp; s.lbl3 = lbl; }
     else { s.kB = in; s.loneB = lone; s.KB = Kp; s.lbl4 = lbl; }
   }
   return s;
 }
 
-// Assignments of source indices j' (3 * spin + colour) to the quarks of one
-// source baryon that lie in the block, for a given shared index x and label
-// spin al.  The baryon tensor eps_{c1 c2 c3} (C g5)_{s1 s2} delta_{s3 al} is
-// placed in the block that holds two or three of its quarks.
-struct Part { int j[3]; int coef; };
-
-std::vector<Part> source_parts(int in, int lone_local, int x, int al) {
-  std::vector<Part> out;
-  if (in == 0) { out.push_back({{-1, -1, -1}, 1}); return out; }
-  if (in == 3) {
-    for (int c0 = 0; c0 < 3; ++c0) for (int c1 = 0; c1 < 3; ++c1) for (int c2 = 0; c2 < 3; ++c2) {
-      const int e = levi(c0, c1, c2);
-      if (!e) continue;
-      for (int s0 = 0; s0 < 4; ++s0) for (int s1 = 0; s1 < 4; ++s1) {
-        if (!kCg5[s0][s1]) continue;
-        out.push_back({{3 * s0 + c0, 3 * s1 + c1, 3 * al + c2}, e * kCg5[s0][s1]});
-      }
-    }
-    return out;
-  }
-  if (in == 1) {  // the lone quark is here: its index is the shared one
-    Part p{{-1, -1, -1}, 1};
-    p.j[lone_local] = lone_local == 2 ? 3 * al + x : x;
-    out.push_back(p);
-    return out;
-  }
-  // in == 2: the lone quark is in the other block, the tensor is here
-  if (lone_local == 2) {
-    const int c2 = x;
-    for (int c0 = 0; c0 < 3; ++c0) for (int c1 = 0; c1 < 3; ++c1) {
-      const int e = levi(c0, c1, c2);
-      if (!e) continue;
-      for (int s0 = 0; s0 < 4; ++s0) for (int s1 = 0; s1 < 4; ++s1) {
-        if (!kCg5[s0][s1]) continue;
-        out.push_back({{3 * s0 + c0, 3 * s1 + c1, -1}, e * kCg5[s0][s1]});
-      }
-    }
-    return out;
-  }
-  const int a = lone_local, b = 1 - a;
-  const int sa = x / 3, ca = x % 3;
-  for (int cb = 0; cb < 3; ++cb) for (int c2 = 0; c2 < 3; ++c2) {
-    const int c0 = a == 0 ? ca : cb, c1 = a == 0 ? cb : ca;
-    const int e = levi(c0, c1, c2);
-    if (!e) continue;
-    for (int sb = 0; sb < 4; ++sb) {
-      const int g = a == 0 ? kCg5[sa][sb] : kCg5[sb][sa];
-      if (!g) continue;
-      Part p{{-1, -1, -1}, e * g};
-      p.j[b] = 3 * sb + cb;
-      p.j[2] = 3 * al + c2;
-      out.push_back(p);
-    }
-  }
-  return out;
+// Number of (colour, spin) terms the source tensor contributes to one entry
+// of a block holding `in` quarks of a source baryon whose lone quark is lone_local.
+int part_terms(int in, int lone_local) {
+  if (in == 3) return 24;
+  if (in == 2) return lone_local == 2 ? 8 : 2;
+  return 1;
 }
 
-struct Term { int type, idx, coef; };
+// A map of operator-block slots to source quarks with its sign.
+struct Map {
+  int m[3], sign;
+  bool operator<(const Map& o) const { return std::tie(m[0], m[1], m[2], sign) < std::tie(o.m[0], o.m[1], o.m[2], o.sign); }
+  bool operator==(const Map& o) const { return m[0] == o.m[0] && m[1] == o.m[1] && m[2] == o.m[2] && sign == o.sign; }
+  int packed() const { return m[0] | (m[1] << 3) | (m[2] << 6) | ((sign < 0) << 9); }
+};
 
-// Entries of an effective block: entries[r * K + k] = list of (type, idx, coef).
-std::vector<std::vector<Term>> block_entries(int mask, const std::vector<BlockTerm>& bts) {
-  const Shape sh = shape_of(mask);
-  const int K = sh.K(), rows = sh.rows();
-  const int n3 = sh.lbl3 ? 2 : 1, n4 = sh.lbl4 ? 2 : 1;
-  std::vector<std::vector<Term>> ent(rows * K);
-  for (int al = 0; al < 2; ++al)
-  for (int a3 = 0; a3 < n3; ++a3)
-  for (int a4 = 0; a4 < n4; ++a4) {
-    const int r = (al * n3 + a3) * n4 + a4;
-    for (int xa = 0; xa < sh.KA; ++xa)
-    for (int xb = 0; xb < sh.KB; ++xb) {
-      const auto pa = source_parts(sh.kA, sh.loneA < 0 ? -1 : sh.loneA, xa, a3);
-      const auto pb = source_parts(sh.kB, sh.loneB < 0 ? -1 : sh.loneB - 3, xb, a4);
-      std::map<std::pair<int, int>, int> acc;
-      for (const auto& A : pa)
-        for (const auto& B : pb) {
-          int j[6] = {A.j[0], A.j[1], A.j[2], B.j[0], B.j[1], B.j[2]};
-          for (const auto& bt : bts) {
-            const int idx = al * 1728 + j[bt.m[0]] * 144 + j[bt.m[1]] * 12 + j[bt.m[2]];
-            acc[{bt.type, idx}] += bt.w * A.coef * B.coef;
-          }
-        }
-      auto& e = ent[r * K + xa * sh.KB + xb];
-      for (const auto& kv : acc)
-        if (kv.second) e.push_back({kv.first.first, kv.first.second, kv.second});
-    }
-  }
-  return ent;
-}
-
-// Effective block of one sink operator for source set `mask` given the
-// flavours of the six source quarks.
-std::vector<BlockTerm> effective_block(const OpExpansion& op, int mask, const int srcfl[6]) {
+// Effective block of a sink operator for source set `mask`: every
+// flavour-respecting map of its slots onto the set, signed by the parity of
+// the map as an ordering of the set (the paper's effective block, Eq. (9)).
+std::vector<Map> effective_block(int op, int mask, const int srcfl[6]) {
+  int fl[3];
+  operator_slots(op, fl);
   int S[3], n = 0;
   for (int k = 0; k < 6; ++k) if ((mask >> k) & 1) S[n++] = k;
-  std::vector<BlockTerm> out;
+  std::vector<Map> out;
   int perm[3] = {0, 1, 2};
-  for (size_t t = 0; t < op.trip.size(); ++t) {
-    std::sort(perm, perm + 3);
-    do {
-      BlockTerm bt{};
-      bt.type = op.trip[t].code();
-      bool ok = true;
-      for (int i = 0; i < 3; ++i) {
-        bt.m[i] = S[perm[i]];
-        if (op.trip[t].f[i] != srcfl[bt.m[i]]) ok = false;
-      }
-      if (!ok) continue;
-      bt.w = op.wnum[t] * seq_sign(perm, 3);
-      out.push_back(bt);
-    } while (std::next_permutation(perm, perm + 3));
-  }
+  do {
+    Map mp{};
+    bool ok = true;
+    for (int i = 0; i < 3; ++i) {
+      mp.m[i] = S[perm[i]];
+      if (fl[i] != srcfl[mp.m[i]]) ok = false;
+    }
+    if (!ok) continue;
+    mp.sign = seq_sign(perm, 3);
+    out.push_back(mp);
+  } while (std::next_permutation(perm, perm + 3));
   std::sort(out.begin(), out.end());
   return out;
 }
@@ -210,6 +117,30 @@ int flavour_count(const Triplet& t, int f) { return (t.f[0] == f) + (t.f[1] == f
 
 }  // namespace
 
+// Kernel dispatch class of a block product (see compiler.hpp).
+int product_class(int K, int rows1, int lone1, int lone2, int nm1, int nm2) {
+  if (K == 1) return kClassFull;
+  if (nm1 < 1 || nm1 > 2 || nm2 < 1 || nm2 > 2) return kClassSplitAny;
+  const int np1 = lone1 == 2 ? 8 : 2, np2 = lone2 == 2 ? 8 : 2;
+  int base = -1;
+  if (rows1 == 4 && np1 == 2 && np2 == 2) base = 1;
+  if (rows1 == 8 && np1 == 2 && np2 == 8) base = 5;
+  if (rows1 == 2 && np1 == 8 && np2 == 2) base = 9;
+  if (rows1 == 4 && np1 == 8 && np2 == 8) base = 13;
+  if (base < 0) return kClassSplitAny;
+  return base + (nm1 - 1) * 2 + (nm2 - 1);
+}
+
+namespace {
+
+struct Block {
+  int mask;
+  std::vector<Map> maps;
+  bool operator<(const Block& o) const { return std::tie(mask, maps) < std::tie(o.mask, o.maps); }
+};
+
+}  // namespace
+
 OpExpansion expand_operator(int op) {
   OpExpansion e;
   auto T = [](int a, int b, int c) { Triplet t; t.f[0] = a; t.f[1] = b; t.f[2] = c; return t; };
@@ -239,303 +170,306 @@ OpExpansion expand_operator(int op) {
   return e;
 }
 
+void operator_slots(int op, int fl[3]) {
+  if (op == 2 || op == 4) { fl[0] = FU; fl[1] = FD; fl[2] = FS; return; }
+  const OpExpansion e = expand_operator(op);
+  for (int i = 0; i < 3; ++i) fl[i] = e.trip.empty() ? -1 : e.trip[0].f[i];
+}
+
 std::string compile_channels(const std::vector<ChannelSpec>& chans, const CompileOptions& opt,
                              Compiled* out) {
   Compiled C;
   C.channels = chans;
   const int n_ch = (int)chans.size();
   if (n_ch <= 0) return "no channels";
+  Program& P = C.prog;
 
-  // ---- 1. diagrams, effective blocks and products -------------------------
-  std::map<std::pair<int, std::vector<BlockTerm>>, int> block_id[2];  // per side
-  std::vector<int> block_mask[2];
-  std::vector<std::vector<BlockTerm>> block_terms[2];
-  std::map<std::pair<int, int>, int> product_id;
-  std::vector<std::pair<int, int>> products;
-  // product -> channel -> coefficient
-  std::vector<std::map<int, double>> product_coef;
-
-  for (int c = 0; c < n_ch; ++c) {
-    OpExpansion op[4];
+  // ---- 1. operator blocks the sink side needs ------------------------------
+  std::map<int, int> op_slot;
+  for (int c = 0; c < n_ch; ++c)
     for (int k = 0; k < 4; ++k) {
       const int code = k < 2 ? chans[c].sink[k] : chans[c].src[k - 2];
       if (code < 0 || code > 10) return "channel " + std::to_string(c) + ": bad operator code";
-      op[k] = expand_operator(code);
     }
-    // flavour conservation
-    int nf[2][3] = {{0, 0, 0}, {0, 0, 0}};
-    for (int side = 0; side < 2; ++side)
-      for (int k = 0; k < 2; ++k)
-        for (int f = 0; f < 3; ++f) nf[side][f] += flavour_count(op[2 * side + k].trip[0], f);
-    for (int f = 0; f < 3; ++f)
-      if (nf[0][f] != nf[1][f]) return "channel " + std::to_string(c) + ": flavour not conserved";
-    for (int f = 0; f < 3; ++f) C.channel_flavour.push_back(nf[0][f]);
-
-    int src_term = 0;
-    for (size_t t3 = 0; t3 < op[2].trip.size(); ++t3)
-      for (size_t t4 = 0; t4 < op[3].trip.size(); ++t4, ++src_term) {
-        int srcfl[6];
-        for (int i = 0; i < 3; ++i) {
-          srcfl[i] = op[2].trip[t3].f[i];
-          srcfl[3 + i] = op[3].trip[t4].f[i];
-        }
-        const double wsrc = op[0].norm * op[1].norm * op[2].norm * op[3].norm *
-                            op[2].wnum[t3] * op[3].wnum[t4];
-        for (int mask = 0; mask < 64; ++mask) {
-          if (popcount(mask) != 3) continue;
-          const int mask2 = 0x3f & ~mask;
-          auto e1 = effective_block(op[0], mask, srcfl);
-          auto e2 = effective_block(op[1], mask2, srcfl);
-          if (e1.empty() || e2.empty()) continue;
-          // count of Wick permutations this diagram covers (per sink term pair)
-          int cross = 0;
-          for (int x = 0; x < 6; ++x)
-            for (int y = 0; y < 6; ++y)
-              if (((mask >> x) & 1) && ((mask2 >> y) & 1) && x > y) ++cross;
-          const double coef = wsrc * ((cross & 1) ? -1.0 : 1.0);
-          int ids[2];
-          const std::vector<BlockTerm>* es[2] = {&e1, &e2};
-          const int ms[2] = {mask, mask2};
-          for (int side = 0; side < 2; ++side) {
-            auto key = std::make_pair(ms[side], *es[side]);
-            auto it = block_id[side].find(key);
-            if (it == block_id[side].end()) {
-              const int id = (int)block_terms[side].size();
-              block_id[side][key] = id;
-              block_terms[side].push_back(*es[side]);
-              block_mask[side].push_back(ms[side]);
-              ids[side] = id;
-            } else {
-              ids[side] = it->second;
-            }
-          }
-          auto pk = std::make_pair(ids[0], ids[1]);
-          int pid;
-          auto pit = product_id.find(pk);
-          if (pit == product_id.end()) {
-            pid = (int)products.size();
-            product_id[pk] = pid;
-            products.push_back(pk);
-            product_coef.emplace_back();
-          } else {
-            pid = pit->second;
-          }
-          product_coef[pid][c] += coef;
-
-          const Shape sh = shape_of(mask);
-          DiagramInfo d{};
-          d.channel = c;
-          d.src_term = src_term;
-          d.set1_mask = mask;
-          d.paper_sign = paper_sign(op[0], op[1], mask, srcfl);
-          d.k = sh.K();
-          d.labels1 = (sh.lbl3 ? 1 : 0) | (sh.lbl4 ? 2 : 0);
-          int open = 0;
-          if (sh.loneA >= 0) open |= (1 << (2 * sh.loneA)) | (sh.loneA != 2 ? 1 << (2 * sh.loneA + 1) : 0);
-          if (sh.loneB >= 0) open |= (1 << (2 * sh.loneB)) | (sh.loneB != 5 ? 1 << (2 * sh.loneB + 1) : 0);
-          d.open_mask = open;
-          d.coef = coef;
-          d.product = pid;
-          C.diagrams.push_back(d);
-          C.sum_k += sh.K();
-          // Wick permutations covered: maps of block 1 x maps of block 2,
-          // per sink flavour-term pair
-          std::map<std::pair<int, int>, int> cnt;
-          int n1[27] = {0}, n2[27] = {0};
-          for (auto& bt : e1) n1[bt.type]++;
-          for (auto& bt : e2) n2[bt.type]++;
-          for (int a = 0; a < 27; ++a)
-            for (int b = 0; b < 27; ++b) C.n_wick += (int64_t)n1[a] * n2[b];
-        }
+  for (int c = 0; c < n_ch; ++c)
+    for (int k = 0; k < 2; ++k)
+      if (!op_slot.count(chans[c].sink[k])) op_slot[chans[c].sink[k]] = 0;
+  for (auto& kv : op_slot) {
+    kv.second = (int)P.op_code.size();
+    P.op_code.push_back(kv.first);
+    const OpExpansion e = expand_operator(kv.first);
+    int sl[3];
+    operator_slots(kv.first, sl);
+    P.op_nterm.push_back((int)e.trip.size());
+    for (int k = 0; k < 3; ++k) {
+      if (k >= (int)e.trip.size()) {
+        P.op_term_trip.push_back(0); P.op_term_perm.push_back(0); P.op_term_w.push_back(0.0);
+        continue;
       }
-  }
-
-  // ---- 2. entries of every block -------------------------------------------
-  std::vector<std::vector<std::vector<Term>>> entries[2];
-  std::set<int> used_types;
-  for (int side = 0; side < 2; ++side)
-    for (size_t b = 0; b < block_terms[side].size(); ++b) {
-      entries[side].push_back(block_entries(block_mask[side][b], block_terms[side][b]));
-      for (auto& e : entries[side].back()) {
-        ++C.n_entries;
-        C.n_terms += (int64_t)e.size();
-        for (auto& t : e) used_types.insert(t.type);
+      // pi(i): the operator slot holding the flavour of triplet slot i
+      int pi[3], used = 0;
+      for (int i = 0; i < 3; ++i) {
+        pi[i] = -1;
+        for (int s = 0; s < 3; ++s)
+          if (!((used >> s) & 1) && sl[s] == e.trip[k].f[i]) { pi[i] = s; used |= 1 << s; break; }
+        if (pi[i] < 0) return "operator slot mismatch";
       }
-    }
-  C.n_blocks = (int)(block_terms[0].size() + block_terms[1].size());
-  C.n_products = (int)products.size();
-
-  Program& P = C.prog;
-  std::map<int, int> type_slot;
-  for (int t : used_types) {
-    type_slot[t] = (int)P.type_code.size();
-    P.type_code.push_back(t);
-  }
-  P.n_types = (int)P.type_code.size();
-
-  // ---- 3. groups of channels ------------------------------------------------
-  std::vector<std::vector<int>> groups;
-  if (opt.group_mode == 1) {
-    for (int c = 0; c < n_ch; ++c) groups.push_back({c});
-  } else {
-    std::map<std::pair<int, int>, std::vector<int>> by_sink;
-    std::vector<std::pair<int, int>> order;
-    for (int c = 0; c < n_ch; ++c) {
-      auto k = std::make_pair(chans[c].sink[0], chans[c].sink[1]);
-      if (!by_sink.count(k)) order.push_back(k);
-      by_sink[k].push_back(c);
-    }
-    for (auto& k : order) {
-      auto& v = by_sink[k];
-      for (size_t i = 0; i < v.size(); i += opt.max_group_channels)
-        groups.emplace_back(v.begin() + i, v.begin() + std::min(v.size(), i + opt.max_group_channels));
+      P.op_term_trip.push_back(e.trip[k].code());
+      P.op_term_perm.push_back(pi[0] | (pi[1] << 2) | (pi[2] << 4));
+      P.op_term_w.push_back(e.norm * e.wnum[k] * seq_sign(pi, 3));
     }
   }
+  P.n_ops = (int)P.op_code.size();
 
-  // products used by each channel
-  std::vector<std::vector<int>> chan_products(n_ch);
-  for (size_t p = 0; p < products.size(); ++p)
-    for (auto& kv : product_coef[p]) chan_products[kv.first].push_back((int)p);
+  // ---- 2. diagrams and products per sink-operator group --------------------
+  std::map<std::pair<int, int>, std::vector<int>> by_sink;
+  std::vector<std::pair<int, int>> order;
+  for (int c = 0; c < n_ch; ++c) {
+    auto k = std::make_pair(chans[c].sink[0], chans[c].sink[1]);
+    if (!by_sink.count(k)) order.push_back(k);
+    by_sink[k].push_back(c);
+  }
+  C.channel_flavour.assign(3 * n_ch, 0);
 
-  P.group_chunk.push_back(0);
+  P.group_prod.push_back(0);
+  P.group_task.push_back(0);
   P.group_ch.push_back(0);
-  P.chunk_step.push_back(0);
-  P.chunk_meb.push_back(0);
-  P.chunk_acc.push_back(0);
-  P.step_ebb.push_back(0);
-  P.ebb_term.push_back(0);
-  P.acc_src_range.push_back(0);
+  P.ch_contrib.push_back(0);
+  std::set<Block> all_blocks[2];
 
-  for (auto& g : groups) {
-    std::map<int, int> local;  // channel -> local index
-    for (int c : g) { local[c] = (int)P.group_channels.size() - P.group_ch.back(); P.group_channels.push_back(c); }
-    P.max_group_channels = std::max(P.max_group_channels, (int)g.size());
-    // products of the group, ordered by their blocks so neighbours share types
-    std::set<int> pset;
-    for (int c : g) for (int p : chan_products[c]) pset.insert(p);
-    std::vector<int> plist(pset.begin(), pset.end());
-    auto type_sig = [&](int p) {
-      std::set<int> t0, t1;
-      for (auto& bt : block_terms[0][products[p].first]) t0.insert(bt.type);
-      for (auto& bt : block_terms[1][products[p].second]) t1.insert(bt.type);
-      return std::make_tuple(std::vector<int>(t0.begin(), t0.end()), std::vector<int>(t1.begin(), t1.end()),
-                             products[p].first, products[p].second);
-    };
-    std::stable_sort(plist.begin(), plist.end(), [&](int a, int b) { return type_sig(a) < type_sig(b); });
-
-    int slot_side = -1, slot_type = -1;
-    size_t pi = 0;
-    while (pi < plist.size()) {
-      // greedy chunk
-      std::map<std::pair<int, int>, int> eoff;  // (side, block) -> offset
-      int esize = 0, items = 0;
-      std::vector<int> cp;
-      while (pi < plist.size()) {
-        const int p = plist[pi];
-        const auto& pr = products[p];
-        const Shape s1 = shape_of(block_mask[0][pr.first]);
-        const int K = s1.K();
-        int add_e = 0;
-        if (!eoff.count({0, pr.first})) add_e += s1.rows() * K;
-        if (!eoff.count({1, pr.second})) add_e += (16 / s1.rows()) * K;
-        const int add_i = (K + opt.k_chunk - 1) / opt.k_chunk;
-        if (!cp.empty() && (esize + add_e > opt.e_budget || items + add_i > opt.item_budget)) break;
-        if (!eoff.count({0, pr.first})) { eoff[{0, pr.first}] = esize; esize += s1.rows() * K; }
-        if (!eoff.count({1, pr.second})) { eoff[{1, pr.second}] = esize; esize += (16 / s1.rows()) * K; }
-        items += add_i;
-        cp.push_back(p);
-        ++pi;
-      }
-      if (esize > opt.e_budget || items > opt.item_budget) return "chunk exceeds LDS budget";
-      P.chunk_esize.push_back(esize);
-      P.max_chunk_esize = std::max(P.max_chunk_esize, esize);
-      P.max_chunk_items = std::max(P.max_chunk_items, items);
-
-      // steps: every (side, type) the chunk's entries read
-      std::map<std::pair<int, int>, std::vector<std::pair<int, std::vector<Term>>>> by_step;
-      for (auto& kv : eoff) {
-        const int side = kv.first.first, b = kv.first.second, off = kv.second;
-        const auto& ents = entries[side][b];
-        for (size_t e = 0; e < ents.size(); ++e) {
-          std::map<int, std::vector<Term>> per_type;
-          for (auto& t : ents[e]) per_type[t.type].push_back(t);
-          for (auto& pt : per_type)
-            by_step[{side, pt.first}].push_back({off + (int)e, pt.second});
-        }
-      }
-      std::vector<std::pair<int, int>> steps;
-      for (auto& kv : by_step) steps.push_back(kv.first);
-      // start with what the LDS slot already holds
-      std::stable_partition(steps.begin(), steps.end(), [&](const std::pair<int, int>& s) {
-        return s.first == slot_side && s.second == slot_type;
+  for (auto& sk : order) {
+    const std::vector<int>& chs = by_sink[sk];
+    // a group is flushed when its product list would exceed the LDS result buffer
+    std::map<std::pair<Block, Block>, int> prod_id;
+    std::vector<std::pair<Block, Block>> prods;
+    std::vector<std::map<int, double>> pcoef;  // product -> channel -> coef
+    auto flush = [&](const std::vector<int>& gch) {
+      // products, sorted into team-size classes and packed into 64-lane tasks
+      const int gbase_prod = (int)(P.prod_desc.size() / kProdInts);
+      std::vector<int> order_p(prods.size());
+      for (size_t i = 0; i < prods.size(); ++i) order_p[i] = (int)i;
+      // Lane layout of a product (the contraction kernel's rules): K = 1 -> one
+      // lane; otherwise one lane per value y of the shared index on the side
+      // where block 1 holds a quark pair (Ky = 3 or 12 lanes in a team of 4 or
+      // 16), each walking the Kz values of the other side.
+      auto ky_of = [&](int p) {
+        const Shape s1 = shape_of(prods[p].first.mask);
+        return s1.K() == 1 ? 1 : (s1.kA == 2 ? s1.KA : s1.KB);
+      };
+      auto team = [&](int p) {
+        const int ky = ky_of(p);
+        return ky == 1 ? 1 : (ky <= 4 ? 4 : 16);
+      };
+      auto kz_of = [&](int p) { return shape_of(prods[p].first.mask).K() / ky_of(p); };
+      auto cls_of = [&](int p) {
+        const Shape s1 = shape_of(prods[p].first.mask), s2 = shape_of(prods[p].second.mask);
+        return product_class(s1.K(), s1.rows(), s1.kA == 2 ? s1.loneA : s1.loneB, s1.kA == 2 ? s2.loneB : s2.loneA,
+                             (int)prods[p].first.maps.size(), (int)prods[p].second.maps.size());
+      };
+      std::stable_sort(order_p.begin(), order_p.end(), [&](int a, int b) {
+        const int ta = team(a), tb = team(b);
+        if (ta != tb) return ta > tb;
+        if (cls_of(a) != cls_of(b)) return cls_of(a) < cls_of(b);
+        if (kz_of(a) != kz_of(b)) return kz_of(a) > kz_of(b);
+        return std::make_tuple(prods[a].first.mask, prods[a].first.maps.size(), prods[a].second.maps.size()) <
+               std::make_tuple(prods[b].first.mask, prods[b].first.maps.size(), prods[b].second.maps.size());
       });
-      for (auto& st : steps) {
-        const int load = !(st.first == slot_side && st.second == slot_type);
-        slot_side = st.first;
-        slot_type = st.second;
-        P.step_side.push_back(st.first);
-        P.step_type.push_back(type_slot[st.second]);
-        P.step_load.push_back(load);
-        for (auto& item : by_step[st]) {
-          P.ebb_e.push_back(item.first);
-          for (auto& t : item.second) {
-            if (t.coef < -32768 || t.coef > 32767) return "term coefficient overflow";
-            P.terms.push_back((t.idx & 0xffff) | (int)((unsigned)(t.coef & 0xffff) << 16));
-          }
-          P.ebb_term.push_back((int)P.terms.size());
-        }
-        P.step_ebb.push_back((int)P.ebb_e.size());
+      std::vector<int> local(prods.size());
+      for (size_t i = 0; i < order_p.size(); ++i) local[order_p[i]] = (int)i;
+      for (int p : order_p) {
+        const Shape s1 = shape_of(prods[p].first.mask);
+        int d[kProdInts] = {0};
+        d[0] = prods[p].first.mask;
+        d[1] = (int)prods[p].first.maps.size();
+        for (size_t i = 0; i < prods[p].first.maps.size(); ++i) d[2 + i] = prods[p].first.maps[i].packed();
+        d[8] = prods[p].second.mask;
+        d[9] = (int)prods[p].second.maps.size();
+        for (size_t i = 0; i < prods[p].second.maps.size(); ++i) d[10 + i] = prods[p].second.maps[i].packed();
+        d[16] = s1.K();
+        d[17] = s1.KB;
+        d[18] = s1.rows();
+        d[19] = (s1.lbl3 ? 1 : 0) | (s1.lbl4 ? 2 : 0);
+        P.prod_desc.insert(P.prod_desc.end(), d, d + kProdInts);
+        C.product_k += s1.K();
       }
-      P.chunk_step.push_back((int)P.step_side.size());
+      // lanes: every task holds teams of one size and one product class only,
+      // so the team reduction and the kernel's class dispatch are uniform
+      // across its wavefront; idle lanes carry the team size and class too
+      std::vector<std::vector<int>> tasks;
+      std::vector<double> tcost;
+      int cur_key = -1;
+      for (int p : order_p) {
+        const int tl = team(p), ky = ky_of(p), kz = kz_of(p), cl = cls_of(p);
+        int lg = 0;
+        while ((1 << lg) < tl) ++lg;
+        const int key = lg * 64 + cl;
+        const int idle = 0xfff | (lg << 16) | (cl << 23);
+        if (key != cur_key || tasks.back().size() == (size_t)kLanesPerTask) {
+          if (!tasks.empty())
+            while (tasks.back().size() < (size_t)kLanesPerTask) tasks.back().push_back(tasks.back().back() | 0xfff);
+          tasks.emplace_back();
+          tcost.push_back(0.0);
+          cur_key = key;
+        }
+        for (int u = 0; u < tl; ++u)
+          tasks.back().push_back(u < ky ? (local[p] | (u << 12) | (lg << 16) | (kz << 19) | (cl << 23)) : idle);
+        const Shape s1 = shape_of(prods[p].first.mask);
+        const double it = (double)kz * (s1.rows() * 2.0 * prods[p].first.maps.size() +
+                                        (16 / s1.rows()) * 2.0 * prods[p].second.maps.size() + 32.0);
+        tcost.back() = std::max(tcost.back(), it);
+      }
+      if (!tasks.empty())
+        while (tasks.back().size() < (size_t)kLanesPerTask) tasks.back().push_back(tasks.back().back() | 0xfff);
+      // longest-processing-time assignment of tasks to the workgroup's
+      // wavefronts, emitted round-robin (wave w takes tasks w, w + W, ...)
+      std::vector<int> by_cost(tasks.size());
+      for (size_t i = 0; i < tasks.size(); ++i) by_cost[i] = (int)i;
+      std::stable_sort(by_cost.begin(), by_cost.end(), [&](int a, int b) { return tcost[a] > tcost[b]; });
+      std::vector<std::vector<int>> bins(kWavesPerGroup);
+      std::vector<double> load(kWavesPerGroup, 0.0);
+      for (int ti : by_cost) {
+        const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        bins[w].push_back(ti);
+        load[w] += tcost[ti];
+      }
+      size_t rounds = 0;
+      for (auto& b : bins) rounds = std::max(rounds, b.size());
+      std::vector<int> lanes;
+      for (size_t r = 0; r < rounds; ++r)
+        for (int w = 0; w < kWavesPerGroup; ++w) {
+          if (r < bins[w].size()) {
+            const auto& tk = tasks[bins[w][r]];
+            lanes.insert(lanes.end(), tk.begin(), tk.end());
+          } else {
+            for (int l = 0; l < kLanesPerTask; ++l) lanes.push_back(0xfff);
+          }
+        }
+      P.task_lanes.insert(P.task_lanes.end(), lanes.begin(), lanes.end());
+      // channel contributions
+      for (int c : gch) {
+        P.group_channels.push_back(c);
+        for (size_t p = 0; p < prods.size(); ++p) {
+          auto it = pcoef[p].find(c);
+          if (it == pcoef[p].end() || it->second == 0.0) continue;
+          const Shape s1 = shape_of(prods[p].first.mask);
+          const int lbl = (s1.lbl3 ? 1 : 0) | (s1.lbl4 ? 2 : 0);
+          P.contrib_prod.push_back(local[p] | (s1.rows() << 16) | (lbl << 20));
+          P.contrib_coef.push_back(it->second);
+        }
+        P.ch_contrib.push_back((int)P.contrib_prod.size());
+      }
+      P.group_op1.push_back(op_slot[sk.first]);
+      P.group_op2.push_back(op_slot[sk.second]);
+      P.group_prod.push_back((int)(P.prod_desc.size() / kProdInts));
+      P.group_task.push_back((int)(P.task_lanes.size() / kLanesPerTask));
+      P.group_ch.push_back((int)P.group_channels.size());
+      P.max_group_products = std::max(P.max_group_products, (int)prods.size());
+      P.max_group_contrib = std::max(P.max_group_contrib, P.ch_contrib.back() - P.ch_contrib[P.group_ch[P.group_ch.size() - 2]]);
+      P.max_group_channels = std::max(P.max_group_channels, (int)gch.size());
+      (void)gbase_prod;
+      prod_id.clear();
+      prods.clear();
+      pcoef.clear();
+    };
 
-      // MEB items and accumulation
-      std::map<int, std::vector<std::pair<int, double>>> acc;  // target -> (src, coef)
-      int item = 0;
-      for (int p : cp) {
-        const auto& pr = products[p];
-        const Shape s1 = shape_of(block_mask[0][pr.first]);
-        const int K = s1.K(), rows1 = s1.rows(), rows2 = 16 / rows1;
-        const int n13 = s1.lbl3 ? 2 : 1, n14 = s1.lbl4 ? 2 : 1;
-        const int n23 = s1.lbl3 ? 1 : 2, n24 = s1.lbl4 ? 1 : 2;
-        const int first_item = item;
-        for (int k0 = 0; k0 < K; k0 += opt.k_chunk) {
-          P.meb_e1.push_back(eoff[{0, pr.first}]);
-          P.meb_e2.push_back(eoff[{1, pr.second}]);
-          P.meb_K.push_back(K);
-          P.meb_k0.push_back(k0);
-          P.meb_kn.push_back(std::min(opt.k_chunk, K - k0));
-          P.meb_rows1.push_back(rows1);
-          ++item;
-        }
-        // output o = r1 * rows2 + r2 -> spin s
-        for (int o = 0; o < 16; ++o) {
-          const int r1 = o / rows2, r2 = o % rows2;
-          // r1 = (a1 * n13 + a3') * n14 + a4' ; r2 = (a2 * n23 + a3'') * n24 + a4''
-          const int a1 = r1 / (n13 * n14), a2 = r2 / (n23 * n24);
-          const int a3 = s1.lbl3 ? (r1 / n14) % n13 : (r2 / n24) % n23;
-          const int a4 = s1.lbl4 ? r1 % n14 : r2 % n24;
-          const int s = 8 * a1 + 4 * a2 + 2 * a3 + a4;
-          for (auto& kv : product_coef[p]) {
-            if (!local.count(kv.first)) continue;
-            const int target = local[kv.first] * 16 + s;
-            for (int it = first_item; it < item; ++it) acc[target].push_back({it * 16 + o, kv.second});
+    std::vector<int> gch;
+    for (int c : chs) {
+      OpExpansion op[4];
+      for (int k = 0; k < 4; ++k) op[k] = expand_operator(k < 2 ? chans[c].sink[k] : chans[c].src[k - 2]);
+      int nf[2][3] = {{0, 0, 0}, {0, 0, 0}};
+      for (int side = 0; side < 2; ++side)
+        for (int k = 0; k < 2; ++k)
+          for (int f = 0; f < 3; ++f) nf[side][f] += flavour_count(op[2 * side + k].trip[0], f);
+      for (int f = 0; f < 3; ++f)
+        if (nf[0][f] != nf[1][f]) return "channel " + std::to_string(c) + ": flavour not conserved";
+      for (int f = 0; f < 3; ++f) C.channel_flavour[3 * c + f] = nf[0][f];
+
+      // products this channel needs
+      std::vector<std::tuple<Block, Block, double>> mine;
+      int src_term = 0;
+      for (size_t t3 = 0; t3 < op[2].trip.size(); ++t3)
+        for (size_t t4 = 0; t4 < op[3].trip.size(); ++t4, ++src_term) {
+          int srcfl[6];
+          for (int i = 0; i < 3; ++i) {
+            srcfl[i] = op[2].trip[t3].f[i];
+            srcfl[3 + i] = op[3].trip[t4].f[i];
+          }
+          const double wsrc = op[2].norm * op[3].norm * op[2].wnum[t3] * op[3].wnum[t4];
+          for (int mask = 0; mask < 64; ++mask) {
+            if (popcount(mask) != 3) continue;
+            const int mask2 = 0x3f & ~mask;
+            Block b1{mask, effective_block(chans[c].sink[0], mask, srcfl)};
+            Block b2{mask2, effective_block(chans[c].sink[1], mask2, srcfl)};
+            if (b1.maps.empty() || b2.maps.empty()) continue;
+            int cross = 0;
+            for (int x = 0; x < 6; ++x)
+              for (int y = 0; y < 6; ++y)
+                if (((mask >> x) & 1) && ((mask2 >> y) & 1) && x > y) ++cross;
+            const double coef = wsrc * ((cross & 1) ? -1.0 : 1.0);
+            mine.emplace_back(b1, b2, coef);
+            all_blocks[0].insert(b1);
+            all_blocks[1].insert(b2);
+            const Shape sh = shape_of(mask);
+            DiagramInfo d{};
+            d.channel = c;
+            d.src_term = src_term;
+            d.set1_mask = mask;
+            d.paper_sign = paper_sign(op[0], op[1], mask, srcfl);
+            d.k = sh.K();
+            d.labels1 = (sh.lbl3 ? 1 : 0) | (sh.lbl4 ? 2 : 0);
+            int open = 0;
+            if (sh.loneA >= 0) open |= (1 << (2 * sh.loneA)) | (sh.loneA != 2 ? 1 << (2 * sh.loneA + 1) : 0);
+            if (sh.loneB >= 0) open |= (1 << (2 * sh.loneB)) | (sh.loneB != 5 ? 1 << (2 * sh.loneB + 1) : 0);
+            d.open_mask = open;
+            d.coef = coef;
+            C.diagrams.push_back(d);
+            C.sum_k += sh.K();
+            // Wick permutations covered, counted on the flavour triplets of the operators
+            // every flavour triplet of an operator has the block's slot flavours, so
+            // each (triplet, triplet) pair covers maps1 x maps2 permutations
+            C.n_wick += (int64_t)op[0].trip.size() * op[1].trip.size() * b1.maps.size() * b2.maps.size();
           }
         }
+      // new products this channel would add to the current group
+      int new_p = 0;
+      for (auto& m : mine)
+        if (!prod_id.count({std::get<0>(m), std::get<1>(m)})) ++new_p;
+      if (!prods.empty() && (int)prods.size() + new_p > opt.max_group_products) {
+        flush(gch);
+        gch.clear();
       }
-      for (auto& kv : acc) {
-        P.acc_target.push_back(kv.first);
-        for (auto& sc : kv.second) {
-          P.acc_src.push_back(sc.first);
-          P.acc_coef.push_back(sc.second);
+      if ((int)mine.size() > opt.max_group_products && prods.empty() && new_p > opt.max_group_products)
+        return "channel " + std::to_string(c) + " needs more products than one group holds";
+      gch.push_back(c);
+      for (auto& m : mine) {
+        auto key = std::make_pair(std::get<0>(m), std::get<1>(m));
+        auto it = prod_id.find(key);
+        int pid;
+        if (it == prod_id.end()) {
+          pid = (int)prods.size();
+          prod_id[key] = pid;
+          prods.push_back(key);
+          pcoef.emplace_back();
+        } else {
+          pid = it->second;
         }
-        P.acc_src_range.push_back((int)P.acc_src.size());
+        pcoef[pid][c] += std::get<2>(m);
       }
-      P.chunk_meb.push_back((int)P.meb_e1.size());
-      P.chunk_acc.push_back((int)P.acc_target.size());
     }
-    P.group_chunk.push_back((int)P.chunk_esize.size());
-    P.group_ch.push_back((int)P.group_channels.size());
+    if (!gch.empty()) flush(gch);
   }
+
+  // ---- 3. statistics ---------------------------------------------------------
+  for (int side = 0; side < 2; ++side)
+    for (const Block& b : all_blocks[side]) {
+      const Shape s = shape_of(b.mask);
+      const int nA = part_terms(s.kA, s.loneA < 0 ? -1 : s.loneA);
+      const int nB = part_terms(s.kB, s.loneB < 0 ? -1 : s.loneB - 3);
+      C.n_entries += (int64_t)s.rows() * s.K();
+      C.n_terms += (int64_t)s.rows() * s.K() * (int64_t)b.maps.size() * nA * nB;
+    }
+  C.n_blocks = (int)(all_blocks[0].size() + all_blocks[1].size());
+  C.n_products = (int)(P.prod_desc.size() / kProdInts);
   *out = std::move(C);
   return "";
 }

@@ -8,6 +8,13 @@
 // of effective blocks E1^(d)(q), E2^(d)(-q) (Eq. (9)) that absorb every
 // same-flavour reordering of the quarks inside a block, and the channel into
 // sum_d sigma_d sum_{xi~_d} E1 E2 (Eq. (10)).
+//
+// Blocks are built per sink *operator* (Sec. 3(i): the Lambda and Sigma0
+// blocks are combinations of the X_u, X_d, X_s blocks), so every effective
+// block reads one operator block.  The device program is coarse: per block
+// product a fixed-size descriptor, per wavefront a 64-lane work list; the
+// entries of an effective block are generated from index arithmetic on the
+// device, not from per-term tables.
 #pragma once
 
 #include <cstdint>
@@ -33,6 +40,10 @@ struct OpExpansion {
 };
 OpExpansion expand_operator(int op);
 
+// Flavours of the three slots of an operator block: the triplet itself for
+// single-term operators, (u, d, s) for the X combinations Lambda and Sigma0.
+void operator_slots(int op, int fl[3]);
+
 struct ChannelSpec {
   int sink[2], src[2];
 };
@@ -41,58 +52,60 @@ struct ChannelSpec {
 struct DiagramInfo {
   int channel, src_term, set1_mask, paper_sign, k, labels1, open_mask;
   double coef;
-  int product;  // index into the product list
 };
 
-// Device program ("SoA tables") for one plan; every array is plain int32 or
-// double so it can be copied to the device as is.
+// Integers per block-product descriptor (layout in kernels and tests):
+//  [0] mask1 [1] nmaps1 [2..7] maps1  [8] mask2 [9] nmaps2 [10..15] maps2
+//  [16] K [17] KB [18] rows1 [19] label flags of block 1 (bit0 a3, bit1 a4)
+// A map packs m0 | m1 << 3 | m2 << 6 | (sign < 0) << 9: operator-block slot
+// i is contracted with source quark m_i.
+constexpr int kProdInts = 20;
+// Lane word of a wavefront task: product (12 bits) | y << 12 (4 bits) |
+// log2(team) << 16 (3 bits) | n << 19 (4 bits) | class << 23 (5 bits);
+// product 0xfff = idle lane.  For K > 1, y is the lane's fixed shared index
+// on the side where block 1 holds a quark pair and n the count of the other
+// side's index; for K = 1, y = 0 and n = 1.  All teams of one task have the
+// same size and class.
+constexpr int kLanesPerTask = 64;
+constexpr int kWavesPerGroup = 8;  // wavefronts of a contraction workgroup
+
+// Product classes (kernel template dispatch): kClassFull = two full
+// projections (K = 1); 1 + 4 b + 2 (nmaps1 - 1) + (nmaps2 - 1) for the split
+// shapes b = 0: 4 x 4 rows, 2 + 2 pair terms (K = 144); b = 1: 8 x 2 rows,
+// 2 + 8 (K = 36); b = 2: 2 x 8 rows, 8 + 2 (K = 36); b = 3: 4 x 4 rows,
+// 8 + 8 (K = 9); kClassSplitAny = any other split product.
+constexpr int kClassFull = 0;
+constexpr int kClassSplitAny = 31;
+int product_class(int K, int rows1, int lone1, int lone2, int nm1, int nm2);
+
 struct Program {
-  int n_types = 0;              // type slots used
-  std::vector<int> type_code;   // slot -> triplet code
+  // operator blocks built by the NBB kernel: slot -> operator code and
+  // recipe N_op = sum_k w_k N_{f1 f2 f3}[al][j_{pi(0)}][j_{pi(1)}][j_{pi(2)}]
+  int n_ops = 0;
+  std::vector<int> op_code;
+  std::vector<int> op_nterm;        // per slot
+  std::vector<int> op_term_trip;    // [slot * 3 + k] triplet code
+  std::vector<int> op_term_perm;    // [slot * 3 + k] pi(0) | pi(1) << 2 | pi(2) << 4
+  std::vector<double> op_term_w;    // [slot * 3 + k]
 
-  // Work groups: each owns a set of channels and a range of chunks.
-  std::vector<int> group_chunk;     // n_groups + 1
-  std::vector<int> group_ch;        // n_groups + 1, ranges into group_channels
-  std::vector<int> group_channels;  // global channel index
-
-  // Chunks: a set of products whose effective blocks fit the LDS budget.
-  std::vector<int> chunk_step;  // n_chunks + 1
-  std::vector<int> chunk_meb;   // n_chunks + 1
-  std::vector<int> chunk_acc;   // n_chunks + 1
-  std::vector<int> chunk_esize; // entries of the chunk's E buffer
-
-  // Load steps: bring N~_type(side ? -q : q) into LDS (if load flag), then
-  // accumulate its contributions into effective-block entries.
-  std::vector<int> step_type, step_side, step_load;
-  std::vector<int> step_ebb;  // n_steps + 1
-
-  // EBB items: E[ebb_e] += sum_{terms} coef * N~[idx]
-  std::vector<int> ebb_e;
-  std::vector<int> ebb_term;  // n_ebb + 1
-  std::vector<int> terms;     // idx | (coef << 16)
-
-  // MEB items: partial[slot][r1 * rows2 + r2] = sum_{k in [k0, k0+kn)}
-  //   E[e1 + r1 * K + k] * E[e2 + r2 * K + k]
-  std::vector<int> meb_e1, meb_e2, meb_K, meb_k0, meb_kn, meb_rows1;
-
-  // Accumulation: acc[target] += sum coef * partial[src], target =
-  // local channel * 16 + spin, src = item_in_chunk * 16 + output.
-  std::vector<int> acc_target;
-  std::vector<int> acc_src_range;  // n_acc + 1
-  std::vector<int> acc_src;
-  std::vector<double> acc_coef;
-
+  // groups: channels sharing a sink operator pair
+  std::vector<int> group_op1, group_op2;  // operator slots (momentum +q, -q)
+  std::vector<int> group_prod;            // n_groups + 1, products (units of kProdInts)
+  std::vector<int> group_task;            // n_groups + 1, tasks (units of 64 lanes)
+  std::vector<int> group_ch;              // n_groups + 1, into group_channels
+  std::vector<int> group_channels;        // global channel index
+  std::vector<int> ch_contrib;            // per group-channel slot + 1, into contrib_*
+  std::vector<int> contrib_prod;          // product (local) | rows1 << 16 | label flags << 20
+  std::vector<double> contrib_coef;
+  std::vector<int> prod_desc;
+  std::vector<int> task_lanes;
+  int max_group_products = 0;
   int max_group_channels = 0;
-  int max_chunk_items = 0;
-  int max_chunk_esize = 0;
+  int max_group_contrib = 0;
 };
 
 struct CompileOptions {
-  int e_budget = 4096;      // effective-block entries per chunk
-  int item_budget = 96;     // MEB items per chunk
-  int k_chunk = 16;         // shared indices per MEB item
-  int max_group_channels = 32;
-  int group_mode = 0;       // 0: channels sharing a sink operator pair; 1: one per channel
+  int max_group_products = 88;  // LDS result buffer bound per group
 };
 
 struct Compiled {
@@ -100,7 +113,7 @@ struct Compiled {
   std::vector<DiagramInfo> diagrams;
   Program prog;
   int n_blocks = 0, n_products = 0;
-  int64_t sum_k = 0, n_entries = 0, n_terms = 0, n_wick = 0;
+  int64_t sum_k = 0, n_entries = 0, n_terms = 0, n_wick = 0, product_k = 0;
   std::vector<int> channel_flavour;  // [n_ch][3] quark counts (u, d, s)
 };
 

@@ -26,20 +26,20 @@ __host__ __device__ inline int fft_factor(int n, int rad[8]) {
   return n == 1 ? ns : -1;
 }
 
-// In-place length-p DFT, y_k = sum_r v_r exp(sign 2 pi i r k / p).
-template <typename T> __host__ __device__ inline void small_dft(cx<T>* v, int p, int sign) {
-  if (p == 2) {
+// In-place length-P DFT, y_k = sum_r v_r exp(sign 2 pi i r k / P).
+template <int P, typename T> __host__ __device__ inline void small_dft(cx<T>* v, int sign) {
+  if constexpr (P == 2) {
     const cx<T> a = v[0], b = v[1];
     v[0] = a + b;
     v[1] = a - b;
-  } else if (p == 4) {
+  } else if constexpr (P == 4) {
     const cx<T> s02 = v[0] + v[2], d02 = v[0] - v[2], s13 = v[1] + v[3], d13 = v[1] - v[3];
     const cx<T> rot = mul_si(d13, sign);
     v[0] = s02 + s13;
     v[2] = s02 - s13;
     v[1] = d02 + rot;
     v[3] = d02 - rot;
-  } else if (p == 3) {
+  } else if constexpr (P == 3) {
     const T h = (T)0.86602540378443864676;  // sin(pi/3)
     const cx<T> t1 = v[1] + v[2], t2 = v[1] - v[2];
     const cx<T> m = v[0] - (T)0.5 * t1;
@@ -47,7 +47,8 @@ template <typename T> __host__ __device__ inline void small_dft(cx<T>* v, int p,
     v[0] = v[0] + t1;
     v[1] = m + rot;
     v[2] = m - rot;
-  } else if (p == 5) {
+  } else {
+    static_assert(P == 5, "radix");
     const T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;  // cos 2pi/5, cos 4pi/5
     const T s1 = (T)0.95105651629515357212, s2 = (T)0.58778525229247312917;   // sin 2pi/5, sin 4pi/5
     const cx<T> a1 = v[1] + v[4], b1 = v[1] - v[4], a2 = v[2] + v[3], b2 = v[2] - v[3];
@@ -61,22 +62,36 @@ template <typename T> __host__ __device__ inline void small_dft(cx<T>* v, int p,
   }
 }
 
-// One butterfly of a Stockham stage.  tw[m] = exp(sign 2 pi i m / n).
+// One butterfly of a radix-P Stockham stage.  tw[m] = exp(sign 2 pi i m / n).
 // Strides: element i of the line is at in[i * is] / out[i * os].
+template <int P, typename T>
+__host__ __device__ inline void stockham_butterfly_p(const cx<T>* in, int is, cx<T>* out, int os, int n, int Ns,
+                                                     int j, const cx<T>* tw, int sign) {
+  cx<T> v[P];
+  const int stride = n / P;
+  const int k = j % Ns;
+#pragma unroll
+  for (int r = 0; r < P; ++r) v[r] = in[(j + r * stride) * is];
+  if (Ns > 1) {
+    const int step = n / (Ns * P);
+#pragma unroll
+    for (int r = 1; r < P; ++r) v[r] = v[r] * tw[(k * r * step) % n];
+  }
+  small_dft<P>(v, sign);
+  const int base = (j / Ns) * Ns * P + k;
+#pragma unroll
+  for (int r = 0; r < P; ++r) out[(base + r * Ns) * os] = v[r];
+}
+
 template <typename T>
 __host__ __device__ inline void stockham_butterfly(const cx<T>* in, int is, cx<T>* out, int os, int n, int p,
                                                    int Ns, int j, const cx<T>* tw, int sign) {
-  cx<T> v[5];
-  const int stride = n / p;
-  const int k = j % Ns;
-  for (int r = 0; r < p; ++r) v[r] = in[(j + r * stride) * is];
-  if (Ns > 1) {
-    const int step = n / (Ns * p);
-    for (int r = 1; r < p; ++r) v[r] = v[r] * tw[(k * r * step) % n];
+  switch (p) {
+    case 4: stockham_butterfly_p<4>(in, is, out, os, n, Ns, j, tw, sign); break;
+    case 2: stockham_butterfly_p<2>(in, is, out, os, n, Ns, j, tw, sign); break;
+    case 3: stockham_butterfly_p<3>(in, is, out, os, n, Ns, j, tw, sign); break;
+    default: stockham_butterfly_p<5>(in, is, out, os, n, Ns, j, tw, sign); break;
   }
-  small_dft(v, p, sign);
-  const int base = (j / Ns) * Ns * p + k;
-  for (int r = 0; r < p; ++r) out[(base + r * Ns) * os] = v[r];
 }
 
 }  // namespace nbs

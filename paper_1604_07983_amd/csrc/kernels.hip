@@ -62,12 +62,14 @@ __global__ void k_channel_scale(const int* exps, const int* chan_nf, double* osc
 }
 
 // ---------------------------------------------------------------------------
-// Normal baryon blocks.  One workgroup per (site, slice): the three
-// propagators are staged in LDS, the diquarks
+// Normal baryon blocks, per sink operator.  One workgroup per (site, slice):
+// the three propagators are staged in LDS, the diquarks
 //   D_{f1 f2}[c][j1][j2] = sum eps_abc (C g5)_{be ga} S_f1[(be,a)][j1] S_f2[(ga,b)][j2]
-// are formed once per flavour pair, then every block
-//   N_{f1 f2 f3}[al][j1][j2][j3] = sum_c D_{f1 f2}[c][j1][j2] S_f3[(al,c)][j3]
-// is written as 3456 contiguous complex values.
+// are formed once per flavour pair, then every operator block
+//   N_op[al][j0][j1][j2] = sum_k w_k sum_c D_k[c][i0][i1] S_{f3,k}[(al,c)][i2],
+//   (i0, i1, i2) = (j_pi(0), j_pi(1), j_pi(2)),
+// (the Lambda and Sigma0 blocks as combinations of the X_u, X_d, X_s blocks,
+// Sec. 3(i)) is written as 3456 contiguous complex values.
 // ---------------------------------------------------------------------------
 template <typename Tin, typename T>
 __global__ __launch_bounds__(kThreads) void k_nbb(NbbArgs a) {
@@ -98,7 +100,7 @@ __global__ __launch_bounds__(kThreads) void k_nbb(NbbArgs a) {
       const T e = cyc == 0 ? (T)1 : (T)-1;
 #pragma unroll
       for (int be = 0; be < 4; ++be) {
-        const int ga = be ^ 1;                 // (C g5)_{be, be^1} = +1 for even be, -1 for odd
+        const int ga = be ^ 1;  // (C g5)_{be, be^1} = +1 for even be, -1 for odd
         const T g = (be & 1) ? -e : e;
         const cx<T> p = S1[(3 * be + ca) * 12 + j1] * S2[(3 * ga + cb) * 12 + j2];
         acc.re = fma(g, p.re, acc.re);
@@ -108,15 +110,27 @@ __global__ __launch_bounds__(kThreads) void k_nbb(NbbArgs a) {
     D[d][r] = acc;
   }
   __syncthreads();
-  for (int slot = 0; slot < a.n_types; ++slot) {
-    const cx<T>* Dd = D[a.type_dq[slot]];
-    const cx<T>* S3 = S[a.type_f3[slot]];
-    cx<T>* out = reinterpret_cast<cx<T>*>(a.Nq) + ((long long)(t * a.n_types + slot) * a.V + site) * kBlockEntries;
+  for (int op = 0; op < a.n_ops; ++op) {
+    cx<T>* out = reinterpret_cast<cx<T>*>(a.Nq) + ((long long)(t * a.n_ops + op) * a.V + site) * kBlockEntries;
+    const int nt = a.op_nterm[op];
     for (int o = threadIdx.x; o < kBlockEntries; o += kThreads) {
-      const int al = o / 1728, j12 = (o / 12) % 144, j3 = o % 12;
+      const int al = o / 1728, j0 = (o / 144) % 12, j1 = (o / 12) % 12, j2 = o % 12;
       cx<T> v{0, 0};
+      for (int k = 0; k < nt; ++k) {
+        const int pm = a.op_perm[op][k];
+        const int p0 = pm & 3, p1 = (pm >> 2) & 3, p2 = (pm >> 4) & 3;
+        const int i0 = p0 == 0 ? j0 : (p0 == 1 ? j1 : j2);
+        const int i1 = p1 == 0 ? j0 : (p1 == 1 ? j1 : j2);
+        const int i2 = p2 == 0 ? j0 : (p2 == 1 ? j1 : j2);
+        const cx<T>* Dd = D[a.op_dq[op][k]];
+        const cx<T>* S3 = S[a.op_f3[op][k]];
+        cx<T> u{0, 0};
 #pragma unroll
-      for (int c = 0; c < 3; ++c) cmac(v, Dd[c * 144 + j12], S3[(3 * al + c) * 12 + j3]);
+        for (int c = 0; c < 3; ++c) cmac(u, Dd[c * 144 + i0 * 12 + i1], S3[(3 * al + c) * 12 + i2]);
+        const T w = (T)a.op_w[op][k];
+        v.re = fma(w, u.re, v.re);
+        v.im = fma(w, u.im, v.im);
+      }
       out[o] = v;
     }
   }
@@ -182,43 +196,432 @@ __global__ __launch_bounds__(kThreads) void k_fft_pass(FftArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Effective blocks and their products.  One workgroup per (channel group,
-// momentum q, slice) runs the group's chunks:
-//   load N~_type(+q or -q) into LDS (when the program says so),
-//   EBB: E[e] += sum_terms coef * N~[idx]           (Eq. (9), SoA tables)
-//   MEB: partial[item][r1, r2] = sum_k E1[r1][k] E2[r2][k]   (Eq. (10))
-//   ACC: F~[channel][spin] += sum coef * partial      (sum over diagrams)
+// Effective blocks and their products (Sec. 3(ii)-(iii), Eqs. (9)-(10)).
+//
+// One workgroup per (sink-operator group, momentum q, slice) stages the two
+// operator blocks N~_op1(q) and N~_op2(-q) in LDS, then every wavefront works
+// through 64-lane tasks without further barriers: a team of 1, 4 or 16 lanes
+// owns one block product, each lane takes a slice of the shared source
+// indices xi~ = (x_A, x_B), generates the effective-block entries
+//   E[al, labels][x_A][x_B] = sum_maps sign sum_{source tensor} coef N~[...]
+// from index arithmetic, accumulates the 4 x 4 (or 8 x 2) product, and the
+// team is reduced with cross-lane shuffles.  Finally each channel output
+// sums its products with their diagram coefficients.
 // The blockIdx -> work mapping keeps every group of one momentum on the same
 // XCD so they share N~(q), N~(-q) in that XCD's L2.
 // ---------------------------------------------------------------------------
+struct BlkShape {
+  int kA, loneA, kB, loneB, nA, nB, KB;
+  bool l3, l4;
+};
+
+__device__ inline BlkShape decode_shape(int mask) {
+  BlkShape s;
+  int lone[2], in[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int bits = (mask >> (3 * h)) & 7;
+    in[h] = __popc(bits);
+    lone[h] = -1;
+    if (in[h] == 2) lone[h] = (~bits & 1) ? 0 : ((~bits & 2) ? 1 : 2);
+    if (in[h] == 1) lone[h] = (bits & 1) ? 0 : ((bits & 2) ? 1 : 2);
+  }
+  s.kA = in[0]; s.loneA = lone[0]; s.kB = in[1]; s.loneB = lone[1];
+  s.nA = in[0] == 3 ? 24 : (in[0] == 2 ? (lone[0] == 2 ? 8 : 2) : 1);
+  s.nB = in[1] == 3 ? 24 : (in[1] == 2 ? (lone[1] == 2 ? 8 : 2) : 1);
+  s.KB = lone[1] < 0 ? 1 : (lone[1] == 2 ? 3 : 12);
+  s.l3 = (mask >> 2) & 1;
+  s.l4 = (mask >> 5) & 1;
+  return s;
+}
+
+__device__ inline int eps3(int a, int b, int c) { return (a - b) * (b - c) * (c - a) / 2; }
+
+// Term t of the source tensor eps_{c1 c2 c3} (C g5)_{s1 s2} delta_{s3 al} of
+// one source baryon, restricted to the block: sets j0..j2 (3 spin + colour)
+// of the baryon's quarks that lie in the block and returns the coefficient.
+// in = quarks of the baryon in the block; lone = its lone quark (local index);
+// x = the shared index of the lone quark (3 spin + colour, or colour alone
+// for the third quark whose spin is the label al).
+__device__ inline int part_term(int in, int lone, int x, int al, int t, int& j0, int& j1, int& j2) {
+  if (in == 3) {
+    const int cp = t >> 2, sp = t & 3;
+    const int c0 = cp < 3 ? cp : cp - 3;
+    const int c1 = cp < 3 ? (c0 + 1) % 3 : (c0 + 2) % 3;
+    const int c2 = cp < 3 ? (c0 + 2) % 3 : (c0 + 1) % 3;
+    j0 = 3 * sp + c0;
+    j1 = 3 * (sp ^ 1) + c1;
+    j2 = 3 * al + c2;
+    return (cp < 3 ? 1 : -1) * ((sp & 1) ? -1 : 1);
+  }
+  if (in == 2) {
+    if (lone == 2) {
+      const int c2 = x, cc = t >> 2, sp = t & 3;
+      const int c0 = cc == 0 ? (c2 + 1) % 3 : (c2 + 2) % 3;
+      const int c1 = cc == 0 ? (c2 + 2) % 3 : (c2 + 1) % 3;
+      j0 = 3 * sp + c0;
+      j1 = 3 * (sp ^ 1) + c1;
+      return (cc == 0 ? 1 : -1) * ((sp & 1) ? -1 : 1);
+    }
+    const int sa = x / 3, ca = x % 3, sb = sa ^ 1;
+    const int o1 = (ca + 1) % 3, o2 = (ca + 2) % 3;
+    const int cb = t == 0 ? o1 : o2, c2 = t == 0 ? o2 : o1;
+    const int g = lone == 0 ? ((sa & 1) ? -1 : 1) : ((sb & 1) ? -1 : 1);
+    const int e = lone == 0 ? eps3(ca, cb, c2) : eps3(cb, ca, c2);
+    if (lone == 0) j1 = 3 * sb + cb; else j0 = 3 * sb + cb;
+    j2 = 3 * al + c2;
+    return e * g;
+  }
+  if (in == 1) {
+    if (lone == 2) j2 = 3 * al + x;
+    else if (lone == 1) j1 = x;
+    else j0 = x;
+  }
+  return 1;
+}
+
+// LDS layout of a staged block: odd strides for the two leading source
+// indices so the lanes of a team (which differ in those indices) spread over
+// the LDS banks instead of all hitting the same one (144 and 12 complex
+// entries are multiples of the bank cycle).
+constexpr int kLdsJ0 = 157, kLdsJ1 = 13, kLdsAl = 1888, kLdsBlock = 2 * kLdsAl;
+
+__device__ inline int lds_index(int i) {
+  const int al = i / 1728, j0 = (i / 144) % 12, j1 = (i / 12) % 12, j2 = i % 12;
+  return al * kLdsAl + j0 * kLdsJ0 + j1 * kLdsJ1 + j2;
+}
+
+__device__ inline int pick6(int m, int j0, int j1, int j2, int j3, int j4, int j5) {
+  return m == 0 ? j0 : m == 1 ? j1 : m == 2 ? j2 : m == 3 ? j3 : m == 4 ? j4 : j5;
+}
+
+// Stride of source quark q in N~[al][slot0][slot1][slot2] under map mp
+// (slot i is contracted with quark m_i): 144, 12, 1, or 0 if q is not in the block.
+__device__ inline int quark_stride(int mp, int q) {
+  return ((mp & 7) == q ? kLdsJ0 : 0) + (((mp >> 3) & 7) == q ? kLdsJ1 : 0) + (((mp >> 6) & 7) == q ? 1 : 0);
+}
+
+// rows r of a block -> (al, a3, a4): r = (al * n3 + a3) * n4 + a4
+__device__ inline void decode_row(const BlkShape& sh, int r, int& al, int& a3, int& a4) {
+  const int n4 = sh.l4 ? 2 : 1, n3 = sh.l3 ? 2 : 1;
+  a4 = sh.l4 ? r % 2 : 0;
+  a3 = sh.l3 ? (r / n4) % 2 : 0;
+  al = r / (n3 * n4);
+}
+
+// Row r = (al, a3, a4) enters the address of every term linearly:
+//   al * 1728 + 3 a3 * stride(quark 2) + 3 a4 * stride(quark 5).
+template <int R>
+__device__ inline void row_offsets(const BlkShape& sh, int mp, int ro[R]) {
+  const int s2 = 3 * quark_stride(mp, 2), s5 = 3 * quark_stride(mp, 5);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    int al, a3, a4;
+    decode_row(sh, r, al, a3, a4);
+    ro[r] = al * kLdsAl + a3 * s2 + a4 * s5;
+  }
+}
+
+template <typename T, int R>
+__device__ inline void add_rows(const cx<T>* slot, int base, T c, const int ro[R], cx<T> e[R]) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const cx<T> x = slot[base + ro[r]];
+    e[r].re = fma(c, x.re, e[r].re);
+    e[r].im = fma(c, x.im, e[r].im);
+  }
+}
+
+// Entries E[r][x_A][x_B] of the R rows of one block at one shared index:
+// each source-tensor term is generated once and read for all rows.
+template <typename T, int R>
+__device__ inline void block_rows(const cx<T>* slot, const BlkShape& sh, int nmaps, int mp0, int mp1,
+                                  const int ro0[R], const int ro1[R], int xA, int xB, cx<T> e[R]) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) e[r] = cx<T>{0, 0};
+  const int sg0 = ((mp0 >> 9) & 1) ? -1 : 1, sg1 = ((mp1 >> 9) & 1) ? -1 : 1;
+  for (int ta = 0; ta < sh.nA; ++ta) {
+    int j0 = 0, j1 = 0, j2 = 0;
+    const int cA = part_term(sh.kA, sh.loneA, xA, 0, ta, j0, j1, j2);
+    for (int tb = 0; tb < sh.nB; ++tb) {
+      int j3 = 0, j4 = 0, j5 = 0;
+      const int c = cA * part_term(sh.kB, sh.loneB, xB, 0, tb, j3, j4, j5);
+      const int b0 = pick6(mp0 & 7, j0, j1, j2, j3, j4, j5) * kLdsJ0 +
+                     pick6((mp0 >> 3) & 7, j0, j1, j2, j3, j4, j5) * kLdsJ1 +
+                     pick6((mp0 >> 6) & 7, j0, j1, j2, j3, j4, j5);
+      add_rows<T, R>(slot, b0, (T)(sg0 * c), ro0, e);
+      if (nmaps > 1) {
+        const int b1 = pick6(mp1 & 7, j0, j1, j2, j3, j4, j5) * kLdsJ0 +
+                       pick6((mp1 >> 3) & 7, j0, j1, j2, j3, j4, j5) * kLdsJ1 +
+                       pick6((mp1 >> 6) & 7, j0, j1, j2, j3, j4, j5);
+        add_rows<T, R>(slot, b1, (T)(sg1 * c), ro1, e);
+      }
+    }
+  }
+}
+
+// Generic lane work (used for products of two full projections, K = 1):
+// k runs over [k0, k0 + nk) and every entry is generated from part_term.
 template <typename T, int R1>
-__device__ inline void meb_item(const cx<T>* E, int e1, int e2, int K, int k0, int kn, cx<T>* out) {
+__device__ inline void lane_work_generic(const cx<T>* slotA, const cx<T>* slotB, const int* d, int k0, int nk,
+                                         cx<T> acc[16]) {
   constexpr int R2 = 16 / R1;
-  cx<T> acc[16];
-#pragma unroll
-  for (int o = 0; o < 16; ++o) acc[o] = cx<T>{0, 0};
-  for (int k = k0; k < k0 + kn; ++k) {
-    cx<T> x[R1], y[R2];
-#pragma unroll
-    for (int r = 0; r < R1; ++r) x[r] = E[e1 + r * K + k];
-#pragma unroll
-    for (int r = 0; r < R2; ++r) y[r] = E[e2 + r * K + k];
+  const BlkShape s1 = decode_shape(d[0]), s2 = decode_shape(d[8]);
+  const int nm1 = d[1], nm2 = d[9];
+  const int p10 = d[2], p11 = d[3], p20 = d[10], p21 = d[11];
+  int ro10[R1], ro11[R1], ro20[R2], ro21[R2];
+  row_offsets<R1>(s1, p10, ro10);
+  row_offsets<R1>(s1, p11, ro11);
+  row_offsets<R2>(s2, p20, ro20);
+  row_offsets<R2>(s2, p21, ro21);
+  const int KB = d[17];
+  for (int k = k0; k < k0 + nk; ++k) {
+    const int xA = k / KB, xB = k - xA * KB;
+    cx<T> e1[R1], e2[R2];
+    block_rows<T, R1>(slotA, s1, nm1, p10, p11, ro10, ro11, xA, xB, e1);
+    block_rows<T, R2>(slotB, s2, nm2, p20, p21, ro20, ro21, xA, xB, e2);
 #pragma unroll
     for (int r1 = 0; r1 < R1; ++r1)
 #pragma unroll
-      for (int r2 = 0; r2 < R2; ++r2) cmac(acc[r1 * R2 + r2], x[r1], y[r2]);
+      for (int r2 = 0; r2 < R2; ++r2) cmac(acc[r1 * R2 + r2], e1[r1], e2[r2]);
   }
+}
+
+// Universal table of the source-tensor terms of a quark pair inside a block
+// (the third quark of that source baryon, the lone one, sits in the other
+// block with shared index x): entry = j_p | j_q << 4 | (coef < 0) << 8 with
+// (p, q) the pair's quarks in order, label spin 0.  Lone quark 0 or 1:
+// 12 values of x, 2 terms; lone quark 2: 3 values (its colour), 8 terms.
+constexpr int kPairTable = 72;
+__device__ inline int pair_index(int lone, int x, int t) { return lone < 2 ? lone * 24 + x * 2 + t : 48 + x * 8 + t; }
+
+__device__ inline void build_pair_table(int* tp, int tid, int nthreads) {
+  for (int i = tid; i < kPairTable; i += nthreads) {
+    const int lone = i < 24 ? 0 : (i < 48 ? 1 : 2);
+    const int x = lone < 2 ? (i - 24 * lone) / 2 : (i - 48) / 8;
+    const int t = lone < 2 ? (i - 24 * lone) % 2 : (i - 48) % 8;
+    int j0 = 0, j1 = 0, j2 = 0;
+    const int c = part_term(2, lone, x, 0, t, j0, j1, j2);
+    const int jp = lone == 0 ? j1 : j0, jq = lone == 2 ? j1 : j2;
+    tp[i] = jp | (jq << 4) | ((c < 0) << 8);
+  }
+}
+
+// Products of a pair+single block with its complementary single+pair block
+// (K = 9, 36, 144).  Side Y is where block 1 holds a quark pair: the lane
+// fixes y on that side, so block 1's pair terms are formed once per lane,
+// and walks z over the other side, where block 1 only shifts by z * stride
+// and block 2's pair terms come from the universal table.
+template <typename T, int R1>
+__device__ inline void lane_work_split(const cx<T>* slotA, const cx<T>* slotB, const int* d, const int* tp,
+                                       int y, cx<T> acc[16]) {
+  constexpr int R2 = 16 / R1;
+  const BlkShape s1 = decode_shape(d[0]), s2 = decode_shape(d[8]);
+  const bool pairA = s1.kA == 2;                    // block 1's pair is in source baryon A
+  const int base1 = pairA ? 0 : 3, base2 = pairA ? 3 : 0;
+  const int lone1 = pairA ? s1.loneA : s1.loneB;    // lone quark (local) of block 1's pair baryon
+  const int lone2 = pairA ? s2.loneB : s2.loneA;    // lone quark (local) of block 2's pair baryon
+  const int Kz = lone2 == 2 ? 3 : 12;
+  const int nP1 = lone1 == 2 ? 8 : 2, nP2 = lone2 == 2 ? 8 : 2;
+  const int p1 = base1 + (lone1 == 0 ? 1 : 0), q1 = base1 + (lone1 == 2 ? 1 : 2);
+  const int p2 = base2 + (lone2 == 0 ? 1 : 0), q2 = base2 + (lone2 == 2 ? 1 : 2);
+  const int ys = base1 + lone1, zs = base2 + lone2;  // the single quarks: in block 2 (y) and block 1 (z)
+  const int nm1 = d[1], nm2 = d[9];
+  const int mp1[2] = {d[2], d[3]}, mp2[2] = {d[10], d[11]};
+  int ro1[2][R1], ro2[2][R2];
+  row_offsets<R1>(s1, mp1[0], ro1[0]);
+  row_offsets<R1>(s1, mp1[1], ro1[1]);
+  row_offsets<R2>(s2, mp2[0], ro2[0]);
+  row_offsets<R2>(s2, mp2[1], ro2[1]);
+  // block 1: fixed pair terms for this lane, z-stride of its single quark
+  int off1[2][8], zst1[2];
+  T c1[8];
 #pragma unroll
-  for (int o = 0; o < 16; ++o) out[o] = acc[o];
+  for (int t = 0; t < 8; ++t) {
+    const int e = t < nP1 ? tp[pair_index(lone1, y, t)] : 0;
+    c1[t] = (e >> 8) & 1 ? (T)-1 : (T)1;
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+      off1[m][t] = (e & 15) * quark_stride(mp1[m], p1) + ((e >> 4) & 15) * quark_stride(mp1[m], q1);
+  }
+  T sg1[2], sg2[2];
+  int yo2[2], st2p[2], st2q[2];
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    zst1[m] = quark_stride(mp1[m], zs);
+    sg1[m] = ((mp1[m] >> 9) & 1) ? (T)-1 : (T)1;
+    sg2[m] = ((mp2[m] >> 9) & 1) ? (T)-1 : (T)1;
+    yo2[m] = y * quark_stride(mp2[m], ys);
+    st2p[m] = quark_stride(mp2[m], p2);
+    st2q[m] = quark_stride(mp2[m], q2);
+  }
+  for (int z = 0; z < Kz; ++z) {
+    cx<T> e1[R1], e2[R2];
+#pragma unroll
+    for (int r = 0; r < R1; ++r) e1[r] = cx<T>{0, 0};
+#pragma unroll
+    for (int r = 0; r < R2; ++r) e2[r] = cx<T>{0, 0};
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      if (m >= nm1) break;
+      const int zo = z * zst1[m];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        if (t >= nP1) break;
+        add_rows<T, R1>(slotA, off1[m][t] + zo, sg1[m] * c1[t], ro1[m], e1);
+      }
+    }
+    for (int t = 0; t < nP2; ++t) {
+      const int e = tp[pair_index(lone2, z, t)];
+      const T c = (e >> 8) & 1 ? (T)-1 : (T)1;
+      const int jp = e & 15, jq = (e >> 4) & 15;
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        if (m >= nm2) break;
+        add_rows<T, R2>(slotB, yo2[m] + jp * st2p[m] + jq * st2q[m], sg2[m] * c, ro2[m], e2);
+      }
+    }
+#pragma unroll
+    for (int r1 = 0; r1 < R1; ++r1)
+#pragma unroll
+      for (int r2 = 0; r2 < R2; ++r2) cmac(acc[r1 * R2 + r2], e1[r1], e2[r2]);
+  }
+}
+
+// Class-specialised form of lane_work_split: rows, pair-term counts and map
+// counts are compile-time, so the loop over z is straight-line code.
+template <typename T, int R1, int NP1, int NP2, int NM1, int NM2>
+__device__ inline void lane_split_fixed(const cx<T>* slotA, const cx<T>* slotB, const int* d, const int* tp,
+                                        int y, cx<T> acc[16]) {
+  constexpr int R2 = 16 / R1;
+  constexpr int KZ = NP2 == 8 ? 3 : 12;
+  const BlkShape s1 = decode_shape(d[0]), s2 = decode_shape(d[8]);
+  const bool pairA = s1.kA == 2;
+  const int base1 = pairA ? 0 : 3, base2 = pairA ? 3 : 0;
+  const int lone1 = pairA ? s1.loneA : s1.loneB;
+  const int lone2 = pairA ? s2.loneB : s2.loneA;
+  const int p1 = base1 + (lone1 == 0 ? 1 : 0), q1 = base1 + (lone1 == 2 ? 1 : 2);
+  const int p2 = base2 + (lone2 == 0 ? 1 : 0), q2 = base2 + (lone2 == 2 ? 1 : 2);
+  const int ys = base1 + lone1, zs = base2 + lone2;
+  int mp1[NM1], mp2[NM2];
+#pragma unroll
+  for (int m = 0; m < NM1; ++m) mp1[m] = d[2 + m];
+#pragma unroll
+  for (int m = 0; m < NM2; ++m) mp2[m] = d[10 + m];
+  int ro1[NM1][R1], ro2[NM2][R2];
+#pragma unroll
+  for (int m = 0; m < NM1; ++m) row_offsets<R1>(s1, mp1[m], ro1[m]);
+#pragma unroll
+  for (int m = 0; m < NM2; ++m) row_offsets<R2>(s2, mp2[m], ro2[m]);
+  int off1[NM1][NP1], zst1[NM1];
+  T cc1[NM1][NP1];
+#pragma unroll
+  for (int t = 0; t < NP1; ++t) {
+    const int e = tp[pair_index(lone1, y, t)];
+    const int jp = e & 15, jq = (e >> 4) & 15;
+    const int c = ((e >> 8) & 1) ? -1 : 1;
+#pragma unroll
+    for (int m = 0; m < NM1; ++m) {
+      off1[m][t] = jp * quark_stride(mp1[m], p1) + jq * quark_stride(mp1[m], q1);
+      cc1[m][t] = (T)((((mp1[m] >> 9) & 1) ? -1 : 1) * c);
+    }
+  }
+  int yo2[NM2], st2p[NM2], st2q[NM2];
+  T sg2[NM2];
+#pragma unroll
+  for (int m = 0; m < NM1; ++m) zst1[m] = quark_stride(mp1[m], zs);
+#pragma unroll
+  for (int m = 0; m < NM2; ++m) {
+    yo2[m] = y * quark_stride(mp2[m], ys);
+    st2p[m] = quark_stride(mp2[m], p2);
+    st2q[m] = quark_stride(mp2[m], q2);
+    sg2[m] = ((mp2[m] >> 9) & 1) ? (T)-1 : (T)1;
+  }
+  const int tz0 = pair_index(lone2, 0, 0), tzs = NP2;  // table row of z is tz0 + z * NP2
+#pragma unroll 1
+  for (int z = 0; z < KZ; ++z) {
+    cx<T> e1[R1], e2[R2];
+#pragma unroll
+    for (int r = 0; r < R1; ++r) e1[r] = cx<T>{0, 0};
+#pragma unroll
+    for (int r = 0; r < R2; ++r) e2[r] = cx<T>{0, 0};
+#pragma unroll
+    for (int m = 0; m < NM1; ++m) {
+      const int zo = z * zst1[m];
+#pragma unroll
+      for (int t = 0; t < NP1; ++t) add_rows<T, R1>(slotA, off1[m][t] + zo, cc1[m][t], ro1[m], e1);
+    }
+#pragma unroll
+    for (int t = 0; t < NP2; ++t) {
+      const int e = tp[tz0 + z * tzs + t];
+      const T c = ((e >> 8) & 1) ? (T)-1 : (T)1;
+      const int jp = e & 15, jq = (e >> 4) & 15;
+#pragma unroll
+      for (int m = 0; m < NM2; ++m)
+        add_rows<T, R2>(slotB, yo2[m] + jp * st2p[m] + jq * st2q[m], sg2[m] * c, ro2[m], e2);
+    }
+#pragma unroll
+    for (int r1 = 0; r1 < R1; ++r1)
+#pragma unroll
+      for (int r2 = 0; r2 < R2; ++r2) cmac(acc[r1 * R2 + r2], e1[r1], e2[r2]);
+  }
+}
+
+// Dispatch on the (wavefront-uniform) product class.
+template <typename T, int R1, int NP1, int NP2>
+__device__ inline void split_maps(int nmc, const cx<T>* sA, const cx<T>* sB, const int* d, const int* tp, int y,
+                                  cx<T> acc[16]) {
+  switch (nmc) {
+    case 0: lane_split_fixed<T, R1, NP1, NP2, 1, 1>(sA, sB, d, tp, y, acc); break;
+    case 1: lane_split_fixed<T, R1, NP1, NP2, 1, 2>(sA, sB, d, tp, y, acc); break;
+    case 2: lane_split_fixed<T, R1, NP1, NP2, 2, 1>(sA, sB, d, tp, y, acc); break;
+    default: lane_split_fixed<T, R1, NP1, NP2, 2, 2>(sA, sB, d, tp, y, acc); break;
+  }
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_contract(ContractArgs a) {
+__device__ inline void run_product(int cls, const cx<T>* sA, const cx<T>* sB, const int* d, const int* tp, int y,
+                                   int n, cx<T> acc[16]) {
+  if (cls == 0) {
+    lane_work_generic<T, 4>(sA, sB, d, y, n, acc);
+  } else if (cls < 5) {
+    split_maps<T, 4, 2, 2>(cls - 1, sA, sB, d, tp, y, acc);
+  } else if (cls < 9) {
+    split_maps<T, 8, 2, 8>(cls - 5, sA, sB, d, tp, y, acc);
+  } else if (cls < 13) {
+    split_maps<T, 2, 8, 2>(cls - 9, sA, sB, d, tp, y, acc);
+  } else if (cls < 17) {
+    split_maps<T, 4, 8, 8>(cls - 13, sA, sB, d, tp, y, acc);
+  } else {
+    const int rows1 = d[18];
+    if (rows1 == 4)
+      lane_work_split<T, 4>(sA, sB, d, tp, y, acc);
+    else if (rows1 == 2)
+      lane_work_split<T, 2>(sA, sB, d, tp, y, acc);
+    else
+      lane_work_split<T, 8>(sA, sB, d, tp, y, acc);
+  }
+}
+
+size_t contract_lds_bytes(int prec, int max_gprod, int max_gcontrib, int max_gch) {
+  const size_t el = prec == 0 ? sizeof(cd) : sizeof(cf);
+  const size_t real = prec == 0 ? sizeof(double) : sizeof(float);
+  return el * (2 * (size_t)kLdsBlock + (size_t)max_gprod * 16) + real * max_gcontrib +
+         sizeof(int) * (kPairTable + max_gcontrib + max_gch + 1);
+}
+
+constexpr int kContractThreads = 512;
+
+template <typename T>
+__global__ __launch_bounds__(kContractThreads) void k_contract(ContractArgs a) {
   extern __shared__ char smem_raw[];
-  cx<T>* slot = reinterpret_cast<cx<T>*>(smem_raw);
-  cx<T>* E = slot + kBlockEntries;
-  cx<T>* part = E + a.e_budget;
-  cx<T>* acc = part + a.item_budget * 16;
+  cx<T>* slotA = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* slotB = slotA + kLdsBlock;
+  cx<T>* R = slotB + kLdsBlock;
+  T* ccoef = reinterpret_cast<T*>(R + a.max_gprod * 16);
+  int* tp = reinterpret_cast<int*>(ccoef + a.max_gcontrib);
+  int* cword = tp + kPairTable;
+  int* coff = cword + a.max_gcontrib;
 
   const long long nb8 = (a.n_blocks + 7) / 8 * 8;
   const long long b = blockIdx.x;
@@ -231,62 +634,90 @@ __global__ __launch_bounds__(kThreads) void k_contract(ContractArgs a) {
   const int mq = (a.Lx - qx) % a.Lx + a.Lx * ((a.Ly - qy) % a.Ly + a.Ly * ((a.Lz - qz) % a.Lz));
   const int tid = threadIdx.x;
 
-  const int gch0 = a.group_ch[g], nch = a.group_ch[g + 1] - gch0;
-  for (int i = tid; i < nch * 16; i += kThreads) acc[i] = cx<T>{0, 0};
-
+  // stage the two operator blocks (all loads in flight before the LDS
+  // stores), the group's channel contributions and the pair table
   const cx<T>* Nq = reinterpret_cast<const cx<T>*>(a.Nq);
-  for (int c = a.group_chunk[g]; c < a.group_chunk[g + 1]; ++c) {
-    const int esize = a.chunk_esize[c];
-    for (int i = tid; i < esize; i += kThreads) E[i] = cx<T>{0, 0};
-    __syncthreads();
-    for (int s = a.chunk_step[c]; s < a.chunk_step[c + 1]; ++s) {
-      if (a.step_load[s]) {
-        const int site = a.step_side[s] ? mq : q;
-        const cx<T>* src = Nq + ((long long)(t * a.n_types + a.step_type[s]) * a.V + site) * kBlockEntries;
-        for (int i = tid; i < kBlockEntries; i += kThreads) slot[i] = src[i];
-        __syncthreads();
-      }
-      for (int it = a.step_ebb[s] + tid; it < a.step_ebb[s + 1]; it += kThreads) {
-        cx<T> v{0, 0};
-        for (int k = a.ebb_term[it]; k < a.ebb_term[it + 1]; ++k) {
-          const int tm = a.terms[k];
-          const T cf = (T)(tm >> 16);
-          const cx<T> x = slot[tm & 0xffff];
-          v.re = fma(cf, x.re, v.re);
-          v.im = fma(cf, x.im, v.im);
-        }
-        E[a.ebb_e[it]] += v;
-      }
-      __syncthreads();
+  const cx<T>* srcA = Nq + ((long long)(t * a.n_ops + a.group_op1[g]) * a.V + q) * kBlockEntries;
+  const cx<T>* srcB = Nq + ((long long)(t * a.n_ops + a.group_op2[g]) * a.V + mq) * kBlockEntries;
+  constexpr int kPer = (kBlockEntries + kContractThreads - 1) / kContractThreads;
+  {
+    cx<T> va[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int i = tid + k * kContractThreads;
+      va[k] = srcA[i < kBlockEntries ? i : kBlockEntries - 1];
     }
-    const int m0 = a.chunk_meb[c], m1 = a.chunk_meb[c + 1];
-    for (int it = m0 + tid; it < m1; it += kThreads) {
-      cx<T>* out = part + (it - m0) * 16;
-      const int r1 = a.meb_rows1[it];
-      if (r1 == 4)
-        meb_item<T, 4>(E, a.meb_e1[it], a.meb_e2[it], a.meb_K[it], a.meb_k0[it], a.meb_kn[it], out);
-      else if (r1 == 2)
-        meb_item<T, 2>(E, a.meb_e1[it], a.meb_e2[it], a.meb_K[it], a.meb_k0[it], a.meb_kn[it], out);
-      else
-        meb_item<T, 8>(E, a.meb_e1[it], a.meb_e2[it], a.meb_K[it], a.meb_k0[it], a.meb_kn[it], out);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int i = tid + k * kContractThreads;
+      if (i < kBlockEntries) slotA[lds_index(i)] = va[k];
     }
-    __syncthreads();
-    for (int it = a.chunk_acc[c] + tid; it < a.chunk_acc[c + 1]; it += kThreads) {
-      cx<T> v{0, 0};
-      for (int k = a.acc_src_range[it]; k < a.acc_src_range[it + 1]; ++k) {
-        const T cf = (T)a.acc_coef[k];
-        const cx<T> x = part[a.acc_src[k]];
-        v.re = fma(cf, x.re, v.re);
-        v.im = fma(cf, x.im, v.im);
-      }
-      acc[a.acc_target[it]] += v;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int i = tid + k * kContractThreads;
+      va[k] = srcB[i < kBlockEntries ? i : kBlockEntries - 1];
     }
-    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int i = tid + k * kContractThreads;
+      if (i < kBlockEntries) slotB[lds_index(i)] = va[k];
+    }
   }
+  const int gc0 = a.group_ch[g], nch = a.group_ch[g + 1] - gc0;
+  const int cbase = a.ch_contrib[gc0], ncon = a.ch_contrib[gc0 + nch] - cbase;
+  for (int i = tid; i < ncon; i += kContractThreads) {
+    cword[i] = a.contrib_prod[cbase + i];
+    ccoef[i] = (T)a.contrib_coef[cbase + i];
+  }
+  for (int i = tid; i <= nch; i += kContractThreads) coff[i] = a.ch_contrib[gc0 + i] - cbase;
+  build_pair_table(tp, tid, kContractThreads);
+  __syncthreads();
+
+  const int pbase = a.group_prod[g];
+  const int wave = tid >> 6, lane = tid & 63;
+  for (int task = a.group_task[g] + wave; task < a.group_task[g + 1]; task += kContractThreads / 64) {
+    const int w = a.task_lanes[(long long)task * 64 + lane];
+    const int p = w & 0xfff, lg = (w >> 16) & 7;
+    const int cls = __builtin_amdgcn_readfirstlane((w >> 23) & 31);
+    cx<T> acc[16];
+#pragma unroll
+    for (int o = 0; o < 16; ++o) acc[o] = cx<T>{0, 0};
+    if (p != 0xfff) {
+      const int y = (w >> 12) & 15, n = (w >> 19) & 15;
+      run_product<T>(cls, slotA, slotB, a.prod_desc + (long long)(pbase + p) * 20, tp, y, n, acc);
+    }
+    for (int dd = 1; dd < (1 << lg); dd <<= 1) {
+#pragma unroll
+      for (int o = 0; o < 16; ++o) {
+        acc[o].re += __shfl_xor(acc[o].re, dd);
+        acc[o].im += __shfl_xor(acc[o].im, dd);
+      }
+    }
+    if (p != 0xfff && (lane & ((1 << lg) - 1)) == 0) {
+#pragma unroll
+      for (int o = 0; o < 16; ++o) R[p * 16 + o] = acc[o];
+    }
+  }
+  __syncthreads();
+
   cx<T>* Ft = reinterpret_cast<cx<T>*>(a.Ft);
-  for (int i = tid; i < nch * 16; i += kThreads) {
-    const int ch = a.group_channels[gch0 + i / 16], s = i % 16;
-    Ft[(((long long)ch * a.t_count + t) * 16 + s) * a.V + q] = acc[i];
+  for (int i = tid; i < nch * 16; i += kContractThreads) {
+    const int cl = i >> 4, s = i & 15;
+    const int a1 = (s >> 3) & 1, a2 = (s >> 2) & 1, a3 = (s >> 1) & 1, a4 = s & 1;
+    cx<T> v{0, 0};
+    for (int c = coff[cl]; c < coff[cl + 1]; ++c) {
+      const int w = cword[c];
+      const int p = w & 0xffff, rows2 = 16 / ((w >> 16) & 15);
+      const bool l3 = (w >> 20) & 1, l4 = (w >> 21) & 1;
+      const int r1 = (a1 * (l3 ? 2 : 1) + (l3 ? a3 : 0)) * (l4 ? 2 : 1) + (l4 ? a4 : 0);
+      const int r2 = (a2 * (l3 ? 1 : 2) + (l3 ? 0 : a3)) * (l4 ? 1 : 2) + (l4 ? 0 : a4);
+      const T cf = ccoef[c];
+      const cx<T> x = R[p * 16 + r1 * rows2 + r2];
+      v.re = fma(cf, x.re, v.re);
+      v.im = fma(cf, x.im, v.im);
+    }
+    const int ch = a.group_channels[gc0 + cl];
+    Ft[(((long long)ch * a.t_count + t) * 16 + s) * a.V + q] = v;
   }
 }
 
@@ -349,24 +780,19 @@ hipError_t launch_fft_pass(int kind, const FftArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-size_t contract_lds_bytes(int prec, int e_budget, int item_budget, int max_gch) {
-  const size_t el = prec == 0 ? sizeof(cd) : sizeof(cf);
-  return el * ((size_t)kBlockEntries + e_budget + (size_t)item_budget * 16 + (size_t)max_gch * 16);
-}
-
 hipError_t launch_contract(int prec, const ContractArgs& a, hipStream_t st) {
-  const size_t lds = contract_lds_bytes(prec, a.e_budget, a.item_budget, a.max_gch);
+  const size_t lds = contract_lds_bytes(prec, a.max_gprod, a.max_gcontrib, a.max_gch);
   const long long nb8 = (a.n_blocks + 7) / 8 * 8;
   dim3 grid((unsigned)nb8);
   hipError_t e;
   if (prec == 0) {
     e = hipFuncSetAttribute((const void*)k_contract<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_contract<double>, grid, dim3(kThreads), lds, st, a);
+    hipLaunchKernelGGL(k_contract<double>, grid, dim3(kContractThreads), lds, st, a);
   } else {
     e = hipFuncSetAttribute((const void*)k_contract<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_contract<float>, grid, dim3(kThreads), lds, st, a);
+    hipLaunchKernelGGL(k_contract<float>, grid, dim3(kContractThreads), lds, st, a);
   }
   return hipGetLastError();
 }

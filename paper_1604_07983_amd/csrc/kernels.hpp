@@ -8,13 +8,17 @@ namespace nbs {
 constexpr int kBlockEntries = 3456;  // 2 x 12 x 12 x 12 complex per normal block
 constexpr int kThreads = 256;
 
-// Normal baryon blocks (Eq. (5)/(8)) of every needed flavour triplet.
+// Operator blocks (Eq. (5)/(8) combined per Eqs. (2)-(3)) of every sink
+// operator: N_op[al][j0][j1][j2] = sum_k w_k N_{trip_k}[al][j_pi(0)][j_pi(1)][j_pi(2)].
+constexpr int kMaxOps = 11;
 struct NbbArgs {
   const void* S[3];      // u, d, s propagators: [t_count][V][12][12]
-  void* Nq;              // [t_count][n_types][V][3456]
-  int V, t_count, n_types;
-  int type_f3[27], type_dq[27];  // per type slot: third flavour, diquark slot
-  int n_dq, dq_f1[9], dq_f2[9];  // diquark flavour pairs
+  void* Nq;              // [t_count][n_ops][V][3456]
+  int V, t_count, n_ops;
+  int n_dq, dq_f1[4], dq_f2[4];    // diquark flavour pairs
+  int op_nterm[kMaxOps];
+  int op_dq[kMaxOps][3], op_f3[kMaxOps][3], op_perm[kMaxOps][3];  // perm: pi(0) | pi(1) << 2 | pi(2) << 4
+  double op_w[kMaxOps][3];
   int flavour_used[3];
   const int* scale_exp;  // [3][t_count] power-of-two exponents (precision form) or null
 };
@@ -31,21 +35,16 @@ struct FftArgs {
   double gscale;          // global factor
 };
 
-// Effective blocks + products (Eqs. (9)-(10)), program interpreted per
-// (channel group, momentum, slice).
+// Effective blocks and their products (Eqs. (9)-(10)) per (group, q, slice).
 struct ContractArgs {
   const void* Nq;
   void* Ft;  // [n_ch][t_count][16][V]
-  int V, Lx, Ly, Lz, t_count, n_types, n_ch, n_groups;
+  int V, Lx, Ly, Lz, t_count, n_ops, n_groups;
   long long n_blocks;  // n_groups * V * t_count
-  const int *group_chunk, *group_ch, *group_channels;
-  const int *chunk_step, *chunk_meb, *chunk_acc, *chunk_esize;
-  const int *step_type, *step_side, *step_load, *step_ebb;
-  const int *ebb_e, *ebb_term, *terms;
-  const int *meb_e1, *meb_e2, *meb_K, *meb_k0, *meb_kn, *meb_rows1;
-  const int *acc_target, *acc_src_range, *acc_src;
-  const double* acc_coef;
-  int e_budget, item_budget, max_gch;
+  const int *group_op1, *group_op2, *group_prod, *group_task, *group_ch, *group_channels;
+  const int *ch_contrib, *contrib_prod, *prod_desc, *task_lanes;
+  const double* contrib_coef;
+  int max_gprod, max_gcontrib, max_gch;
 };
 
 // prec: 0 = FP64 form, 1 = precision form (complex64 storage, FP32 compute).
@@ -57,7 +56,7 @@ hipError_t launch_channel_scale(const int* exps, const int* chan_nf, double* osc
 hipError_t launch_nbb(int prec, const NbbArgs& a, hipStream_t st);
 // kind: 0 = complex128 -> complex128, 1 = complex64 -> complex64, 2 = complex64 -> complex128
 hipError_t launch_fft_pass(int kind, const FftArgs& a, hipStream_t st);
-size_t contract_lds_bytes(int prec, int e_budget, int item_budget, int max_gch);
+size_t contract_lds_bytes(int prec, int max_gprod, int max_gcontrib, int max_gch);
 hipError_t launch_contract(int prec, const ContractArgs& a, hipStream_t st);
 
 }  // namespace nbs

@@ -199,27 +199,33 @@ nbs_status nbs_plan_create(nbs_plan* out, const nbs_geometry* g, int32_t n_geom,
   if (hipSetDevice(device) != hipSuccess) { delete p; return NBS_ERR_DEVICE; }
 
   const auto& P = p->comp.prog;
-  const int nt = P.n_types;
-  // diquark flavour pairs and per-type parameters for the NBB kernel
+  const int nt = P.n_ops;
+  if (nt > nbs::kMaxOps) { delete p; return NBS_ERR_UNSUPPORTED; }
+  // diquark flavour pairs and per-operator recipes for the NBB kernel
   nbs::NbbArgs& nb = p->nbb;
   std::map<int, int> dq;
   for (int s = 0; s < nt; ++s) {
-    const int code = P.type_code[s];
-    const int f1 = code / 9, f2 = (code / 3) % 3, f3 = code % 3;
-    const int key = f1 * 3 + f2;
-    if (!dq.count(key)) {
-      const int id = (int)dq.size();
-      dq[key] = id;
-      if (id >= 4) { delete p; return NBS_ERR_UNSUPPORTED; }
-      nb.dq_f1[id] = f1;
-      nb.dq_f2[id] = f2;
+    nb.op_nterm[s] = P.op_nterm[s];
+    for (int k = 0; k < P.op_nterm[s]; ++k) {
+      const int code = P.op_term_trip[3 * s + k];
+      const int f1 = code / 9, f2 = (code / 3) % 3, f3 = code % 3;
+      const int key = f1 * 3 + f2;
+      if (!dq.count(key)) {
+        const int id = (int)dq.size();
+        if (id >= 4) { delete p; return NBS_ERR_UNSUPPORTED; }
+        dq[key] = id;
+        nb.dq_f1[id] = f1;
+        nb.dq_f2[id] = f2;
+      }
+      nb.op_dq[s][k] = dq[key];
+      nb.op_f3[s][k] = f3;
+      nb.op_perm[s][k] = P.op_term_perm[3 * s + k];
+      nb.op_w[s][k] = P.op_term_w[3 * s + k];
+      nb.flavour_used[f1] = nb.flavour_used[f2] = nb.flavour_used[f3] = 1;
     }
-    nb.type_dq[s] = dq[key];
-    nb.type_f3[s] = f3;
-    nb.flavour_used[f1] = nb.flavour_used[f2] = nb.flavour_used[f3] = 1;
   }
   nb.n_dq = (int)dq.size();
-  nb.n_types = nt;
+  nb.n_ops = nt;
   nb.V = (int)V;
   nb.t_count = g->t_count;
 
@@ -233,18 +239,15 @@ nbs_status nbs_plan_create(nbs_plan* out, const nbs_geometry* g, int32_t n_geom,
     flat.insert(flat.end(), v.begin(), v.end());
     flat.push_back(0);  // keep empty tables addressable
   };
-  put("group_chunk", P.group_chunk); put("group_ch", P.group_ch); put("group_channels", P.group_channels);
-  put("chunk_step", P.chunk_step); put("chunk_meb", P.chunk_meb); put("chunk_acc", P.chunk_acc);
-  put("chunk_esize", P.chunk_esize); put("step_type", P.step_type); put("step_side", P.step_side);
-  put("step_load", P.step_load); put("step_ebb", P.step_ebb); put("ebb_e", P.ebb_e);
-  put("ebb_term", P.ebb_term); put("terms", P.terms); put("meb_e1", P.meb_e1); put("meb_e2", P.meb_e2);
-  put("meb_K", P.meb_K); put("meb_k0", P.meb_k0); put("meb_kn", P.meb_kn); put("meb_rows1", P.meb_rows1);
-  put("acc_target", P.acc_target); put("acc_src_range", P.acc_src_range); put("acc_src", P.acc_src);
+  put("group_op1", P.group_op1); put("group_op2", P.group_op2); put("group_prod", P.group_prod);
+  put("group_task", P.group_task); put("group_ch", P.group_ch); put("group_channels", P.group_channels);
+  put("ch_contrib", P.ch_contrib); put("contrib_prod", P.contrib_prod); put("prod_desc", P.prod_desc);
+  put("task_lanes", P.task_lanes);
   std::vector<int> nf(p->comp.channel_flavour);
 
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) { (void)hipGetLastError(); free_b = (size_t)-1; }
-  const size_t need = nq_bytes + ft_bytes + flat.size() * 4 + P.acc_coef.size() * 8 + (1 << 20);
+  const size_t need = nq_bytes + ft_bytes + flat.size() * 4 + P.contrib_coef.size() * 8 + (1 << 20);
   if (need > free_b) {
     delete p;
     return NBS_ERR_NOMEM;
@@ -260,7 +263,7 @@ nbs_status nbs_plan_create(nbs_plan* out, const nbs_geometry* g, int32_t n_geom,
     return s;
   }
   p->prog = (int*)tmp;
-  if ((s = dev_alloc(p, std::max<size_t>(8, P.acc_coef.size() * 8), &tmp, &countdown)) != NBS_OK) {
+  if ((s = dev_alloc(p, std::max<size_t>(8, P.contrib_coef.size() * 8), &tmp, &countdown)) != NBS_OK) {
     free_all(p); delete p; return s;
   }
   p->coef = (double*)tmp;
@@ -274,8 +277,8 @@ nbs_status nbs_plan_create(nbs_plan* out, const nbs_geometry* g, int32_t n_geom,
   p->chan_nf = (int*)tmp;
 
   hipError_t e = hipMemcpy(p->prog, flat.data(), flat.size() * 4, hipMemcpyHostToDevice);
-  if (e == hipSuccess && !P.acc_coef.empty())
-    e = hipMemcpy(p->coef, P.acc_coef.data(), P.acc_coef.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess && !P.contrib_coef.empty())
+    e = hipMemcpy(p->coef, P.contrib_coef.data(), P.contrib_coef.size() * 8, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->chan_nf, nf.data(), nf.size() * 4, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -291,27 +294,23 @@ nbs_status nbs_plan_create(nbs_plan* out, const nbs_geometry* g, int32_t n_geom,
   c.V = (int)V;
   c.Lx = g->L[0]; c.Ly = g->L[1]; c.Lz = g->L[2];
   c.t_count = g->t_count;
-  c.n_types = nt;
-  c.n_ch = n_ch;
-  c.n_groups = (int)P.group_chunk.size() - 1;
+  c.n_ops = nt;
+  c.n_groups = (int)P.group_prod.size() - 1;
   c.n_blocks = (long long)c.n_groups * V * g->t_count;
   if (c.n_blocks + 8 > 0x7fffffffLL) {
     free_all(p);
     delete p;
     return NBS_ERR_UNSUPPORTED;
   }
-  c.group_chunk = T("group_chunk"); c.group_ch = T("group_ch"); c.group_channels = T("group_channels");
-  c.chunk_step = T("chunk_step"); c.chunk_meb = T("chunk_meb"); c.chunk_acc = T("chunk_acc");
-  c.chunk_esize = T("chunk_esize"); c.step_type = T("step_type"); c.step_side = T("step_side");
-  c.step_load = T("step_load"); c.step_ebb = T("step_ebb"); c.ebb_e = T("ebb_e"); c.ebb_term = T("ebb_term");
-  c.terms = T("terms"); c.meb_e1 = T("meb_e1"); c.meb_e2 = T("meb_e2"); c.meb_K = T("meb_K");
-  c.meb_k0 = T("meb_k0"); c.meb_kn = T("meb_kn"); c.meb_rows1 = T("meb_rows1");
-  c.acc_target = T("acc_target"); c.acc_src_range = T("acc_src_range"); c.acc_src = T("acc_src");
-  c.acc_coef = p->coef;
-  c.e_budget = p->opt.e_budget;
-  c.item_budget = p->opt.item_budget;
+  c.group_op1 = T("group_op1"); c.group_op2 = T("group_op2"); c.group_prod = T("group_prod");
+  c.group_task = T("group_task"); c.group_ch = T("group_ch"); c.group_channels = T("group_channels");
+  c.ch_contrib = T("ch_contrib"); c.contrib_prod = T("contrib_prod"); c.prod_desc = T("prod_desc");
+  c.task_lanes = T("task_lanes");
+  c.contrib_coef = p->coef;
+  c.max_gprod = std::max(1, P.max_group_products);
+  c.max_gcontrib = std::max(1, P.max_group_contrib);
   c.max_gch = std::max(1, P.max_group_channels);
-  if (nbs::contract_lds_bytes(prec, c.e_budget, c.item_budget, c.max_gch) > 160 * 1024) {
+  if (nbs::contract_lds_bytes(prec, c.max_gprod, c.max_gcontrib, c.max_gch) > 160 * 1024) {
     free_all(p);
     delete p;
     return NBS_ERR_UNSUPPORTED;
@@ -356,7 +355,7 @@ nbs_status nbs_build_blocks(nbs_plan p, const void* const* prop_u, const void* c
   }
   if ((s = hip_check(p, nbs::launch_nbb(p->prec, a, st), "nbb")) != NBS_OK) return s;
   const int kind = p->prec == NBS_FP64 ? 0 : 1;
-  s = fft3d(p, kind, kind, p->Nq, p->Nq, (long long)g.t_count * p->comp.prog.n_types, g.L, nbs::kBlockEntries,
+  s = fft3d(p, kind, kind, p->Nq, p->Nq, (long long)g.t_count * p->comp.prog.n_ops, g.L, nbs::kBlockEntries,
             -1, nullptr, 1, 1.0, st);
   if (s != NBS_OK) return s;
   p->stage = ST_BUILT;
@@ -411,7 +410,7 @@ nbs_status nbs_plan_destroy(nbs_plan p) {
 nbs_status nbs_plan_info(const nbs_plan p, nbs_plan_info_t* info) {
   if (!p || !info) return NBS_ERR_INVALID;
   info->n_channels = p->n_ch;
-  info->n_types = p->comp.prog.n_types;
+  info->n_types = p->comp.prog.n_ops;
   info->n_diagrams = (int32_t)p->comp.diagrams.size();
   info->n_blocks = p->comp.n_blocks;
   info->n_products = p->comp.n_products;
@@ -448,20 +447,18 @@ nbs_status nbs_plan_table(const nbs_plan p, const char* name, void* buf, int64_t
   if (!p || !name || !n || (cap > 0 && !buf)) return NBS_ERR_INVALID;
   const auto& P = p->comp.prog;
   const std::string nm(name);
-  if (nm == "acc_coef") {
-    *n = (int64_t)P.acc_coef.size();
-    if (cap > 0) std::memcpy(buf, P.acc_coef.data(), sizeof(double) * std::min<int64_t>(cap, *n));
+  const std::vector<double>* dt = nm == "contrib_coef" ? &P.contrib_coef : nm == "op_term_w" ? &P.op_term_w : nullptr;
+  if (dt) {
+    *n = (int64_t)dt->size();
+    if (cap > 0) std::memcpy(buf, dt->data(), sizeof(double) * std::min<int64_t>(cap, *n));
     return NBS_OK;
   }
   const std::map<std::string, const std::vector<int>*> tabs = {
-      {"type_code", &P.type_code}, {"group_chunk", &P.group_chunk}, {"group_ch", &P.group_ch},
-      {"group_channels", &P.group_channels}, {"chunk_step", &P.chunk_step}, {"chunk_meb", &P.chunk_meb},
-      {"chunk_acc", &P.chunk_acc}, {"chunk_esize", &P.chunk_esize}, {"step_type", &P.step_type},
-      {"step_side", &P.step_side}, {"step_load", &P.step_load}, {"step_ebb", &P.step_ebb},
-      {"ebb_e", &P.ebb_e}, {"ebb_term", &P.ebb_term}, {"terms", &P.terms}, {"meb_e1", &P.meb_e1},
-      {"meb_e2", &P.meb_e2}, {"meb_K", &P.meb_K}, {"meb_k0", &P.meb_k0}, {"meb_kn", &P.meb_kn},
-      {"meb_rows1", &P.meb_rows1}, {"acc_target", &P.acc_target}, {"acc_src_range", &P.acc_src_range},
-      {"acc_src", &P.acc_src}};
+      {"op_code", &P.op_code}, {"op_nterm", &P.op_nterm}, {"op_term_trip", &P.op_term_trip},
+      {"op_term_perm", &P.op_term_perm}, {"group_op1", &P.group_op1}, {"group_op2", &P.group_op2},
+      {"group_prod", &P.group_prod}, {"group_task", &P.group_task}, {"group_ch", &P.group_ch},
+      {"group_channels", &P.group_channels}, {"ch_contrib", &P.ch_contrib}, {"contrib_prod", &P.contrib_prod},
+      {"prod_desc", &P.prod_desc}, {"task_lanes", &P.task_lanes}};
   auto it = tabs.find(nm);
   if (it == tabs.end()) return NBS_ERR_INVALID;
   *n = (int64_t)it->second->size();
@@ -471,9 +468,9 @@ nbs_status nbs_plan_table(const nbs_plan p, const char* name, void* buf, int64_t
 
 nbs_status nbs_plan_params(const nbs_plan p, int32_t out[4]) {
   if (!p || !out) return NBS_ERR_INVALID;
-  out[0] = p->opt.e_budget;
-  out[1] = p->opt.item_budget;
-  out[2] = p->opt.k_chunk;
+  out[0] = nbs::kProdInts;
+  out[1] = nbs::kLanesPerTask;
+  out[2] = std::max(1, p->comp.prog.max_group_products);
   out[3] = std::max(1, p->comp.prog.max_group_channels);
   return NBS_OK;
 }

@@ -1,73 +1,176 @@
 """CPU emulation of the compiled contraction program (test code only).
 
-Executes the SoA tables exported by nbs_plan_table exactly as the
-contraction kernel interprets them (load / EBB / MEB / ACC per chunk), on
-momentum-space normal blocks supplied by the test.  It lets the host test
-suite check the channel compiler and its scheduling against the oracle
-without a GPU; it is never part of the product path.
+Executes the structure-of-arrays program exported by nbs_plan_table the way
+the contraction kernel does: per group the two operator blocks, per 64-lane
+task the lane words (product, first shared index, team size, count), the
+effective-block entries generated from the source-tensor structure, the
+team sums and the channel accumulation.  It lets the host test suite check
+the channel compiler, the task packing and the entry generation rules
+against the oracle without a GPU; it is never part of the product path.
 """
 from __future__ import annotations
 
 import numpy as np
 
-NAMES = ("type_code", "group_chunk", "group_ch", "group_channels", "chunk_step", "chunk_meb",
-         "chunk_acc", "chunk_esize", "step_type", "step_side", "step_load", "step_ebb", "ebb_e",
-         "ebb_term", "terms", "meb_e1", "meb_e2", "meb_K", "meb_k0", "meb_kn", "meb_rows1",
-         "acc_target", "acc_src_range", "acc_src", "acc_coef")
+NAMES = ("op_code", "op_nterm", "op_term_trip", "op_term_perm", "op_term_w", "group_op1", "group_op2",
+         "group_prod", "group_task", "group_ch", "group_channels", "ch_contrib", "contrib_prod",
+         "contrib_coef", "prod_desc", "task_lanes")
+PROD_INTS = 20
+
+EPS = {(0, 1, 2): 1, (1, 2, 0): 1, (2, 0, 1): 1, (0, 2, 1): -1, (2, 1, 0): -1, (1, 0, 2): -1}
+CG5 = {(0, 1): 1, (1, 0): -1, (2, 3): 1, (3, 2): -1}
 
 
 def tables(plan):
     return {n: plan.table(n) for n in NAMES}
 
 
-def emulate_q(T, params, Nq_plus, Nq_minus, n_ch):
-    """F~(q) [n_ch, 16] from Nq_plus[slot] = N~_type(q), Nq_minus[slot] = N~_type(-q)."""
-    out = np.zeros((n_ch, 16), dtype=np.complex128)
-    terms = T["terms"].astype(np.int64)
-    t_idx = terms & 0xFFFF
-    t_coef = (T["terms"] >> 16).astype(np.float64)  # arithmetic shift keeps the sign
-    n_groups = len(T["group_chunk"]) - 1
-    for g in range(n_groups):
-        c0, c1 = T["group_ch"][g], T["group_ch"][g + 1]
-        nch = c1 - c0
-        assert nch <= params["max_group_channels"]
-        acc = np.zeros(nch * 16, dtype=np.complex128)
-        held = None
-        slot = None
-        for c in range(T["group_chunk"][g], T["group_chunk"][g + 1]):
-            esize = T["chunk_esize"][c]
-            assert esize <= params["e_budget"]
-            E = np.zeros(esize, dtype=np.complex128)
-            for s in range(T["chunk_step"][c], T["chunk_step"][c + 1]):
-                want = (int(T["step_type"][s]), int(T["step_side"][s]))
-                if T["step_load"][s]:
-                    held = want
-                    slot = (Nq_minus if want[1] else Nq_plus)[want[0]]
-                assert held == want, "step reads a block the LDS slot does not hold"
-                i0, i1 = T["step_ebb"][s], T["step_ebb"][s + 1]
-                if i1 == i0:
+def operator_blocks(T, triplet_blocks):
+    """Operator blocks N_op[V, 3456] from triplet blocks {code: [V, 2, 12, 12, 12]}."""
+    out = []
+    for s, _code in enumerate(T["op_code"]):
+        acc = None
+        for k in range(T["op_nterm"][s]):
+            code = int(T["op_term_trip"][3 * s + k])
+            pm = int(T["op_term_perm"][3 * s + k])
+            pi = (pm & 3, (pm >> 2) & 3, (pm >> 4) & 3)
+            sigma = [pi.index(o) for o in range(3)]  # op slot -> triplet slot
+            blk = np.transpose(triplet_blocks[code], (0, 1, 2 + sigma[0], 2 + sigma[1], 2 + sigma[2]))
+            term = T["op_term_w"][3 * s + k] * blk
+            acc = term if acc is None else acc + term
+        out.append(acc.reshape(acc.shape[0], 3456))
+    return out
+
+
+def _shape(mask):
+    sh = {}
+    for h, base in ((0, 0), (1, 3)):
+        bits = (mask >> base) & 7
+        n = bin(bits).count("1")
+        lone = -1
+        if n == 2:
+            lone = [i for i in range(3) if not (bits >> i) & 1][0]
+        elif n == 1:
+            lone = [i for i in range(3) if (bits >> i) & 1][0]
+        sh["in%d" % h], sh["lone%d" % h] = n, lone
+    sh["l3"], sh["l4"] = bool((mask >> 2) & 1), bool((mask >> 5) & 1)
+    return sh
+
+
+def _part(n, lone, x, al):
+    """(quark -> j, coef) terms of one source baryon's tensor inside a block."""
+    out = []
+    if n == 3:
+        for (c0, c1, c2), e in EPS.items():
+            for (s0, s1), g in CG5.items():
+                out.append(({0: 3 * s0 + c0, 1: 3 * s1 + c1, 2: 3 * al + c2}, e * g))
+    elif n == 2 and lone == 2:
+        for (c0, c1, c2), e in EPS.items():
+            if c2 != x:
+                continue
+            for (s0, s1), g in CG5.items():
+                out.append(({0: 3 * s0 + c0, 1: 3 * s1 + c1}, e * g))
+    elif n == 2:
+        sa, ca = divmod(x, 3)
+        b = 1 - lone
+        for cs, e in EPS.items():
+            if cs[lone] != ca:
+                continue
+            for sp, g in CG5.items():
+                if sp[lone] != sa:
                     continue
-                lo, hi = T["ebb_term"][i0], T["ebb_term"][i1]
-                vals = t_coef[lo:hi] * slot[t_idx[lo:hi]]
-                starts = T["ebb_term"][i0:i1] - lo
-                sums = np.add.reduceat(vals, starts)
-                tgt = T["ebb_e"][i0:i1]
-                assert len(np.unique(tgt)) == len(tgt)
-                assert tgt.max() < esize
-                E[tgt] += sums
-            m0, m1 = T["chunk_meb"][c], T["chunk_meb"][c + 1]
-            assert m1 - m0 <= params["item_budget"]
-            part = np.zeros((m1 - m0) * 16, dtype=np.complex128)
-            for it in range(m0, m1):
-                e1, e2, K = T["meb_e1"][it], T["meb_e2"][it], T["meb_K"][it]
-                k0, kn, r1 = T["meb_k0"][it], T["meb_kn"][it], T["meb_rows1"][it]
-                r2 = 16 // r1
-                ks = np.arange(k0, k0 + kn)
-                X = E[e1 + np.arange(r1)[:, None] * K + ks[None, :]]
-                Y = E[e2 + np.arange(r2)[:, None] * K + ks[None, :]]
-                part[(it - m0) * 16:(it - m0 + 1) * 16] = (X @ Y.T).ravel()
-            for it in range(T["chunk_acc"][c], T["chunk_acc"][c + 1]):
-                a0, a1 = T["acc_src_range"][it], T["acc_src_range"][it + 1]
-                acc[T["acc_target"][it]] += np.sum(T["acc_coef"][a0:a1] * part[T["acc_src"][a0:a1]])
-        out[T["group_channels"][c0:c1]] = acc.reshape(nch, 16)
+                out.append(({b: 3 * sp[b] + cs[b], 2: 3 * al + cs[2]}, e * g))
+    elif n == 1:
+        out.append(({lone: 3 * al + x if lone == 2 else x}, 1))
+    else:
+        out.append(({}, 1))
+    return out
+
+
+def _entry(slot, mask, maps, r, xA, xB):
+    sh = _shape(mask)
+    n3, n4 = (2 if sh["l3"] else 1), (2 if sh["l4"] else 1)
+    a4 = r % 2 if sh["l4"] else 0
+    a3 = (r // n4) % 2 if sh["l3"] else 0
+    al = r // (n3 * n4)
+    v = 0j
+    for ja, ca in _part(sh["in0"], sh["lone0"], xA, a3):
+        for jb, cb in _part(sh["in1"], sh["lone1"], xB, a4):
+            j = dict(ja)
+            j.update({k + 3: vv for k, vv in jb.items()})
+            for mp in maps:
+                m = (mp & 7, (mp >> 3) & 7, (mp >> 6) & 7)
+                sg = -1 if (mp >> 9) & 1 else 1
+                v += sg * ca * cb * slot[al * 1728 + j[m[0]] * 144 + j[m[1]] * 12 + j[m[2]]]
+    return v
+
+
+def emulate_q(T, Nq_plus, Nq_minus, n_ch):
+    """F~(q) [n_ch, 16] from operator blocks at +q (Nq_plus[slot]) and -q."""
+    out = np.zeros((n_ch, 16), dtype=np.complex128)
+    lanes = T["task_lanes"].reshape(-1, 64)
+    desc = T["prod_desc"].reshape(-1, PROD_INTS)
+    n_groups = len(T["group_prod"]) - 1
+    for g in range(n_groups):
+        slotA, slotB = Nq_plus[T["group_op1"][g]], Nq_minus[T["group_op2"][g]]
+        pb, pe = T["group_prod"][g], T["group_prod"][g + 1]
+        R = {}
+        for task in range(T["group_task"][g], T["group_task"][g + 1]):
+            words = lanes[task]
+            lgs = {(int(w) >> 16) & 7 for w in words if int(w) & 0xFFF != 0xFFF}
+            cls = {(int(w) >> 23) & 31 for w in words if int(w) & 0xFFF != 0xFFF}
+            if not lgs:
+                continue
+            assert len(lgs) == 1, "a task mixes team sizes"
+            assert len(cls) == 1, "a task mixes product classes"
+            tl = 1 << lgs.pop()
+            for t0 in range(0, 64, tl):
+                team = [int(w) for w in words[t0:t0 + tl]]
+                ps = {w & 0xFFF for w in team} - {0xFFF}
+                if not ps:
+                    continue
+                assert len(ps) == 1, "a team mixes products"
+                p = ps.pop()
+                assert p not in R, "product computed twice"
+                d = desc[pb + p]
+                K, KB, r1n = int(d[16]), int(d[17]), int(d[18])
+                r2n = 16 // r1n
+                m1 = [int(x) for x in d[2:2 + d[1]]]
+                m2 = [int(x) for x in d[10:10 + d[9]]]
+                pairA = _shape(int(d[0]))["in0"] == 2
+                covered = []
+                acc = np.zeros(16, dtype=np.complex128)
+                for w in team:
+                    if w & 0xFFF == 0xFFF:
+                        continue
+                    y, n = (w >> 12) & 15, (w >> 19) & 15
+                    for z in range(n):
+                        if K == 1:
+                            xA = xB = 0
+                        else:
+                            xA, xB = (y, z) if pairA else (z, y)
+                        covered.append(xA * KB + xB)
+                        e1 = [_entry(slotA, int(d[0]), m1, r, xA, xB) for r in range(r1n)]
+                        e2 = [_entry(slotB, int(d[8]), m2, r, xA, xB) for r in range(r2n)]
+                        acc += np.outer(e1, e2).ravel()
+                assert sorted(covered) == list(range(K)), "shared indices not covered exactly once"
+                R[p] = acc
+        assert sorted(R) == list(range(pe - pb))
+        c0 = T["group_ch"][g]
+        for cl in range(T["group_ch"][g + 1] - c0):
+            ch = T["group_channels"][c0 + cl]
+            for s in range(16):
+                a1, a2, a3, a4 = (s >> 3) & 1, (s >> 2) & 1, (s >> 1) & 1, s & 1
+                v = 0j
+                for c in range(T["ch_contrib"][c0 + cl], T["ch_contrib"][c0 + cl + 1]):
+                    w = int(T["contrib_prod"][c])
+                    p = w & 0xFFFF
+                    d = desc[pb + p]
+                    assert (w >> 16) & 15 == d[18] and (w >> 20) & 3 == d[19]
+                    l3, l4 = bool(d[19] & 1), bool(d[19] & 2)
+                    rows2 = 16 // d[18]
+                    r1 = (a1 * (2 if l3 else 1) + (a3 if l3 else 0)) * (2 if l4 else 1) + (a4 if l4 else 0)
+                    r2 = (a2 * (1 if l3 else 2) + (0 if l3 else a3)) * (1 if l4 else 2) + (0 if l4 else a4)
+                    v += T["contrib_coef"][c] * R[p][r1 * rows2 + r2]
+                out[ch, s] = v
     return out

@@ -69,7 +69,7 @@ def test_r52_table_counts():
     assert info["n_diagrams"] == 640
     assert info["sum_k"] == 41920
     assert info["n_wick_perms"] == 3376
-    assert info["n_types"] == 9
+    assert info["n_types"] == 8  # operator blocks: p n Lambda Sigma0 Sigma+ Sigma- Xi0 Xi-
     # every channel's Wick permutation count agrees with the oracle's enumeration
     total = sum(oracle.count_perms(c)[1] for c in ch)
     assert total == info["n_wick_perms"]
@@ -82,14 +82,16 @@ def test_per_channel_wick_counts(chan):
     assert p.info()["n_wick_perms"] == oracle.count_perms(chan)[1]
 
 
-def _momentum_blocks(L, S, type_codes):
+def _momentum_operator_blocks(L, S, T):
     V = int(np.prod(L))
-    out = []
-    for code in type_codes:
-        f1, f2, f3 = code // 9, (code // 3) % 3, code % 3
-        N = oracle.normal_blocks(L, S, f1, f2, f3).reshape(V, 3456)
-        out.append(oracle.dft3(N, L, -1))
-    return out
+    trip = {}
+    for s in range(len(T["op_code"])):
+        for k in range(T["op_nterm"][s]):
+            code = int(T["op_term_trip"][3 * s + k])
+            if code not in trip:
+                trip[code] = oracle.normal_blocks(L, S, code // 9, (code // 3) % 3, code % 3)
+    ops = emu.operator_blocks(T, trip)
+    return [oracle.dft3(o.reshape(V, 3456), L, -1) for o in ops]
 
 
 def _neg(L, q):
@@ -99,19 +101,22 @@ def _neg(L, q):
 
 @pytest.mark.parametrize("chans,L,qs", [
     ([channels.WORKED_EXAMPLE, ("p", "p", "p", "p")], (2, 2, 2), None),
-    (channels.r52(), (2, 3, 2), [0, 1, 7]),
+    ([("Lambda", "Lambda", "Sigma+", "Sigma-"), ("Xi0", "Sigma0", "Xi-", "Sigma+"),
+      ("n", "Xi0", "Lambda", "Lambda")], (2, 2, 2), [0, 3, 5]),
+    (channels.r52(), (2, 3, 2), [0, 7]),
 ])
 def test_compiled_program_reproduces_oracle(chans, L, qs):
+    """The compiled program, run by the CPU emulator with the kernel's rules,
+    gives the oracle's F~(q) (built from explicit Wick permutations)."""
     rng = np.random.default_rng(101)
     S = ref.random_props(rng, L)
     p = host_plan(chans, L=L, T=4)
     T = emu.tables(p)
-    params = p.params()
-    Nt = _momentum_blocks(L, S, T["type_code"])
+    Nt = _momentum_operator_blocks(L, S, T)
     V = int(np.prod(L))
     for q in (qs if qs is not None else range(V)):
         mq = _neg(L, q)
-        got = emu.emulate_q(T, params, [n[q] for n in Nt], [n[mq] for n in Nt], len(chans))
+        got = emu.emulate_q(T, [n[q] for n in Nt], [n[mq] for n in Nt], len(chans))
         qv = (q % L[0], (q // L[0]) % L[1], q // (L[0] * L[1]))
         want = oracle.correlators_at_q(L, S, chans, qv)
         err = np.linalg.norm(got - want, axis=1) / np.linalg.norm(want, axis=1)
