@@ -101,6 +101,10 @@ nbs_status hip_check(nbs_plan p, hipError_t e, const char* what) {
   return fail(p, NBS_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Elements of one FFT tile in LDS (two FP64 buffers of this size per
+// workgroup): 1024 keeps four workgroups resident per CU.
+constexpr int kFftTile = 1024;
+
 int pick_ib(long long inner) {
   for (int ib : {16, 8, 4, 2})
     if (inner % ib == 0) return ib;
@@ -123,7 +127,7 @@ nbs_status fft3d(nbs_plan p, int kind_first, int kind_rest, const void* in, void
     a.inner = inner;
     a.outer = batch * V / ((long long)L[ax] * (inner / inner0));
     a.IB = pick_ib(inner);
-    a.OB = std::max(1, 2048 / (a.IB * a.n));
+    a.OB = std::max(1, kFftTile / (a.IB * a.n));
     a.sign = sign;
     a.gscale = ax == 2 ? gscale : 1.0;
     a.oscale = ax == 2 ? oscale : nullptr;

@@ -1,0 +1,73 @@
+"""GPU parity at the workloads' full sizes, in the launch configuration the
+benchmark times: 16^3 x 32 (plain FP64, all 52 channels) and 32^3 x 64 (the
+precision form).  The oracle cannot afford every output at these sizes, so it
+is evaluated one by one at sampled momenta (F~_c(q) of all 52 channels, the
+q = 0 one being the sum rule) and, for a channel subset, over a full slice.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1604_07983_amd import binding, channels, runner
+from tests.parity_util import flat_props, rel_err_per_channel
+
+pytestmark = pytest.mark.gpu
+
+DECAY = {"u": 0.4, "d": 0.4, "s": 0.55}
+
+
+def announce(msg):
+    print("[case] " + msg, flush=True)
+
+
+def run_window(L, T, prec, t_begin, t_count, chans):
+    import torch
+    dt = np.complex128 if prec == binding.NBS_FP64 else np.complex64
+    props = runner.host_props(L, T, range(t_begin, t_begin + t_count), decay=DECAY, dtype=dt)
+    dp = runner.device_props(props, prec)
+    r = runner.Runner(L, T, chans, prec=prec, t_begin=t_begin, t_count=t_count)
+    F = r.run(*dp)
+    torch.cuda.synchronize()
+    out = F.cpu().numpy()
+    r.close()
+    del dp
+    return props, out
+
+
+def check_sampled_momenta(L, props, Fg, chans, slices, qs, tol):
+    """F~_c(q) = sum_r F_c(r) exp(-i q.r) of the GPU output against the oracle."""
+    for ti in slices:
+        Fq = np.fft.fftn(Fg[:, ti], axes=(2, 3, 4))  # [c, 16, qz, qy, qx]
+        S = flat_props(props, ti)
+        for q in qs:
+            want = oracle.correlators_at_q(L, S, chans, q)
+            got = Fq[:, :, q[2], q[1], q[0]]
+            err = np.linalg.norm(got - want, axis=1) / np.linalg.norm(want, axis=1)
+            assert err.max() <= tol, (ti, q, float(err.max()), int(err.argmax()))
+
+
+def test_config2_fp64_16c32_all_channels():
+    announce("16^3 x 32 fp64 r52")
+    L, T = (16, 16, 16), 32
+    chans = channels.r52()
+    props, Fg = run_window(L, T, binding.NBS_FP64, 0, 32, chans)
+    assert np.isfinite(Fg).all()
+    check_sampled_momenta(L, props, Fg, chans, slices=(0, 31), qs=((0, 0, 0), (1, 2, 3), (15, 8, 1)),
+                          tol=1e-12)
+    # a full slice for channels of each sector
+    sub = [0, 1, 12, 30, 51]
+    Fo = oracle.correlators(L, flat_props(props, 17), [chans[c] for c in sub], mode="fft")
+    err = rel_err_per_channel(Fg[sub][:, 17:18], Fo[:, None])
+    assert err.max() <= 1e-12, err
+
+
+@pytest.mark.parametrize("t_begin", [0, 62])
+def test_config3_fp32_32c64_windows(t_begin):
+    """Precision form at 32^3, two-slice windows at both ends of T = 64 (the
+    latest slices decay by e^-(0.4*4+0.55*2)*63 ~ 1e-74 in some channels)."""
+    announce("32^3 x 64 precision form window %d" % t_begin)
+    L, T = (32, 32, 32), 64
+    chans = channels.r52()
+    props, Fg = run_window(L, T, binding.NBS_FP32_MFMA, t_begin, 2, chans)
+    assert np.isfinite(Fg).all()
+    check_sampled_momenta(L, props, Fg, chans, slices=(1,), qs=((0, 0, 0), (3, 30, 7)), tol=1e-5)
