@@ -254,13 +254,16 @@ std::string compile_channels(const std::vector<ChannelSpec>& chans, const Compil
       // 16), each walking the Kz values of the other side.
       auto ky_of = [&](int p) {
         const Shape s1 = shape_of(prods[p].first.mask);
-        return s1.K() == 1 ? 1 : (s1.kA == 2 ? s1.KA : s1.KB);
+        return s1.K() == 1 ? 16 : (s1.kA == 2 ? s1.KA : s1.KB);  // K = 1: 16 lanes share the 24 terms
       };
       auto team = [&](int p) {
         const int ky = ky_of(p);
-        return ky == 1 ? 1 : (ky <= 4 ? 4 : 16);
+        return ky <= 4 ? 4 : 16;
       };
-      auto kz_of = [&](int p) { return shape_of(prods[p].first.mask).K() / ky_of(p); };
+      auto kz_of = [&](int p) {
+        const int K = shape_of(prods[p].first.mask).K();
+        return K == 1 ? 1 : K / ky_of(p);
+      };
       auto cls_of = [&](int p) {
         const Shape s1 = shape_of(prods[p].first.mask), s2 = shape_of(prods[p].second.mask);
         return product_class(s1.K(), s1.rows(), s1.kA == 2 ? s1.loneA : s1.loneB, s1.kA == 2 ? s2.loneB : s2.loneA,

@@ -64,8 +64,9 @@ constexpr int kProdInts = 20;
 // log2(team) << 16 (3 bits) | n << 19 (4 bits) | class << 23 (5 bits);
 // product 0xfff = idle lane.  For K > 1, y is the lane's fixed shared index
 // on the side where block 1 holds a quark pair and n the count of the other
-// side's index; for K = 1, y = 0 and n = 1.  All teams of one task have the
-// same size and class.
+// side's index; for K = 1, y is the lane's share of the source terms and n = 1.  All teams of one task have the
+// same size and class.  Products of two full projections (K = 1) take a
+// 16-lane team whose lanes y = 0..15 share the 24 source-tensor terms.
 constexpr int kLanesPerTask = 64;
 constexpr int kWavesPerGroup = 8;  // wavefronts of a contraction workgroup
 

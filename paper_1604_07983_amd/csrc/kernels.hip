@@ -567,6 +567,70 @@ __device__ inline void lane_split_fixed(const cx<T>* slotA, const cx<T>* slotB, 
   }
 }
 
+// Product of two full projections (K = 1): E1[a1 a3'] and E2[a2 a4'] are
+// sums of the 24 source-tensor terms of one baryon each.  A 16-lane team
+// shares the terms (lane u takes terms u and u + 16), reduces E1 and E2
+// across the team, and lane 0 forms the 4 x 4 outer product (the other lanes
+// contribute zero to the team sum that follows).
+template <typename T, int NM1, int NM2>
+__device__ inline void lane_full(const cx<T>* slotA, const cx<T>* slotB, const int* d, int u, cx<T> acc[16]) {
+  const BlkShape s1 = decode_shape(d[0]), s2 = decode_shape(d[8]);
+  int mp1[2] = {d[2], d[3]}, mp2[2] = {d[10], d[11]};
+  cx<T> e1[4], e2[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) e1[r] = e2[r] = cx<T>{0, 0};
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int t = u + 16 * h;
+    if (t < 24) {
+      // block 1
+      {
+        int j0 = 0, j1 = 0, j2 = 0, j3 = 0, j4 = 0, j5 = 0;
+        const int c = s1.kA == 3 ? part_term(3, -1, 0, 0, t, j0, j1, j2) : part_term(3, -1, 0, 0, t, j3, j4, j5);
+#pragma unroll
+        for (int m = 0; m < NM1; ++m) {
+          int ro[4];
+          row_offsets<4>(s1, mp1[m], ro);
+          const int b = pick6(mp1[m] & 7, j0, j1, j2, j3, j4, j5) * kLdsJ0 +
+                        pick6((mp1[m] >> 3) & 7, j0, j1, j2, j3, j4, j5) * kLdsJ1 +
+                        pick6((mp1[m] >> 6) & 7, j0, j1, j2, j3, j4, j5);
+          add_rows<T, 4>(slotA, b, (T)((((mp1[m] >> 9) & 1) ? -1 : 1) * c), ro, e1);
+        }
+      }
+      // block 2
+      {
+        int j0 = 0, j1 = 0, j2 = 0, j3 = 0, j4 = 0, j5 = 0;
+        const int c = s2.kA == 3 ? part_term(3, -1, 0, 0, t, j0, j1, j2) : part_term(3, -1, 0, 0, t, j3, j4, j5);
+#pragma unroll
+        for (int m = 0; m < NM2; ++m) {
+          int ro[4];
+          row_offsets<4>(s2, mp2[m], ro);
+          const int b = pick6(mp2[m] & 7, j0, j1, j2, j3, j4, j5) * kLdsJ0 +
+                        pick6((mp2[m] >> 3) & 7, j0, j1, j2, j3, j4, j5) * kLdsJ1 +
+                        pick6((mp2[m] >> 6) & 7, j0, j1, j2, j3, j4, j5);
+          add_rows<T, 4>(slotB, b, (T)((((mp2[m] >> 9) & 1) ? -1 : 1) * c), ro, e2);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int dd = 1; dd < 16; dd <<= 1) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      e1[r].re += __shfl_xor(e1[r].re, dd);
+      e1[r].im += __shfl_xor(e1[r].im, dd);
+      e2[r].re += __shfl_xor(e2[r].re, dd);
+      e2[r].im += __shfl_xor(e2[r].im, dd);
+    }
+  }
+  if (u == 0) {
+#pragma unroll
+    for (int r1 = 0; r1 < 4; ++r1)
+#pragma unroll
+      for (int r2 = 0; r2 < 4; ++r2) cmac(acc[r1 * 4 + r2], e1[r1], e2[r2]);
+  }
+}
+
 // Dispatch on the (wavefront-uniform) product class.
 template <typename T, int R1, int NP1, int NP2>
 __device__ inline void split_maps(int nmc, const cx<T>* sA, const cx<T>* sB, const int* d, const int* tp, int y,
@@ -583,7 +647,11 @@ template <typename T>
 __device__ inline void run_product(int cls, const cx<T>* sA, const cx<T>* sB, const int* d, const int* tp, int y,
                                    int n, cx<T> acc[16]) {
   if (cls == 0) {
-    lane_work_generic<T, 4>(sA, sB, d, y, n, acc);
+    const int nmc = (d[1] - 1) * 2 + (d[9] - 1);
+    if (nmc == 0) lane_full<T, 1, 1>(sA, sB, d, y, acc);
+    else if (nmc == 1) lane_full<T, 1, 2>(sA, sB, d, y, acc);
+    else if (nmc == 2) lane_full<T, 2, 1>(sA, sB, d, y, acc);
+    else lane_full<T, 2, 2>(sA, sB, d, y, acc);
   } else if (cls < 5) {
     split_maps<T, 4, 2, 2>(cls - 1, sA, sB, d, tp, y, acc);
   } else if (cls < 9) {
@@ -682,7 +750,17 @@ __global__ __launch_bounds__(kContractThreads) void k_contract(ContractArgs a) {
     cx<T> acc[16];
 #pragma unroll
     for (int o = 0; o < 16; ++o) acc[o] = cx<T>{0, 0};
-    if (p != 0xfff) {
+    if (cls == 0) {
+      // full projections: the whole wavefront runs the team code (it
+      // shuffles); idle lanes compute on product 0 and drop the result
+      const int y = (w >> 12) & 15;
+      const int* d = a.prod_desc + (long long)(pbase + (p != 0xfff ? p : 0)) * 20;
+      run_product<T>(0, slotA, slotB, d, tp, y, 1, acc);
+      if (p == 0xfff) {
+#pragma unroll
+        for (int o = 0; o < 16; ++o) acc[o] = cx<T>{0, 0};
+      }
+    } else if (p != 0xfff) {
       const int y = (w >> 12) & 15, n = (w >> 19) & 15;
       run_product<T>(cls, slotA, slotB, a.prod_desc + (long long)(pbase + p) * 20, tp, y, n, acc);
     }
@@ -700,24 +778,37 @@ __global__ __launch_bounds__(kContractThreads) void k_contract(ContractArgs a) {
   }
   __syncthreads();
 
+  // channel sums: 8 lanes per output (spin s of local channel cl), each
+  // summing every 8th contribution, then a fixed-order shuffle reduction
   cx<T>* Ft = reinterpret_cast<cx<T>*>(a.Ft);
-  for (int i = tid; i < nch * 16; i += kContractThreads) {
-    const int cl = i >> 4, s = i & 15;
-    const int a1 = (s >> 3) & 1, a2 = (s >> 2) & 1, a3 = (s >> 1) & 1, a4 = s & 1;
+  for (int i0 = 0; i0 < nch * 16 * 8; i0 += kContractThreads) {
+    const int i = i0 + tid;
+    const int o = i >> 3, sub = i & 7;
+    const int cl = o >> 4, s = o & 15;
     cx<T> v{0, 0};
-    for (int c = coff[cl]; c < coff[cl + 1]; ++c) {
-      const int w = cword[c];
-      const int p = w & 0xffff, rows2 = 16 / ((w >> 16) & 15);
-      const bool l3 = (w >> 20) & 1, l4 = (w >> 21) & 1;
-      const int r1 = (a1 * (l3 ? 2 : 1) + (l3 ? a3 : 0)) * (l4 ? 2 : 1) + (l4 ? a4 : 0);
-      const int r2 = (a2 * (l3 ? 1 : 2) + (l3 ? 0 : a3)) * (l4 ? 1 : 2) + (l4 ? 0 : a4);
-      const T cf = ccoef[c];
-      const cx<T> x = R[p * 16 + r1 * rows2 + r2];
-      v.re = fma(cf, x.re, v.re);
-      v.im = fma(cf, x.im, v.im);
+    if (cl < nch) {
+      const int a1 = (s >> 3) & 1, a2 = (s >> 2) & 1, a3 = (s >> 1) & 1, a4 = s & 1;
+      for (int c = coff[cl] + sub; c < coff[cl + 1]; c += 8) {
+        const int w = cword[c];
+        const int p = w & 0xffff, rows2 = 16 / ((w >> 16) & 15);
+        const bool l3 = (w >> 20) & 1, l4 = (w >> 21) & 1;
+        const int r1 = (a1 * (l3 ? 2 : 1) + (l3 ? a3 : 0)) * (l4 ? 2 : 1) + (l4 ? a4 : 0);
+        const int r2 = (a2 * (l3 ? 1 : 2) + (l3 ? 0 : a3)) * (l4 ? 1 : 2) + (l4 ? 0 : a4);
+        const T cf = ccoef[c];
+        const cx<T> x = R[p * 16 + r1 * rows2 + r2];
+        v.re = fma(cf, x.re, v.re);
+        v.im = fma(cf, x.im, v.im);
+      }
     }
-    const int ch = a.group_channels[gc0 + cl];
-    Ft[(((long long)ch * a.t_count + t) * 16 + s) * a.V + q] = v;
+#pragma unroll
+    for (int dd = 1; dd < 8; dd <<= 1) {
+      v.re += __shfl_xor(v.re, dd);
+      v.im += __shfl_xor(v.im, dd);
+    }
+    if (cl < nch && sub == 0) {
+      const int ch = a.group_channels[gc0 + cl];
+      Ft[(((long long)ch * a.t_count + t) * 16 + s) * a.V + q] = v;
+    }
   }
 }
 

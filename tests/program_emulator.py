@@ -140,6 +140,9 @@ def emulate_q(T, Nq_plus, Nq_minus, n_ch):
                 pairA = _shape(int(d[0]))["in0"] == 2
                 covered = []
                 acc = np.zeros(16, dtype=np.complex128)
+                if K == 1:  # the team shares one full-projection product
+                    assert sorted(((w >> 12) & 15) for w in team if w & 0xFFF != 0xFFF) == list(range(16))
+                    team = [w for w in team if (w >> 12) & 15 == 0]
                 for w in team:
                     if w & 0xFFF == 0xFFF:
                         continue
