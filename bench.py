@@ -39,7 +39,23 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="fp64_16c32", choices=sorted(CONFIGS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (the reference kernel for HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain device-to-device copy of 1 GiB, five times: the FETCH_SIZE and
+    WRITE_SIZE counters read on it give the scale between counter units and
+    bytes actually moved."""
+    import torch
+    n = 1 << 30
+    x = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 5}), flush=True)
 
 
 def program_work(plan):
@@ -54,13 +70,14 @@ def program_work(plan):
     return 4.0 * info["n_terms"], 8.0 * 16 * float(desc[:, 16].astype(np.int64).sum())
 
 
-def cpu_baseline():
-    """The oracle (FFT mode, all 52 channels) on one time slice of an 8^3
-    lattice with the same generator: a bounded sample of the per-site work."""
+def cpu_baseline(L):
+    """The oracle (DFT-correlation mode, all 52 channels) on one time slice of
+    the workload's lattice (for lattices above 16^3, a 16^3 slice) with the
+    same generator: a bounded sample of the per-site work."""
     import numpy as np
     import oracle
     from paper_1604_07983_amd import channels, runner
-    L = (8, 8, 8)
+    L = tuple(min(x, 16) for x in L)
     props = runner.host_props(L, 32, [5])
     S = [np.ascontiguousarray(p[0].reshape(-1, 12, 12)) for p in props]
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
@@ -70,9 +87,10 @@ def cpu_baseline():
     t = time.perf_counter()
     oracle.correlators(L, S, channels.r52(), mode="fft")
     dt = time.perf_counter() - t
-    return {"value": 512 * 52 / dt, "unit": "site-channels/s", "cores": cores, "kind": "oracle",
-            "sample": "oracle DFT-correlation mode, all 52 channels, one slice of an 8^3 lattice "
-                      "(512 sites), %.1f s" % dt}
+    V = L[0] * L[1] * L[2]
+    return {"value": V * 52 / dt, "unit": "site-channels/s", "cores": cores, "kind": "oracle",
+            "sample": "oracle DFT-correlation mode, all 52 channels, one slice of a %dx%dx%d lattice "
+                      "(%d sites), %.1f s" % (L[0], L[1], L[2], V, dt)}
 
 
 def main():
@@ -81,6 +99,9 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(a time-slice split would need no communication; see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import numpy as np
     import torch
     from paper_1604_07983_amd import binding, channels, runner
@@ -154,7 +175,7 @@ def main():
     r.close()
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(L)
     print(json.dumps(out), flush=True)
 
 

@@ -1,7 +1,9 @@
 // kernels.hip -- HIP kernels for gfx950 (MI355X) of the NBS four-point function.
 //
 //   k_nbb       normal baryon blocks, Eq. (5) / Sec. 3(i) Eq. (8)
-//   k_fft_pass  one axis of the in-house batched 3-D FFT (Eq. (6))
+//   k_fft_line  one axis of the in-house batched 3-D FFT (Eq. (6)), one line
+//               per thread in registers
+//   k_fft_pass  the same through LDS tiles, for the lengths k_fft_line lacks
 //   k_contract  effective blocks and their products, Sec. 3(ii)-(iii),
 //               Eqs. (9)-(10), driven by the compiled SoA program
 //   k_absmax / k_scale_exps / k_channel_scale   per-slice power-of-two
@@ -10,6 +12,7 @@
 
 #include "cx.hpp"
 #include "fft.hpp"
+#include "fft_reg.hpp"
 #include "kernels.hpp"
 
 namespace nbs {
@@ -193,6 +196,28 @@ __global__ __launch_bounds__(kThreads) void k_fft_pass(FftArgs a) {
     const cd v = src[(o * IB + ib) * ld + in_];
     out[g] = conv<Tout>(cd{v.re * f, v.im * f});
   }
+}
+
+// One axis of the batched transform with the whole line in registers: thread
+// (o, i) transforms the N elements o N inner + i + k inner, k < N.  Adjacent
+// threads take adjacent i, so every load and store of a wavefront is one
+// contiguous run; arithmetic in FP64 whatever the storage type.
+template <int N, int SIGN, typename Tin, typename Tout>
+__global__ __launch_bounds__(kThreads) void k_fft_line(FftArgs a) {
+  const long long gid = (long long)blockIdx.x * kThreads + threadIdx.x;
+  if (gid >= a.outer * a.inner) return;
+  const long long o = gid / a.inner, i = gid - o * a.inner;
+  const long long base = o * N * a.inner + i;
+  const cx<Tin>* in = reinterpret_cast<const cx<Tin>*>(a.in);
+  cd v[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = conv<double>(in[base + k * a.inner]);
+  fft_reg<N, SIGN>(v);
+  double f = a.gscale;
+  if (a.oscale) f *= a.oscale[o / a.oscale_div];
+  cx<Tout>* out = reinterpret_cast<cx<Tout>*>(a.out);
+#pragma unroll
+  for (int k = 0; k < N; ++k) out[base + k * a.inner] = conv<Tout>(cd{v[k].re * f, v[k].im * f});
 }
 
 // ---------------------------------------------------------------------------
@@ -848,6 +873,53 @@ hipError_t launch_nbb(int prec, const NbbArgs& a, hipStream_t st) {
   else
     hipLaunchKernelGGL((k_nbb<float, float>), grid, dim3(kThreads), 0, st, a);
   return hipGetLastError();
+}
+
+namespace {
+
+template <int N, int SIGN, typename Tin, typename Tout> hipError_t launch_line(const FftArgs& a, hipStream_t st) {
+  const long long threads = a.outer * a.inner;
+  dim3 grid((unsigned)((threads + kThreads - 1) / kThreads));
+  hipLaunchKernelGGL((k_fft_line<N, SIGN, Tin, Tout>), grid, dim3(kThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int N> hipError_t launch_line_kind(int kind, const FftArgs& a, hipStream_t st) {
+  if (kind == 0) return a.sign < 0 ? launch_line<N, -1, double, double>(a, st) : launch_line<N, 1, double, double>(a, st);
+  if (kind == 1) return launch_line<N, -1, float, float>(a, st);  // forward transform of the precision form
+  return launch_line<N, 1, float, double>(a, st);                  // first inverse pass of the precision form
+}
+
+}  // namespace
+
+bool fft_line_supported(int n) {
+  switch (n) {
+    case 2: case 3: case 4: case 5: case 6: case 8: case 10: case 12: case 16: case 20: case 24: case 32:
+    case 40: case 48:
+      return true;
+  }
+  return false;
+}
+
+hipError_t launch_fft_line(int kind, const FftArgs& a, hipStream_t st) {
+  if ((kind == 1 && a.sign > 0) || (kind == 2 && a.sign < 0)) return hipErrorInvalidValue;
+  switch (a.n) {
+    case 2: return launch_line_kind<2>(kind, a, st);
+    case 3: return launch_line_kind<3>(kind, a, st);
+    case 4: return launch_line_kind<4>(kind, a, st);
+    case 5: return launch_line_kind<5>(kind, a, st);
+    case 6: return launch_line_kind<6>(kind, a, st);
+    case 8: return launch_line_kind<8>(kind, a, st);
+    case 10: return launch_line_kind<10>(kind, a, st);
+    case 12: return launch_line_kind<12>(kind, a, st);
+    case 16: return launch_line_kind<16>(kind, a, st);
+    case 20: return launch_line_kind<20>(kind, a, st);
+    case 24: return launch_line_kind<24>(kind, a, st);
+    case 32: return launch_line_kind<32>(kind, a, st);
+    case 40: return launch_line_kind<40>(kind, a, st);
+    case 48: return launch_line_kind<48>(kind, a, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_fft_pass(int kind, const FftArgs& a, hipStream_t st) {

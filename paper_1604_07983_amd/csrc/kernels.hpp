@@ -56,6 +56,10 @@ hipError_t launch_channel_scale(const int* exps, const int* chan_nf, double* osc
 hipError_t launch_nbb(int prec, const NbbArgs& a, hipStream_t st);
 // kind: 0 = complex128 -> complex128, 1 = complex64 -> complex64, 2 = complex64 -> complex128
 hipError_t launch_fft_pass(int kind, const FftArgs& a, hipStream_t st);
+// Lengths with a register-resident kernel, and its launcher (kind as above;
+// the forward precision-form kind takes sign -1, the mixed kind sign +1).
+bool fft_line_supported(int n);
+hipError_t launch_fft_line(int kind, const FftArgs& a, hipStream_t st);
 size_t contract_lds_bytes(int prec, int max_gprod, int max_gcontrib, int max_gch);
 hipError_t launch_contract(int prec, const ContractArgs& a, hipStream_t st);
 

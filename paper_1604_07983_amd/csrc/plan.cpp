@@ -105,6 +105,8 @@ nbs_status hip_check(nbs_plan p, hipError_t e, const char* what) {
 // workgroup): 1024 keeps four workgroups resident per CU.
 constexpr int kFftTile = 1024;
 
+constexpr long long kLineMinInner = 16;
+
 int pick_ib(long long inner) {
   for (int ib : {16, 8, 4, 2})
     if (inner % ib == 0) return ib;
@@ -132,7 +134,12 @@ nbs_status fft3d(nbs_plan p, int kind_first, int kind_rest, const void* in, void
     a.gscale = ax == 2 ? gscale : 1.0;
     a.oscale = ax == 2 ? oscale : nullptr;
     a.oscale_div = oscale_div;
-    nbs_status s = hip_check(p, nbs::launch_fft_pass(ax == 0 ? kind_first : kind_rest, a, st), "fft pass");
+    // one line per thread in registers where the length has a kernel and the
+    // lines are wide enough apart for adjacent threads to read one run
+    const int kind = ax == 0 ? kind_first : kind_rest;
+    const bool line = nbs::fft_line_supported(a.n) && inner >= kLineMinInner;
+    nbs_status s = hip_check(p, line ? nbs::launch_fft_line(kind, a, st) : nbs::launch_fft_pass(kind, a, st),
+                             "fft pass");
     if (s != NBS_OK) return s;
   }
   return NBS_OK;
