@@ -176,6 +176,94 @@ void operator_slots(int op, int fl[3]) {
   for (int i = 0; i < 3; ++i) fl[i] = e.trip.empty() ? -1 : e.trip[0].f[i];
 }
 
+namespace {
+
+// Lane layout of one block product inside a task (see the lane word).
+struct TeamUnit {
+  int p;        // product (local index)
+  int cls;      // product class
+  int ky;       // lanes carrying the fixed index (16 term lanes for K = 1)
+  int kypad;    // ky rounded up to 4 or 16
+  int kz;       // values of the walked index
+  int zsl;      // the walked index is split over 2^zsl lane sets
+  double cell;  // estimated cost of one step of one lane
+};
+
+int team_lg(const TeamUnit& u) {
+  int lg = 0;
+  while ((1 << lg) < (u.kypad << u.zsl)) ++lg;
+  return lg;
+}
+
+// Packs the products into 64-lane tasks (teams of one size and one class per
+// task), assigns the tasks to the workgroup's wavefronts by longest
+// processing time first and, if lanes is given, emits them round-robin (wave
+// w takes tasks w, w + W, ...; empty slots are all-idle tasks).  Returns the
+// estimated time of the busiest wavefront.
+double pack_tasks(const std::vector<TeamUnit>& units, int waves, std::vector<int>* lanes) {
+  constexpr double kShuffleStep = 32.0;  // one team-reduction step, same units as cell
+  std::vector<int> ord(units.size());
+  for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int)i;
+  auto steps = [](const TeamUnit& u) { return (u.kz + (1 << u.zsl) - 1) >> u.zsl; };
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+    const int la = team_lg(units[a]), lb = team_lg(units[b]);
+    if (la != lb) return la > lb;
+    if (units[a].cls != units[b].cls) return units[a].cls < units[b].cls;
+    return steps(units[a]) * units[a].cell > steps(units[b]) * units[b].cell;
+  });
+  std::vector<std::vector<int>> tasks;
+  std::vector<double> tcost;
+  int cur_key = -1;
+  for (int i : ord) {
+    const TeamUnit& u = units[i];
+    const int lg = team_lg(u);
+    const int key = lg * 64 + u.cls;
+    const int idle = 0xfff | (lg << 16) | (u.cls << 26);
+    if (key != cur_key || tasks.back().size() == (size_t)kLanesPerTask) {
+      if (!tasks.empty())
+        while (tasks.back().size() < (size_t)kLanesPerTask) tasks.back().push_back(tasks.back().back() | 0xfff);
+      tasks.emplace_back();
+      tcost.push_back(0.0);
+      cur_key = key;
+    }
+    for (int zs = 0; zs < (1 << u.zsl); ++zs)
+      for (int y = 0; y < u.kypad; ++y) {
+        const bool busy = y < u.ky && zs < u.kz;
+        tasks.back().push_back(busy ? (u.p | (y << 12) | (lg << 16) | (zs << 19) | (u.zsl << 23) | (u.cls << 26))
+                                    : idle);
+      }
+    tcost.back() = std::max(tcost.back(), steps(u) * u.cell + lg * kShuffleStep);
+  }
+  if (!tasks.empty())
+    while (tasks.back().size() < (size_t)kLanesPerTask) tasks.back().push_back(tasks.back().back() | 0xfff);
+  std::vector<int> by_cost(tasks.size());
+  for (size_t i = 0; i < tasks.size(); ++i) by_cost[i] = (int)i;
+  std::stable_sort(by_cost.begin(), by_cost.end(), [&](int a, int b) { return tcost[a] > tcost[b]; });
+  std::vector<std::vector<int>> bins(waves);
+  std::vector<double> load(waves, 0.0);
+  for (int ti : by_cost) {
+    const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    bins[w].push_back(ti);
+    load[w] += tcost[ti];
+  }
+  if (lanes) {
+    size_t rounds = 0;
+    for (auto& b : bins) rounds = std::max(rounds, b.size());
+    for (size_t r = 0; r < rounds; ++r)
+      for (int w = 0; w < waves; ++w) {
+        if (r < bins[w].size()) {
+          const auto& tk = tasks[bins[w][r]];
+          lanes->insert(lanes->end(), tk.begin(), tk.end());
+        } else {
+          for (int l = 0; l < kLanesPerTask; ++l) lanes->push_back(0xfff | (kClassIdle << 26));
+        }
+      }
+  }
+  return *std::max_element(load.begin(), load.end());
+}
+
+}  // namespace
+
 std::string compile_channels(const std::vector<ChannelSpec>& chans, const CompileOptions& opt,
                              Compiled* out) {
   Compiled C;
@@ -295,58 +383,46 @@ std::string compile_channels(const std::vector<ChannelSpec>& chans, const Compil
         P.prod_desc.insert(P.prod_desc.end(), d, d + kProdInts);
         C.product_k += s1.K();
       }
-      // lanes: every task holds teams of one size and one product class only,
-      // so the team reduction and the kernel's class dispatch are uniform
-      // across its wavefront; idle lanes carry the team size and class too
-      std::vector<std::vector<int>> tasks;
-      std::vector<double> tcost;
-      int cur_key = -1;
+      // lanes: one team per product; the walked index may be split over
+      // 2^zsl lane sets (a larger team, fewer steps per lane).  The split is
+      // chosen per group by trying targets for the steps per lane and keeping
+      // the one with the smallest estimated workgroup time.
+      std::vector<TeamUnit> units;
       for (int p : order_p) {
-        const int tl = team(p), ky = ky_of(p), kz = kz_of(p), cl = cls_of(p);
-        int lg = 0;
-        while ((1 << lg) < tl) ++lg;
-        const int key = lg * 64 + cl;
-        const int idle = 0xfff | (lg << 16) | (cl << 23);
-        if (key != cur_key || tasks.back().size() == (size_t)kLanesPerTask) {
-          if (!tasks.empty())
-            while (tasks.back().size() < (size_t)kLanesPerTask) tasks.back().push_back(tasks.back().back() | 0xfff);
-          tasks.emplace_back();
-          tcost.push_back(0.0);
-          cur_key = key;
+        const Shape s1 = shape_of(prods[p].first.mask), s2 = shape_of(prods[p].second.mask);
+        TeamUnit u{};
+        u.p = local[p];
+        u.cls = cls_of(p);
+        u.ky = ky_of(p);
+        u.kypad = team(p);
+        u.kz = kz_of(p);
+        u.zsl = 0;
+        const int nm1 = (int)prods[p].first.maps.size(), nm2 = (int)prods[p].second.maps.size();
+        if (s1.K() == 1) {
+          u.cell = 8.0 * (nm1 + nm2) + 64.0 + 32.0;
+        } else {
+          const int lone1 = s1.kA == 2 ? s1.loneA : s1.loneB, lone2 = s1.kA == 2 ? s2.loneB : s2.loneA;
+          const int np1 = lone1 == 2 ? 8 : 2, np2 = lone2 == 2 ? 8 : 2;
+          u.cell = (double)s1.rows() * np1 * nm1 + (double)(16 / s1.rows()) * np2 * nm2 + 32.0;
         }
-        for (int u = 0; u < tl; ++u)
-          tasks.back().push_back(u < ky ? (local[p] | (u << 12) | (lg << 16) | (kz << 19) | (cl << 23)) : idle);
-        const Shape s1 = shape_of(prods[p].first.mask);
-        const double it = (double)kz * (s1.rows() * 2.0 * prods[p].first.maps.size() +
-                                        (16 / s1.rows()) * 2.0 * prods[p].second.maps.size() + 32.0);
-        tcost.back() = std::max(tcost.back(), it);
+        units.push_back(u);
       }
-      if (!tasks.empty())
-        while (tasks.back().size() < (size_t)kLanesPerTask) tasks.back().push_back(tasks.back().back() | 0xfff);
-      // longest-processing-time assignment of tasks to the workgroup's
-      // wavefronts, emitted round-robin (wave w takes tasks w, w + W, ...)
-      std::vector<int> by_cost(tasks.size());
-      for (size_t i = 0; i < tasks.size(); ++i) by_cost[i] = (int)i;
-      std::stable_sort(by_cost.begin(), by_cost.end(), [&](int a, int b) { return tcost[a] > tcost[b]; });
-      std::vector<std::vector<int>> bins(kWavesPerGroup);
-      std::vector<double> load(kWavesPerGroup, 0.0);
-      for (int ti : by_cost) {
-        const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        bins[w].push_back(ti);
-        load[w] += tcost[ti];
+      std::vector<TeamUnit> best = units;
+      double best_t = pack_tasks(units, opt.waves, nullptr);
+      for (int target : {6, 4, 3, 2, 1}) {
+        std::vector<TeamUnit> trial = units;
+        for (auto& u : trial) {
+          if (u.cls == kClassFull) continue;
+          while ((u.kz + (1 << u.zsl) - 1) >> u.zsl > target && (u.kypad << (u.zsl + 1)) <= kLanesPerTask) ++u.zsl;
+        }
+        const double t = pack_tasks(trial, opt.waves, nullptr);
+        if (t < best_t) {
+          best_t = t;
+          best = trial;
+        }
       }
-      size_t rounds = 0;
-      for (auto& b : bins) rounds = std::max(rounds, b.size());
       std::vector<int> lanes;
-      for (size_t r = 0; r < rounds; ++r)
-        for (int w = 0; w < kWavesPerGroup; ++w) {
-          if (r < bins[w].size()) {
-            const auto& tk = tasks[bins[w][r]];
-            lanes.insert(lanes.end(), tk.begin(), tk.end());
-          } else {
-            for (int l = 0; l < kLanesPerTask; ++l) lanes.push_back(0xfff);
-          }
-        }
+      pack_tasks(best, opt.waves, &lanes);
       P.task_lanes.insert(P.task_lanes.end(), lanes.begin(), lanes.end());
       // channel contributions
       for (int c : gch) {

@@ -61,14 +61,15 @@ struct DiagramInfo {
 // i is contracted with source quark m_i.
 constexpr int kProdInts = 20;
 // Lane word of a wavefront task: product (12 bits) | y << 12 (4 bits) |
-// log2(team) << 16 (3 bits) | n << 19 (4 bits) | class << 23 (5 bits);
-// product 0xfff = idle lane.  For K > 1, y is the lane's fixed shared index
-// on the side where block 1 holds a quark pair and n the count of the other
-// side's index; for K = 1, y is the lane's share of the source terms and n = 1.  All teams of one task have the
-// same size and class.  Products of two full projections (K = 1) take a
-// 16-lane team whose lanes y = 0..15 share the 24 source-tensor terms.
+// log2(team) << 16 (3 bits) | z0 << 19 (4 bits) | zsl << 23 (3 bits) |
+// class << 26 (5 bits); product 0xfff = idle lane.  For K > 1, y is the
+// lane's fixed shared index on the side where block 1 holds a quark pair and
+// the lane walks the other side's index z = z0, z0 + 2^zsl, ... (the team is
+// 2^zsl sets of 4 or 16 lanes, lane y + set size * z0).  For K = 1 the team
+// has 16 lanes whose y = 0..15 share the 24 source-tensor terms.  All teams
+// of one task have the same size and class; a task of class kClassIdle is
+// empty.
 constexpr int kLanesPerTask = 64;
-constexpr int kWavesPerGroup = 8;  // wavefronts of a contraction workgroup
 
 // Product classes (kernel template dispatch): kClassFull = two full
 // projections (K = 1); 1 + 4 b + 2 (nmaps1 - 1) + (nmaps2 - 1) for the split
@@ -76,6 +77,7 @@ constexpr int kWavesPerGroup = 8;  // wavefronts of a contraction workgroup
 // 2 + 8 (K = 36); b = 2: 2 x 8 rows, 8 + 2 (K = 36); b = 3: 4 x 4 rows,
 // 8 + 8 (K = 9); kClassSplitAny = any other split product.
 constexpr int kClassFull = 0;
+constexpr int kClassIdle = 30;
 constexpr int kClassSplitAny = 31;
 int product_class(int K, int rows1, int lone1, int lone2, int nm1, int nm2);
 
@@ -107,6 +109,7 @@ struct Program {
 
 struct CompileOptions {
   int max_group_products = 88;  // LDS result buffer bound per group
+  int waves = 8;                // wavefronts of a contraction workgroup
 };
 
 struct Compiled {

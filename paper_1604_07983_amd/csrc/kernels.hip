@@ -150,7 +150,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_pass(FftArgs a) {
   extern __shared__ cd smem_fft[];
   const int n = a.n, IB = a.IB, OB = a.OB, ld = n + 1;
   const long long n_itiles = a.inner / IB;
-  const long long tile = blockIdx.x;
+  const long long tile = a.unit0 + blockIdx.x;
   const long long o0 = (tile / n_itiles) * OB, i0 = (tile % n_itiles) * IB;
   const int ob = (int)((a.outer - o0) < OB ? (a.outer - o0) : OB);
   const int lines = ob * IB;
@@ -204,7 +204,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_pass(FftArgs a) {
 // contiguous run; arithmetic in FP64 whatever the storage type.
 template <int N, int SIGN, typename Tin, typename Tout>
 __global__ __launch_bounds__(kThreads) void k_fft_line(FftArgs a) {
-  const long long gid = (long long)blockIdx.x * kThreads + threadIdx.x;
+  const long long gid = a.unit0 + (long long)blockIdx.x * kThreads + threadIdx.x;
   if (gid >= a.outer * a.inner) return;
   const long long o = gid / a.inner, i = gid - o * a.inner;
   const long long base = o * N * a.inner + i;
@@ -439,7 +439,7 @@ __device__ inline void build_pair_table(int* tp, int tid, int nthreads) {
 // and block 2's pair terms come from the universal table.
 template <typename T, int R1>
 __device__ inline void lane_work_split(const cx<T>* slotA, const cx<T>* slotB, const int* d, const int* tp,
-                                       int y, cx<T> acc[16]) {
+                                       int y, int z0, int zstep, cx<T> acc[16]) {
   constexpr int R2 = 16 / R1;
   const BlkShape s1 = decode_shape(d[0]), s2 = decode_shape(d[8]);
   const bool pairA = s1.kA == 2;                    // block 1's pair is in source baryon A
@@ -480,7 +480,7 @@ __device__ inline void lane_work_split(const cx<T>* slotA, const cx<T>* slotB, c
     st2p[m] = quark_stride(mp2[m], p2);
     st2q[m] = quark_stride(mp2[m], q2);
   }
-  for (int z = 0; z < Kz; ++z) {
+  for (int z = z0; z < Kz; z += zstep) {
     cx<T> e1[R1], e2[R2];
 #pragma unroll
     for (int r = 0; r < R1; ++r) e1[r] = cx<T>{0, 0};
@@ -517,7 +517,7 @@ __device__ inline void lane_work_split(const cx<T>* slotA, const cx<T>* slotB, c
 // counts are compile-time, so the loop over z is straight-line code.
 template <typename T, int R1, int NP1, int NP2, int NM1, int NM2>
 __device__ inline void lane_split_fixed(const cx<T>* slotA, const cx<T>* slotB, const int* d, const int* tp,
-                                        int y, cx<T> acc[16]) {
+                                        int y, int z0, int zstep, cx<T> acc[16]) {
   constexpr int R2 = 16 / R1;
   constexpr int KZ = NP2 == 8 ? 3 : 12;
   const BlkShape s1 = decode_shape(d[0]), s2 = decode_shape(d[8]);
@@ -564,7 +564,7 @@ __device__ inline void lane_split_fixed(const cx<T>* slotA, const cx<T>* slotB, 
   }
   const int tz0 = pair_index(lone2, 0, 0), tzs = NP2;  // table row of z is tz0 + z * NP2
 #pragma unroll 1
-  for (int z = 0; z < KZ; ++z) {
+  for (int z = z0; z < KZ; z += zstep) {
     cx<T> e1[R1], e2[R2];
 #pragma unroll
     for (int r = 0; r < R1; ++r) e1[r] = cx<T>{0, 0};
@@ -659,18 +659,18 @@ __device__ inline void lane_full(const cx<T>* slotA, const cx<T>* slotB, const i
 // Dispatch on the (wavefront-uniform) product class.
 template <typename T, int R1, int NP1, int NP2>
 __device__ inline void split_maps(int nmc, const cx<T>* sA, const cx<T>* sB, const int* d, const int* tp, int y,
-                                  cx<T> acc[16]) {
+                                  int z0, int zs, cx<T> acc[16]) {
   switch (nmc) {
-    case 0: lane_split_fixed<T, R1, NP1, NP2, 1, 1>(sA, sB, d, tp, y, acc); break;
-    case 1: lane_split_fixed<T, R1, NP1, NP2, 1, 2>(sA, sB, d, tp, y, acc); break;
-    case 2: lane_split_fixed<T, R1, NP1, NP2, 2, 1>(sA, sB, d, tp, y, acc); break;
-    default: lane_split_fixed<T, R1, NP1, NP2, 2, 2>(sA, sB, d, tp, y, acc); break;
+    case 0: lane_split_fixed<T, R1, NP1, NP2, 1, 1>(sA, sB, d, tp, y, z0, zs, acc); break;
+    case 1: lane_split_fixed<T, R1, NP1, NP2, 1, 2>(sA, sB, d, tp, y, z0, zs, acc); break;
+    case 2: lane_split_fixed<T, R1, NP1, NP2, 2, 1>(sA, sB, d, tp, y, z0, zs, acc); break;
+    default: lane_split_fixed<T, R1, NP1, NP2, 2, 2>(sA, sB, d, tp, y, z0, zs, acc); break;
   }
 }
 
 template <typename T>
 __device__ inline void run_product(int cls, const cx<T>* sA, const cx<T>* sB, const int* d, const int* tp, int y,
-                                   int n, cx<T> acc[16]) {
+                                   int z0, int zs, cx<T> acc[16]) {
   if (cls == 0) {
     const int nmc = (d[1] - 1) * 2 + (d[9] - 1);
     if (nmc == 0) lane_full<T, 1, 1>(sA, sB, d, y, acc);
@@ -678,21 +678,21 @@ __device__ inline void run_product(int cls, const cx<T>* sA, const cx<T>* sB, co
     else if (nmc == 2) lane_full<T, 2, 1>(sA, sB, d, y, acc);
     else lane_full<T, 2, 2>(sA, sB, d, y, acc);
   } else if (cls < 5) {
-    split_maps<T, 4, 2, 2>(cls - 1, sA, sB, d, tp, y, acc);
+    split_maps<T, 4, 2, 2>(cls - 1, sA, sB, d, tp, y, z0, zs, acc);
   } else if (cls < 9) {
-    split_maps<T, 8, 2, 8>(cls - 5, sA, sB, d, tp, y, acc);
+    split_maps<T, 8, 2, 8>(cls - 5, sA, sB, d, tp, y, z0, zs, acc);
   } else if (cls < 13) {
-    split_maps<T, 2, 8, 2>(cls - 9, sA, sB, d, tp, y, acc);
+    split_maps<T, 2, 8, 2>(cls - 9, sA, sB, d, tp, y, z0, zs, acc);
   } else if (cls < 17) {
-    split_maps<T, 4, 8, 8>(cls - 13, sA, sB, d, tp, y, acc);
+    split_maps<T, 4, 8, 8>(cls - 13, sA, sB, d, tp, y, z0, zs, acc);
   } else {
     const int rows1 = d[18];
     if (rows1 == 4)
-      lane_work_split<T, 4>(sA, sB, d, tp, y, acc);
+      lane_work_split<T, 4>(sA, sB, d, tp, y, z0, zs, acc);
     else if (rows1 == 2)
-      lane_work_split<T, 2>(sA, sB, d, tp, y, acc);
+      lane_work_split<T, 2>(sA, sB, d, tp, y, z0, zs, acc);
     else
-      lane_work_split<T, 8>(sA, sB, d, tp, y, acc);
+      lane_work_split<T, 8>(sA, sB, d, tp, y, z0, zs, acc);
   }
 }
 
@@ -703,10 +703,15 @@ size_t contract_lds_bytes(int prec, int max_gprod, int max_gcontrib, int max_gch
          sizeof(int) * (kPairTable + max_gcontrib + max_gch + 1);
 }
 
-constexpr int kContractThreads = 512;
+// NT threads per workgroup: 512 for FP64 (the two staged blocks take most of
+// the LDS, one workgroup per CU), 256 for the precision form (two workgroups
+// per CU, so one stages while the other computes).  The channel compiler
+// balances each group's tasks over NT / 64 wavefronts.
+constexpr int kIdleClass = 30;
 
-template <typename T>
-__global__ __launch_bounds__(kContractThreads) void k_contract(ContractArgs a) {
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
+  constexpr int kContractThreads = NT;
   extern __shared__ char smem_raw[];
   cx<T>* slotA = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* slotB = slotA + kLdsBlock;
@@ -716,10 +721,13 @@ __global__ __launch_bounds__(kContractThreads) void k_contract(ContractArgs a) {
   int* cword = tp + kPairTable;
   int* coff = cword + a.max_gcontrib;
 
-  const long long nb8 = (a.n_blocks + 7) / 8 * 8;
+  // consecutive logical workgroups on one XCD (hardware deals workgroups
+  // round-robin over the 8 XCDs)
+  const long long nb8 = (a.n_chunk + 7) / 8 * 8;
   const long long b = blockIdx.x;
-  const long long logical = (b % 8) * (nb8 / 8) + b / 8;
-  if (logical >= a.n_blocks) return;
+  const long long local = (b % 8) * (nb8 / 8) + b / 8;
+  if (local >= a.n_chunk) return;
+  const long long logical = a.block0 + local;
   const int g = (int)(logical % a.n_groups);
   const long long qt = logical / a.n_groups;
   const int t = (int)(qt / a.V), q = (int)(qt % a.V);
@@ -771,7 +779,8 @@ __global__ __launch_bounds__(kContractThreads) void k_contract(ContractArgs a) {
   for (int task = a.group_task[g] + wave; task < a.group_task[g + 1]; task += kContractThreads / 64) {
     const int w = a.task_lanes[(long long)task * 64 + lane];
     const int p = w & 0xfff, lg = (w >> 16) & 7;
-    const int cls = __builtin_amdgcn_readfirstlane((w >> 23) & 31);
+    const int cls = __builtin_amdgcn_readfirstlane((w >> 26) & 31);
+    if (cls == kIdleClass) continue;
     cx<T> acc[16];
 #pragma unroll
     for (int o = 0; o < 16; ++o) acc[o] = cx<T>{0, 0};
@@ -780,14 +789,14 @@ __global__ __launch_bounds__(kContractThreads) void k_contract(ContractArgs a) {
       // shuffles); idle lanes compute on product 0 and drop the result
       const int y = (w >> 12) & 15;
       const int* d = a.prod_desc + (long long)(pbase + (p != 0xfff ? p : 0)) * 20;
-      run_product<T>(0, slotA, slotB, d, tp, y, 1, acc);
+      run_product<T>(0, slotA, slotB, d, tp, y, 0, 1, acc);
       if (p == 0xfff) {
 #pragma unroll
         for (int o = 0; o < 16; ++o) acc[o] = cx<T>{0, 0};
       }
     } else if (p != 0xfff) {
-      const int y = (w >> 12) & 15, n = (w >> 19) & 15;
-      run_product<T>(cls, slotA, slotB, a.prod_desc + (long long)(pbase + p) * 20, tp, y, n, acc);
+      const int y = (w >> 12) & 15, z0 = (w >> 19) & 15, zs = 1 << ((w >> 23) & 7);
+      run_product<T>(cls, slotA, slotB, a.prod_desc + (long long)(pbase + p) * 20, tp, y, z0, zs, acc);
     }
     for (int dd = 1; dd < (1 << lg); dd <<= 1) {
 #pragma unroll
@@ -878,10 +887,17 @@ hipError_t launch_nbb(int prec, const NbbArgs& a, hipStream_t st) {
 namespace {
 
 template <int N, int SIGN, typename Tin, typename Tout> hipError_t launch_line(const FftArgs& a, hipStream_t st) {
-  const long long threads = a.outer * a.inner;
-  dim3 grid((unsigned)((threads + kThreads - 1) / kThreads));
-  hipLaunchKernelGGL((k_fft_line<N, SIGN, Tin, Tout>), grid, dim3(kThreads), 0, st, a);
-  return hipGetLastError();
+  const long long lines = a.outer * a.inner;
+  for (long long l0 = 0; l0 < lines; l0 += kMaxLaunchItems) {
+    FftArgs c = a;
+    c.unit0 = l0;
+    const long long n = lines - l0 < kMaxLaunchItems ? lines - l0 : kMaxLaunchItems;
+    hipLaunchKernelGGL((k_fft_line<N, SIGN, Tin, Tout>), dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads),
+                       0, st, c);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 template <int N> hipError_t launch_line_kind(int kind, const FftArgs& a, hipStream_t st) {
@@ -925,7 +941,6 @@ hipError_t launch_fft_line(int kind, const FftArgs& a, hipStream_t st) {
 hipError_t launch_fft_pass(int kind, const FftArgs& a, hipStream_t st) {
   const long long tiles = ((a.outer + a.OB - 1) / a.OB) * (a.inner / a.IB);
   const size_t lds = sizeof(cd) * (a.n + 2 * (size_t)a.OB * a.IB * (a.n + 1));
-  dim3 grid((unsigned)tiles);
   static bool attr_set = false;
   if (!attr_set) {
     const int mx = 160 * 1024;
@@ -934,30 +949,46 @@ hipError_t launch_fft_pass(int kind, const FftArgs& a, hipStream_t st) {
     (void)hipFuncSetAttribute((const void*)k_fft_pass<float, double>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
     attr_set = true;
   }
-  if (kind == 0)
-    hipLaunchKernelGGL((k_fft_pass<double, double>), grid, dim3(kThreads), lds, st, a);
-  else if (kind == 1)
-    hipLaunchKernelGGL((k_fft_pass<float, float>), grid, dim3(kThreads), lds, st, a);
-  else
-    hipLaunchKernelGGL((k_fft_pass<float, double>), grid, dim3(kThreads), lds, st, a);
-  return hipGetLastError();
+  const long long chunk = kMaxLaunchItems / kThreads;
+  for (long long t0 = 0; t0 < tiles; t0 += chunk) {
+    FftArgs c = a;
+    c.unit0 = t0;
+    dim3 grid((unsigned)(tiles - t0 < chunk ? tiles - t0 : chunk));
+    if (kind == 0)
+      hipLaunchKernelGGL((k_fft_pass<double, double>), grid, dim3(kThreads), lds, st, c);
+    else if (kind == 1)
+      hipLaunchKernelGGL((k_fft_pass<float, float>), grid, dim3(kThreads), lds, st, c);
+    else
+      hipLaunchKernelGGL((k_fft_pass<float, double>), grid, dim3(kThreads), lds, st, c);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
+
+int contract_waves(int prec) { return prec == 0 ? 8 : 4; }
+
+namespace {
+template <typename T, int NT> hipError_t launch_contract_t(const ContractArgs& a, size_t lds, hipStream_t st) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_contract<T, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const long long chunk = kMaxLaunchItems / NT / 8 * 8;
+  for (long long b0 = 0; b0 < a.n_blocks; b0 += chunk) {
+    ContractArgs c = a;
+    c.block0 = b0;
+    c.n_chunk = a.n_blocks - b0 < chunk ? a.n_blocks - b0 : chunk;
+    const long long nb8 = (c.n_chunk + 7) / 8 * 8;
+    hipLaunchKernelGGL((k_contract<T, NT>), dim3((unsigned)nb8), dim3(NT), lds, st, c);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+}  // namespace
 
 hipError_t launch_contract(int prec, const ContractArgs& a, hipStream_t st) {
   const size_t lds = contract_lds_bytes(prec, a.max_gprod, a.max_gcontrib, a.max_gch);
-  const long long nb8 = (a.n_blocks + 7) / 8 * 8;
-  dim3 grid((unsigned)nb8);
-  hipError_t e;
-  if (prec == 0) {
-    e = hipFuncSetAttribute((const void*)k_contract<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_contract<double>, grid, dim3(kContractThreads), lds, st, a);
-  } else {
-    e = hipFuncSetAttribute((const void*)k_contract<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_contract<float>, grid, dim3(kContractThreads), lds, st, a);
-  }
-  return hipGetLastError();
+  if (a.waves != contract_waves(prec)) return hipErrorInvalidValue;
+  return prec == 0 ? launch_contract_t<double, 512>(a, lds, st) : launch_contract_t<float, 256>(a, lds, st);
 }
 
 }  // namespace nbs

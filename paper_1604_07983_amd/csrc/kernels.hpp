@@ -33,7 +33,13 @@ struct FftArgs {
   const double* oscale;   // optional per-outer-group factor oscale[o / oscale_div]
   long long oscale_div;
   double gscale;          // global factor
+  long long unit0;        // first tile (LDS kernel) or line (register kernel) of this launch
 };
+
+// Workgroups per launch stay below this bound, so that workgroups x threads
+// stays below the 2^32 work-items a dispatch can address; larger grids are
+// issued as several launches with an offset.
+constexpr long long kMaxLaunchItems = 1LL << 31;
 
 // Effective blocks and their products (Eqs. (9)-(10)) per (group, q, slice).
 struct ContractArgs {
@@ -45,6 +51,8 @@ struct ContractArgs {
   const int *ch_contrib, *contrib_prod, *prod_desc, *task_lanes;
   const double* contrib_coef;
   int max_gprod, max_gcontrib, max_gch;
+  int waves;  // wavefronts the compiled tasks are balanced over
+  long long block0, n_chunk;  // logical workgroups [block0, block0 + n_chunk) in this launch
 };
 
 // prec: 0 = FP64 form, 1 = precision form (complex64 storage, FP32 compute).
@@ -61,6 +69,9 @@ hipError_t launch_fft_pass(int kind, const FftArgs& a, hipStream_t st);
 bool fft_line_supported(int n);
 hipError_t launch_fft_line(int kind, const FftArgs& a, hipStream_t st);
 size_t contract_lds_bytes(int prec, int max_gprod, int max_gcontrib, int max_gch);
+// Wavefronts per contraction workgroup for a precision (the channel compiler
+// balances each group's tasks over this many).
+int contract_waves(int prec);
 hipError_t launch_contract(int prec, const ContractArgs& a, hipStream_t st);
 
 }  // namespace nbs

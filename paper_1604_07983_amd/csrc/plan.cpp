@@ -191,6 +191,7 @@ nbs_status nbs_plan_create(nbs_plan* out, const nbs_geometry* g, int32_t n_geom,
       specs[c].src[k] = ch[c].src[k];
     }
   }
+  p->opt.waves = nbs::contract_waves(prec == NBS_FP64 ? 0 : 1);
   std::string msg = nbs::compile_channels(specs, p->opt, &p->comp);
   if (!msg.empty()) {
     delete p;
@@ -321,6 +322,7 @@ nbs_status nbs_plan_create(nbs_plan* out, const nbs_geometry* g, int32_t n_geom,
   c.max_gprod = std::max(1, P.max_group_products);
   c.max_gcontrib = std::max(1, P.max_group_contrib);
   c.max_gch = std::max(1, P.max_group_channels);
+  c.waves = p->opt.waves;
   if (nbs::contract_lds_bytes(prec, c.max_gprod, c.max_gcontrib, c.max_gch) > 160 * 1024) {
     free_all(p);
     delete p;

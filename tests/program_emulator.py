@@ -16,6 +16,7 @@ NAMES = ("op_code", "op_nterm", "op_term_trip", "op_term_perm", "op_term_w", "gr
          "group_prod", "group_task", "group_ch", "group_channels", "ch_contrib", "contrib_prod",
          "contrib_coef", "prod_desc", "task_lanes")
 PROD_INTS = 20
+IDLE_CLASS = 30
 
 EPS = {(0, 1, 2): 1, (1, 2, 0): 1, (2, 0, 1): 1, (0, 2, 1): -1, (2, 1, 0): -1, (1, 0, 2): -1}
 CG5 = {(0, 1): 1, (1, 0): -1, (2, 3): 1, (3, 2): -1}
@@ -118,7 +119,11 @@ def emulate_q(T, Nq_plus, Nq_minus, n_ch):
         for task in range(T["group_task"][g], T["group_task"][g + 1]):
             words = lanes[task]
             lgs = {(int(w) >> 16) & 7 for w in words if int(w) & 0xFFF != 0xFFF}
-            cls = {(int(w) >> 23) & 31 for w in words if int(w) & 0xFFF != 0xFFF}
+            cls = {(int(w) >> 26) & 31 for w in words if int(w) & 0xFFF != 0xFFF}
+            if ((int(words[0]) >> 26) & 31) == IDLE_CLASS:
+                assert not lgs, "an idle task holds work"
+                continue
+            assert {(int(w) >> 16) & 7 for w in words} == lgs or not lgs, "idle lanes disagree on the team size"
             if not lgs:
                 continue
             assert len(lgs) == 1, "a task mixes team sizes"
@@ -146,8 +151,9 @@ def emulate_q(T, Nq_plus, Nq_minus, n_ch):
                 for w in team:
                     if w & 0xFFF == 0xFFF:
                         continue
-                    y, n = (w >> 12) & 15, (w >> 19) & 15
-                    for z in range(n):
+                    y, z0, zs = (w >> 12) & 15, (w >> 19) & 15, 1 << ((w >> 23) & 7)
+                    kz = 1 if K == 1 else (KB if pairA else K // KB)
+                    for z in range(z0, kz, zs):
                         if K == 1:
                             xA = xB = 0
                         else:
