@@ -29,6 +29,21 @@ CONFIGS = {
                    "window of 16 slices"),
 }
 
+# The batching form: 24^3 x 48, 32^3 x 64 and 40^3 x 40 lattices, 8 source
+# slices each (t0_k = k T / 8, seeds per source), the sink slice t0_k + 4,
+# all 24 geometries in one plan and one captured graph, decay 0.45.
+BATCH_LATTICES = (((24, 24, 24), 48), ((32, 32, 32), 64), ((40, 40, 40), 40))
+
+
+def batch_geoms():
+    out = []
+    for L, T in BATCH_LATTICES:
+        for k in range(8):
+            t0 = k * T // 8
+            out.append(dict(L=L, T=T, t0=t0, t_begin=(t0 + 4) % T, t_count=1))
+    return out
+
+
 PEAK = {"hbm": 8.0e12, "fp64": 78.6e12, "fp32_vector": 157.3e12}
 
 
@@ -37,7 +52,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="fp64_16c32", choices=sorted(CONFIGS))
+    ap.add_argument("--config", default="fp64_16c32", choices=sorted(CONFIGS) + ["batch_c4"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (the reference kernel for HBM byte counters)")
@@ -93,6 +108,69 @@ def cpu_baseline(L):
                       "(%d sites), %.1f s" % (L[0], L[1], L[2], V, dt)}
 
 
+def bench_batch(args):
+    """The batching form: one step = one launch of the captured graph over
+    all 24 geometries (build, contraction in one launch, inverse transforms)."""
+    import numpy as np
+    import torch
+    from paper_1604_07983_amd import binding, channels, runner
+    geoms = batch_geoms()
+    chans = channels.r52()
+    decay = {"u": 0.45, "d": 0.45, "s": 0.45}
+    print("[bench] generating propagators for %d geometries" % len(geoms), file=sys.stderr, flush=True)
+    hprops = runner.host_props_many(geoms, decay=decay, dtype=np.complex64, workers=8)
+    dprops = [runner.device_props(p, binding.NBS_FP32_MFMA) for p in hprops]
+    del hprops
+    br = runner.BatchRunner(geoms, chans, prec=binding.NBS_FP32_MFMA)
+    print("[bench] autotune", file=sys.stderr, flush=True)
+    tune = br.autotune(dprops)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        br.run_graph(dprops)
+    torch.cuda.synchronize()
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        br.run_graph(dprops)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall * 1e3 / args.steps
+    # the contraction alone, timed on the same stream, for the roofline
+    ec = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ec[0].record(stream)
+    for _ in range(args.steps):
+        br.contract()
+    ec[1].record(stream)
+    torch.cuda.synchronize()
+    contract_ms = ec[0].elapsed_time(ec[1]) / args.steps
+    sites = sum(g["L"][0] * g["L"][1] * g["L"][2] * g["t_count"] for g in geoms)
+    ebb_f, meb_f = program_work(br.plan)
+    flops = (ebb_f + meb_f) * sites
+    roof = {"bound": "alu", "achieved": flops / (contract_ms * 1e-3) / 1e12, "peak": PEAK["fp32_vector"] / 1e12,
+            "unit": "TFLOP/s", "traffic": None, "kernel": "k_contract (effective blocks + products, all geometries)"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    out = {
+        "metric": "NBS site-channels/sec + GFLOP/s, FP32-MFMA batched vs FP64 plain at stated rel err",
+        "value": sites * len(chans) / (ms_step * 1e-3), "unit": "site-channels/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batching form: 24^3x48, 32^3x64, 40^3x40 lattices x 8 source slices, one sink "
+                               "slice each, 52 channels, complex64, decay 0.45, one captured graph",
+                   "geometries": len(geoms), "channels": len(chans), "sites_per_step": sites, "tuning": tune},
+        "stage_ms": {"graph_step": ms_step, "contract_channels": contract_ms},
+        "roofline": roof,
+    }
+    br.close()
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline((16, 16, 16))
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -101,6 +179,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.config == "batch_c4":
+        bench_batch(args)
         return
     import numpy as np
     import torch

@@ -87,7 +87,10 @@ typedef struct nbs_plan_s* nbs_plan;
 
 /* Compile the channel table (Sec. 3(ii)-(iii): diagram classification into
  * structure-of-arrays tables, done once on the host) and allocate device
- * workspace.  g: n_geom geometries (this build: n_geom == 1).
+ * workspace.  g: n_geom geometries, 1 <= n_geom <= 32 (NBS_ERR_UNSUPPORTED
+ * above).  Geometries may differ in every field (lattice extents, T, source
+ * slice, window); each gets its own workspace, and the channel contraction
+ * covers all of them in one launch (the batching form).
  * device >= 0: the HIP device to use; device == -1: host-only plan that
  * holds the compiled tables for inspection (nbs_plan_info, nbs_plan_diagrams,
  * nbs_plan_table, nbs_plan_params)
@@ -119,6 +122,30 @@ nbs_status nbs_contract_channels(nbs_plan plan, void* stream);
  * [n_ch][t_count][16][Lz][Ly][Lx], owned by the caller.  Must follow
  * nbs_contract_channels. */
 nbs_status nbs_relative_sum(nbs_plan plan, void* const* F_out, void* stream);
+
+/* All three stages for every geometry as one captured HIP graph.  The first
+ * call (and any call whose pointers differ from the captured ones) records
+ * build, contract and relative sum into a graph on a plan-owned stream and
+ * instantiates it; every call then launches the graph on `stream`.
+ * Arguments as for the three stage calls; the plan is left as after
+ * nbs_relative_sum.  The captured sequence contains no memset nodes. */
+nbs_status nbs_run_graph(nbs_plan plan, const void* const* prop_u, const void* const* prop_d,
+                         const void* const* prop_s, void* const* F_out, void* stream);
+
+/* Measure launch-shape candidates on the device with the caller's
+ * propagators and keep the fastest: for the block transforms, the register
+ * line kernel or LDS tiles of 512, 1024, 2048 or 4096 elements; for the
+ * contraction, with or without splitting a product's walked index over
+ * lanes and (precision form) 256- or 512-thread workgroups.  Synchronous;
+ * leaves the plan as after nbs_build_blocks.  Results are unchanged up to
+ * rounding order (the channel sums keep their order). */
+nbs_status nbs_plan_autotune(nbs_plan plan, const void* const* prop_u, const void* const* prop_d,
+                             const void* const* prop_s, void* stream);
+
+/* The plan's launch shapes: out[0] register line FFT on/off, out[1] LDS FFT
+ * tile elements, out[2] wavefronts per contraction workgroup, out[3] index
+ * splitting on/off. */
+nbs_status nbs_plan_tuning(const nbs_plan plan, int32_t out[4]);
 
 /* Release everything the plan owns (waits for its device work). NULL is ok. */
 nbs_status nbs_plan_destroy(nbs_plan plan);

@@ -20,7 +20,8 @@ STATUS = {0: "NBS_OK", 1: "NBS_ERR_INVALID", 2: "NBS_ERR_UNSUPPORTED", 3: "NBS_E
 # Every symbol include/nbs.h declares.
 SYMBOLS = ("nbs_plan_create", "nbs_workspace_bytes", "nbs_build_blocks", "nbs_contract_channels",
            "nbs_relative_sum", "nbs_plan_destroy", "nbs_status_string", "nbs_last_error",
-           "nbs_plan_info", "nbs_plan_diagrams", "nbs_plan_table", "nbs_plan_params")
+           "nbs_plan_info", "nbs_plan_diagrams", "nbs_plan_table", "nbs_plan_params", "nbs_run_graph",
+           "nbs_plan_autotune", "nbs_plan_tuning")
 
 
 class NbsError(RuntimeError):
@@ -87,6 +88,12 @@ def lib():
         L.nbs_plan_table.restype = I32
         L.nbs_plan_params.argtypes = [P, ctypes.POINTER(I32)]
         L.nbs_plan_params.restype = I32
+        L.nbs_run_graph.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), P]
+        L.nbs_run_graph.restype = I32
+        L.nbs_plan_autotune.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), P]
+        L.nbs_plan_autotune.restype = I32
+        L.nbs_plan_tuning.argtypes = [P, ctypes.POINTER(I32)]
+        L.nbs_plan_tuning.restype = I32
         _lib = L
     return _lib
 
@@ -114,15 +121,30 @@ def make_channels(chans):
     return arr
 
 
-class Plan:
-    """Owner of an nbs_plan handle."""
+def _ptrs(x, n):
+    xs = list(x) if isinstance(x, (list, tuple)) else [x]
+    if len(xs) != n:
+        raise ValueError("expected %d pointers, got %d" % (n, len(xs)))
+    return (ctypes.c_void_p * n)(*xs)
 
-    def __init__(self, L, T, chans, prec=NBS_FP64, device=0, t0=0, t_begin=0, t_count=None):
+
+class Plan:
+    """Owner of an nbs_plan handle.  One geometry from (L, T, t0, t_begin,
+    t_count), or several (the batching form) from geoms: a list of dicts
+    with keys L, T and optionally t0, t_begin, t_count."""
+
+    def __init__(self, L, T, chans, prec=NBS_FP64, device=0, t0=0, t_begin=0, t_count=None, geoms=None):
         self._h = ctypes.c_void_p()
-        self.geom = make_geometry(L, T, t0, t_begin, t_count)
+        if geoms is None:
+            geoms = [dict(L=L, T=T, t0=t0, t_begin=t_begin, t_count=t_count)]
+        self.geoms = (Geometry * len(geoms))()
+        for i, g in enumerate(geoms):
+            self.geoms[i] = make_geometry(g["L"], g["T"], g.get("t0", 0), g.get("t_begin", 0), g.get("t_count"))
+        self.geom = self.geoms[0]
+        self.n_geom = len(geoms)
         self.chans = list(chans)
         self._ch = make_channels(self.chans)
-        st = lib().nbs_plan_create(ctypes.byref(self._h), ctypes.byref(self.geom), 1, self._ch,
+        st = lib().nbs_plan_create(ctypes.byref(self._h), self.geoms, self.n_geom, self._ch,
                                    len(self.chans), int(prec), int(device))
         if st != 0:
             raise NbsError(st, "nbs_plan_create")
@@ -142,17 +164,32 @@ class Plan:
         return n.value
 
     def build_blocks(self, prop_u, prop_d, prop_s, stream=0):
-        pu = (ctypes.c_void_p * 1)(prop_u)
-        pd = (ctypes.c_void_p * 1)(prop_d)
-        ps = (ctypes.c_void_p * 1)(prop_s)
-        self._check(lib().nbs_build_blocks(self._h, pu, pd, ps, ctypes.c_void_p(stream)), "nbs_build_blocks")
+        """Pointers (or, for several geometries, lists of pointers)."""
+        n = self.n_geom
+        self._check(lib().nbs_build_blocks(self._h, _ptrs(prop_u, n), _ptrs(prop_d, n), _ptrs(prop_s, n),
+                                           ctypes.c_void_p(stream)), "nbs_build_blocks")
 
     def contract_channels(self, stream=0):
         self._check(lib().nbs_contract_channels(self._h, ctypes.c_void_p(stream)), "nbs_contract_channels")
 
     def relative_sum(self, F_out, stream=0):
-        pf = (ctypes.c_void_p * 1)(F_out)
-        self._check(lib().nbs_relative_sum(self._h, pf, ctypes.c_void_p(stream)), "nbs_relative_sum")
+        self._check(lib().nbs_relative_sum(self._h, _ptrs(F_out, self.n_geom), ctypes.c_void_p(stream)),
+                    "nbs_relative_sum")
+
+    def run_graph(self, prop_u, prop_d, prop_s, F_out, stream=0):
+        n = self.n_geom
+        self._check(lib().nbs_run_graph(self._h, _ptrs(prop_u, n), _ptrs(prop_d, n), _ptrs(prop_s, n),
+                                        _ptrs(F_out, n), ctypes.c_void_p(stream)), "nbs_run_graph")
+
+    def autotune(self, prop_u, prop_d, prop_s, stream=0):
+        n = self.n_geom
+        self._check(lib().nbs_plan_autotune(self._h, _ptrs(prop_u, n), _ptrs(prop_d, n), _ptrs(prop_s, n),
+                                            ctypes.c_void_p(stream)), "nbs_plan_autotune")
+
+    def tuning(self):
+        out = (ctypes.c_int32 * 4)()
+        self._check(lib().nbs_plan_tuning(self._h, out), "nbs_plan_tuning")
+        return {"fft_line": out[0], "fft_tile": out[1], "waves": out[2], "split": out[3]}
 
     def info(self):
         inf = PlanInfo()

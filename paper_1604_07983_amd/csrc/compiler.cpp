@@ -410,6 +410,7 @@ std::string compile_channels(const std::vector<ChannelSpec>& chans, const Compil
       std::vector<TeamUnit> best = units;
       double best_t = pack_tasks(units, opt.waves, nullptr);
       for (int target : {6, 4, 3, 2, 1}) {
+        if (!opt.split) break;
         std::vector<TeamUnit> trial = units;
         for (auto& u : trial) {
           if (u.cls == kClassFull) continue;

@@ -110,6 +110,7 @@ struct Program {
 struct CompileOptions {
   int max_group_products = 88;  // LDS result buffer bound per group
   int waves = 8;                // wavefronts of a contraction workgroup
+  bool split = true;            // may split a product's walked index over lanes
 };
 
 struct Compiled {

@@ -240,7 +240,7 @@ struct BlkShape {
   bool l3, l4;
 };
 
-__device__ inline BlkShape decode_shape(int mask) {
+__device__ __forceinline__ BlkShape decode_shape(int mask) {
   BlkShape s;
   int lone[2], in[2];
 #pragma unroll
@@ -260,7 +260,7 @@ __device__ inline BlkShape decode_shape(int mask) {
   return s;
 }
 
-__device__ inline int eps3(int a, int b, int c) { return (a - b) * (b - c) * (c - a) / 2; }
+__device__ __forceinline__ int eps3(int a, int b, int c) { return (a - b) * (b - c) * (c - a) / 2; }
 
 // Term t of the source tensor eps_{c1 c2 c3} (C g5)_{s1 s2} delta_{s3 al} of
 // one source baryon, restricted to the block: sets j0..j2 (3 spin + colour)
@@ -268,7 +268,7 @@ __device__ inline int eps3(int a, int b, int c) { return (a - b) * (b - c) * (c 
 // in = quarks of the baryon in the block; lone = its lone quark (local index);
 // x = the shared index of the lone quark (3 spin + colour, or colour alone
 // for the third quark whose spin is the label al).
-__device__ inline int part_term(int in, int lone, int x, int al, int t, int& j0, int& j1, int& j2) {
+__device__ __forceinline__ int part_term(int in, int lone, int x, int al, int t, int& j0, int& j1, int& j2) {
   if (in == 3) {
     const int cp = t >> 2, sp = t & 3;
     const int c0 = cp < 3 ? cp : cp - 3;
@@ -311,23 +311,23 @@ __device__ inline int part_term(int in, int lone, int x, int al, int t, int& j0,
 // entries are multiples of the bank cycle).
 constexpr int kLdsJ0 = 157, kLdsJ1 = 13, kLdsAl = 1888, kLdsBlock = 2 * kLdsAl;
 
-__device__ inline int lds_index(int i) {
+__device__ __forceinline__ int lds_index(int i) {
   const int al = i / 1728, j0 = (i / 144) % 12, j1 = (i / 12) % 12, j2 = i % 12;
   return al * kLdsAl + j0 * kLdsJ0 + j1 * kLdsJ1 + j2;
 }
 
-__device__ inline int pick6(int m, int j0, int j1, int j2, int j3, int j4, int j5) {
+__device__ __forceinline__ int pick6(int m, int j0, int j1, int j2, int j3, int j4, int j5) {
   return m == 0 ? j0 : m == 1 ? j1 : m == 2 ? j2 : m == 3 ? j3 : m == 4 ? j4 : j5;
 }
 
 // Stride of source quark q in N~[al][slot0][slot1][slot2] under map mp
 // (slot i is contracted with quark m_i): 144, 12, 1, or 0 if q is not in the block.
-__device__ inline int quark_stride(int mp, int q) {
+__device__ __forceinline__ int quark_stride(int mp, int q) {
   return ((mp & 7) == q ? kLdsJ0 : 0) + (((mp >> 3) & 7) == q ? kLdsJ1 : 0) + (((mp >> 6) & 7) == q ? 1 : 0);
 }
 
 // rows r of a block -> (al, a3, a4): r = (al * n3 + a3) * n4 + a4
-__device__ inline void decode_row(const BlkShape& sh, int r, int& al, int& a3, int& a4) {
+__device__ __forceinline__ void decode_row(const BlkShape& sh, int r, int& al, int& a3, int& a4) {
   const int n4 = sh.l4 ? 2 : 1, n3 = sh.l3 ? 2 : 1;
   a4 = sh.l4 ? r % 2 : 0;
   a3 = sh.l3 ? (r / n4) % 2 : 0;
@@ -337,7 +337,7 @@ __device__ inline void decode_row(const BlkShape& sh, int r, int& al, int& a3, i
 // Row r = (al, a3, a4) enters the address of every term linearly:
 //   al * 1728 + 3 a3 * stride(quark 2) + 3 a4 * stride(quark 5).
 template <int R>
-__device__ inline void row_offsets(const BlkShape& sh, int mp, int ro[R]) {
+__device__ __forceinline__ void row_offsets(const BlkShape& sh, int mp, int ro[R]) {
   const int s2 = 3 * quark_stride(mp, 2), s5 = 3 * quark_stride(mp, 5);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -348,7 +348,7 @@ __device__ inline void row_offsets(const BlkShape& sh, int mp, int ro[R]) {
 }
 
 template <typename T, int R>
-__device__ inline void add_rows(const cx<T>* slot, int base, T c, const int ro[R], cx<T> e[R]) {
+__device__ __forceinline__ void add_rows(const cx<T>* slot, int base, T c, const int ro[R], cx<T> e[R]) {
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const cx<T> x = slot[base + ro[r]];
@@ -360,7 +360,7 @@ __device__ inline void add_rows(const cx<T>* slot, int base, T c, const int ro[R
 // Entries E[r][x_A][x_B] of the R rows of one block at one shared index:
 // each source-tensor term is generated once and read for all rows.
 template <typename T, int R>
-__device__ inline void block_rows(const cx<T>* slot, const BlkShape& sh, int nmaps, int mp0, int mp1,
+__device__ __forceinline__ void block_rows(const cx<T>* slot, const BlkShape& sh, int nmaps, int mp0, int mp1,
                                   const int ro0[R], const int ro1[R], int xA, int xB, cx<T> e[R]) {
 #pragma unroll
   for (int r = 0; r < R; ++r) e[r] = cx<T>{0, 0};
@@ -388,7 +388,7 @@ __device__ inline void block_rows(const cx<T>* slot, const BlkShape& sh, int nma
 // Generic lane work (used for products of two full projections, K = 1):
 // k runs over [k0, k0 + nk) and every entry is generated from part_term.
 template <typename T, int R1>
-__device__ inline void lane_work_generic(const cx<T>* slotA, const cx<T>* slotB, const int* d, int k0, int nk,
+__device__ __forceinline__ void lane_work_generic(const cx<T>* slotA, const cx<T>* slotB, const int* d, int k0, int nk,
                                          cx<T> acc[16]) {
   constexpr int R2 = 16 / R1;
   const BlkShape s1 = decode_shape(d[0]), s2 = decode_shape(d[8]);
@@ -418,9 +418,9 @@ __device__ inline void lane_work_generic(const cx<T>* slotA, const cx<T>* slotB,
 // (p, q) the pair's quarks in order, label spin 0.  Lone quark 0 or 1:
 // 12 values of x, 2 terms; lone quark 2: 3 values (its colour), 8 terms.
 constexpr int kPairTable = 72;
-__device__ inline int pair_index(int lone, int x, int t) { return lone < 2 ? lone * 24 + x * 2 + t : 48 + x * 8 + t; }
+__device__ __forceinline__ int pair_index(int lone, int x, int t) { return lone < 2 ? lone * 24 + x * 2 + t : 48 + x * 8 + t; }
 
-__device__ inline void build_pair_table(int* tp, int tid, int nthreads) {
+__device__ __forceinline__ void build_pair_table(int* tp, int tid, int nthreads) {
   for (int i = tid; i < kPairTable; i += nthreads) {
     const int lone = i < 24 ? 0 : (i < 48 ? 1 : 2);
     const int x = lone < 2 ? (i - 24 * lone) / 2 : (i - 48) / 8;
@@ -438,7 +438,7 @@ __device__ inline void build_pair_table(int* tp, int tid, int nthreads) {
 // and walks z over the other side, where block 1 only shifts by z * stride
 // and block 2's pair terms come from the universal table.
 template <typename T, int R1>
-__device__ inline void lane_work_split(const cx<T>* slotA, const cx<T>* slotB, const int* d, const int* tp,
+__device__ __forceinline__ void lane_work_split(const cx<T>* slotA, const cx<T>* slotB, const int* d, const int* tp,
                                        int y, int z0, int zstep, cx<T> acc[16]) {
   constexpr int R2 = 16 / R1;
   const BlkShape s1 = decode_shape(d[0]), s2 = decode_shape(d[8]);
@@ -516,7 +516,7 @@ __device__ inline void lane_work_split(const cx<T>* slotA, const cx<T>* slotB, c
 // Class-specialised form of lane_work_split: rows, pair-term counts and map
 // counts are compile-time, so the loop over z is straight-line code.
 template <typename T, int R1, int NP1, int NP2, int NM1, int NM2>
-__device__ inline void lane_split_fixed(const cx<T>* slotA, const cx<T>* slotB, const int* d, const int* tp,
+__device__ __forceinline__ void lane_split_fixed(const cx<T>* slotA, const cx<T>* slotB, const int* d, const int* tp,
                                         int y, int z0, int zstep, cx<T> acc[16]) {
   constexpr int R2 = 16 / R1;
   constexpr int KZ = NP2 == 8 ? 3 : 12;
@@ -598,7 +598,7 @@ __device__ inline void lane_split_fixed(const cx<T>* slotA, const cx<T>* slotB, 
 // across the team, and lane 0 forms the 4 x 4 outer product (the other lanes
 // contribute zero to the team sum that follows).
 template <typename T, int NM1, int NM2>
-__device__ inline void lane_full(const cx<T>* slotA, const cx<T>* slotB, const int* d, int u, cx<T> acc[16]) {
+__device__ __forceinline__ void lane_full(const cx<T>* slotA, const cx<T>* slotB, const int* d, int u, cx<T> acc[16]) {
   const BlkShape s1 = decode_shape(d[0]), s2 = decode_shape(d[8]);
   int mp1[2] = {d[2], d[3]}, mp2[2] = {d[10], d[11]};
   cx<T> e1[4], e2[4];
@@ -658,7 +658,7 @@ __device__ inline void lane_full(const cx<T>* slotA, const cx<T>* slotB, const i
 
 // Dispatch on the (wavefront-uniform) product class.
 template <typename T, int R1, int NP1, int NP2>
-__device__ inline void split_maps(int nmc, const cx<T>* sA, const cx<T>* sB, const int* d, const int* tp, int y,
+__device__ __forceinline__ void split_maps(int nmc, const cx<T>* sA, const cx<T>* sB, const int* d, const int* tp, int y,
                                   int z0, int zs, cx<T> acc[16]) {
   switch (nmc) {
     case 0: lane_split_fixed<T, R1, NP1, NP2, 1, 1>(sA, sB, d, tp, y, z0, zs, acc); break;
@@ -669,7 +669,7 @@ __device__ inline void split_maps(int nmc, const cx<T>* sA, const cx<T>* sB, con
 }
 
 template <typename T>
-__device__ inline void run_product(int cls, const cx<T>* sA, const cx<T>* sB, const int* d, const int* tp, int y,
+__device__ __forceinline__ void run_product(int cls, const cx<T>* sA, const cx<T>* sB, const int* d, const int* tp, int y,
                                    int z0, int zs, cx<T> acc[16]) {
   if (cls == 0) {
     const int nmc = (d[1] - 1) * 2 + (d[9] - 1);
@@ -703,6 +703,35 @@ size_t contract_lds_bytes(int prec, int max_gprod, int max_gcontrib, int max_gch
          sizeof(int) * (kPairTable + max_gcontrib + max_gch + 1);
 }
 
+// The geometry owning logical workgroup `logical` (geometries in order of
+// their first workgroup).  The table is read with vector loads; every field
+// is moved to scalar registers explicitly (it is wavefront-uniform), which
+// keeps vector registers free for the product loops.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ long long uni64(long long v) {
+  const unsigned lo = (unsigned)uni((int)(unsigned)(v & 0xffffffffLL));
+  const unsigned hi = (unsigned)uni((int)(unsigned)((unsigned long long)v >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+__device__ __forceinline__ ContractGeom find_geometry(const ContractGeom* geo, int n_geom, long long logical) {
+  int gi = 0;
+  for (int k = 1; k < n_geom; ++k)
+    if (logical >= uni64(geo[k].block0)) gi = k;
+  gi = uni(gi);
+  ContractGeom G;
+  G.Nq = (const void*)uni64((long long)geo[gi].Nq);
+  G.Ft = (void*)uni64((long long)geo[gi].Ft);
+  G.V = uni(geo[gi].V);
+  G.Lx = uni(geo[gi].Lx);
+  G.Ly = uni(geo[gi].Ly);
+  G.Lz = uni(geo[gi].Lz);
+  G.t_count = uni(geo[gi].t_count);
+  G.pad = 0;
+  G.block0 = uni64(geo[gi].block0);
+  return G;
+}
+
 // NT threads per workgroup: 512 for FP64 (the two staged blocks take most of
 // the LDS, one workgroup per CU), 256 for the precision form (two workgroups
 // per CU, so one stages while the other computes).  The channel compiler
@@ -728,25 +757,34 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
   const long long local = (b % 8) * (nb8 / 8) + b / 8;
   if (local >= a.n_chunk) return;
   const long long logical = a.block0 + local;
-  const int g = (int)(logical % a.n_groups);
-  const long long qt = logical / a.n_groups;
-  const int t = (int)(qt / a.V), q = (int)(qt % a.V);
-  const int qx = q % a.Lx, qy = (q / a.Lx) % a.Ly, qz = q / (a.Lx * a.Ly);
-  const int mq = (a.Lx - qx) % a.Lx + a.Lx * ((a.Ly - qy) % a.Ly + a.Ly * ((a.Lz - qz) % a.Lz));
+  const ContractGeom G = find_geometry(a.geo, a.n_geom, logical);
+  const long long lb = logical - G.block0;
+  const int g = (int)(lb % a.n_groups);
+  const long long qt = lb / a.n_groups;
+  const int t = (int)(qt / G.V), q = (int)(qt % G.V);
+  const int qx = q % G.Lx, qy = (q / G.Lx) % G.Ly, qz = q / (G.Lx * G.Ly);
+  const int mq = (G.Lx - qx) % G.Lx + G.Lx * ((G.Ly - qy) % G.Ly + G.Ly * ((G.Lz - qz) % G.Lz));
   const int tid = threadIdx.x;
 
   // stage the two operator blocks (all loads in flight before the LDS
   // stores), the group's channel contributions and the pair table
-  const cx<T>* Nq = reinterpret_cast<const cx<T>*>(a.Nq);
-  const cx<T>* srcA = Nq + ((long long)(t * a.n_ops + a.group_op1[g]) * a.V + q) * kBlockEntries;
-  const cx<T>* srcB = Nq + ((long long)(t * a.n_ops + a.group_op2[g]) * a.V + mq) * kBlockEntries;
+  const cx<T>* Nq = reinterpret_cast<const cx<T>*>(G.Nq);
+  const cx<T>* srcA = Nq + ((long long)(t * a.n_ops + a.group_op1[g]) * G.V + q) * kBlockEntries;
+  const cx<T>* srcB = Nq + ((long long)(t * a.n_ops + a.group_op2[g]) * G.V + mq) * kBlockEntries;
   constexpr int kPer = (kBlockEntries + kContractThreads - 1) / kContractThreads;
   {
+    // the block pointers come from the geometry table: state that they
+    // address global memory, so the loads are global loads that may all be
+    // in flight before the LDS stores
+    using gptr = const __attribute__((address_space(1))) cx<T>*;
+    const gptr gA = (gptr)srcA;
+    const gptr gB = (gptr)srcB;
     cx<T> va[kPer];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       const int i = tid + k * kContractThreads;
-      va[k] = srcA[i < kBlockEntries ? i : kBlockEntries - 1];
+      const int ii = i < kBlockEntries ? i : kBlockEntries - 1;
+      va[k] = cx<T>{gA[ii].re, gA[ii].im};
     }
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
@@ -756,7 +794,8 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       const int i = tid + k * kContractThreads;
-      va[k] = srcB[i < kBlockEntries ? i : kBlockEntries - 1];
+      const int ii = i < kBlockEntries ? i : kBlockEntries - 1;
+      va[k] = cx<T>{gB[ii].re, gB[ii].im};
     }
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
@@ -813,8 +852,13 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
   __syncthreads();
 
   // channel sums: 8 lanes per output (spin s of local channel cl), each
-  // summing every 8th contribution, then a fixed-order shuffle reduction
-  cx<T>* Ft = reinterpret_cast<cx<T>*>(a.Ft);
+  // summing every 8th contribution, then a fixed-order shuffle reduction.
+  // The geometry is read again here rather than kept live through the
+  // product loop above, where registers are scarce.
+  const ContractGeom G2 = find_geometry(a.geo, a.n_geom, logical);
+  const long long qt2 = (logical - G2.block0) / a.n_groups;
+  const int t2 = (int)(qt2 / G2.V), q2 = (int)(qt2 % G2.V);
+  cx<T>* Ft = reinterpret_cast<cx<T>*>(G2.Ft);
   for (int i0 = 0; i0 < nch * 16 * 8; i0 += kContractThreads) {
     const int i = i0 + tid;
     const int o = i >> 3, sub = i & 7;
@@ -841,7 +885,7 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
     }
     if (cl < nch && sub == 0) {
       const int ch = a.group_channels[gc0 + cl];
-      Ft[(((long long)ch * a.t_count + t) * 16 + s) * a.V + q] = v;
+      Ft[(((long long)ch * G2.t_count + t2) * 16 + s) * G2.V + q2] = v;
     }
   }
 }
@@ -941,14 +985,6 @@ hipError_t launch_fft_line(int kind, const FftArgs& a, hipStream_t st) {
 hipError_t launch_fft_pass(int kind, const FftArgs& a, hipStream_t st) {
   const long long tiles = ((a.outer + a.OB - 1) / a.OB) * (a.inner / a.IB);
   const size_t lds = sizeof(cd) * (a.n + 2 * (size_t)a.OB * a.IB * (a.n + 1));
-  static bool attr_set = false;
-  if (!attr_set) {
-    const int mx = 160 * 1024;
-    (void)hipFuncSetAttribute((const void*)k_fft_pass<double, double>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-    (void)hipFuncSetAttribute((const void*)k_fft_pass<float, float>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-    (void)hipFuncSetAttribute((const void*)k_fft_pass<float, double>, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-    attr_set = true;
-  }
   const long long chunk = kMaxLaunchItems / kThreads;
   for (long long t0 = 0; t0 < tiles; t0 += chunk) {
     FftArgs c = a;
@@ -968,10 +1004,27 @@ hipError_t launch_fft_pass(int kind, const FftArgs& a, hipStream_t st) {
 
 int contract_waves(int prec) { return prec == 0 ? 8 : 4; }
 
+hipError_t prepare_kernels(int prec, int waves, size_t contract_lds) {
+  const int mx = 160 * 1024;
+  hipError_t e = hipSuccess;
+  auto set = [&](const void* f, int bytes) {
+    if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  };
+  set((const void*)k_fft_pass<double, double>, mx);
+  set((const void*)k_fft_pass<float, float>, mx);
+  set((const void*)k_fft_pass<float, double>, mx);
+  if (prec == 0)
+    set((const void*)k_contract<double, 512>, (int)contract_lds);
+  else if (waves == 8)
+    set((const void*)k_contract<float, 512>, (int)contract_lds);
+  else
+    set((const void*)k_contract<float, 256>, (int)contract_lds);
+  return e;
+}
+
 namespace {
 template <typename T, int NT> hipError_t launch_contract_t(const ContractArgs& a, size_t lds, hipStream_t st) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_contract<T, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
   const long long chunk = kMaxLaunchItems / NT / 8 * 8;
   for (long long b0 = 0; b0 < a.n_blocks; b0 += chunk) {
     ContractArgs c = a;
@@ -987,8 +1040,10 @@ template <typename T, int NT> hipError_t launch_contract_t(const ContractArgs& a
 
 hipError_t launch_contract(int prec, const ContractArgs& a, hipStream_t st) {
   const size_t lds = contract_lds_bytes(prec, a.max_gprod, a.max_gcontrib, a.max_gch);
-  if (a.waves != contract_waves(prec)) return hipErrorInvalidValue;
-  return prec == 0 ? launch_contract_t<double, 512>(a, lds, st) : launch_contract_t<float, 256>(a, lds, st);
+  if (prec == 0) return a.waves == 8 ? launch_contract_t<double, 512>(a, lds, st) : hipErrorInvalidValue;
+  if (a.waves == 4) return launch_contract_t<float, 256>(a, lds, st);
+  if (a.waves == 8) return launch_contract_t<float, 512>(a, lds, st);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace nbs

@@ -41,12 +41,23 @@ struct FftArgs {
 // issued as several launches with an offset.
 constexpr long long kMaxLaunchItems = 1LL << 31;
 
-// Effective blocks and their products (Eqs. (9)-(10)) per (group, q, slice).
+// One geometry of a contraction launch: its blocks, its F~ output and the
+// first logical workgroup it owns (logical workgroups of geometry i are
+// [block0, block0 + n_groups * V * t_count), in geometry order).
+struct ContractGeom {
+  const void* Nq;  // [t_count][n_ops][V][3456]
+  void* Ft;        // [n_ch][t_count][16][V]
+  int V, Lx, Ly, Lz, t_count, pad;
+  long long block0;
+};
+constexpr int kMaxGeom = 32;
+
+// Effective blocks and their products (Eqs. (9)-(10)) per (group, q, slice),
+// over every geometry of the plan in one launch.
 struct ContractArgs {
-  const void* Nq;
-  void* Ft;  // [n_ch][t_count][16][V]
-  int V, Lx, Ly, Lz, t_count, n_ops, n_groups;
-  long long n_blocks;  // n_groups * V * t_count
+  const ContractGeom* geo;  // device table, n_geom entries
+  int n_geom, n_ops, n_groups;
+  long long n_blocks;  // sum over geometries of n_groups * V * t_count
   const int *group_op1, *group_op2, *group_prod, *group_task, *group_ch, *group_channels;
   const int *ch_contrib, *contrib_prod, *prod_desc, *task_lanes;
   const double* contrib_coef;
@@ -73,5 +84,9 @@ size_t contract_lds_bytes(int prec, int max_gprod, int max_gcontrib, int max_gch
 // balances each group's tasks over this many).
 int contract_waves(int prec);
 hipError_t launch_contract(int prec, const ContractArgs& a, hipStream_t st);
+// Sets the dynamic-LDS limits of the kernels that need more than the
+// default; called once per plan before any launch (and so outside any
+// stream capture).
+hipError_t prepare_kernels(int prec, int waves, size_t contract_lds);
 
 }  // namespace nbs

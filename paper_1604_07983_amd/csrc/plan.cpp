@@ -26,31 +26,53 @@ struct DevBuf {
 
 enum Stage { ST_NEW = 0, ST_BUILT = 1, ST_CONTRACTED = 2 };
 
+// Per-geometry device workspace.
+struct GeomWork {
+  nbs_geometry g{};
+  long long V = 0;
+  void* Nq = nullptr;          // [t_count][n_ops][V][3456] blocks, then N~(q) in place
+  void* Ft = nullptr;          // [n_ch][t_count][16][V] F~_c(q)
+  unsigned* maxbits = nullptr; // precision form: [3][t_count] max |Re|, |Im| as float bits
+  int* exps = nullptr;         // precision form: [3][t_count] power-of-two exponents
+  double* oscale = nullptr;    // precision form: [n_ch][t_count] un-scaling factors
+};
+
+// Launch-shape choices (set by nbs_plan_autotune, else the defaults).
+struct Tuning {
+  int fft_tile = 1024;  // elements of an LDS tile of k_fft_pass (FP64 pairs)
+  int fft_line = 1;     // 1: register line kernel where the length has one
+  int split = 1;        // 1: compiler may split the walked index of a product over lanes
+  int waves = 8;        // wavefronts per contraction workgroup
+};
+
 }  // namespace
 
 struct nbs_plan_s {
-  nbs_geometry geom{};
+  std::vector<GeomWork> gw;
   int n_ch = 0;
   int prec = 0;
   int device = -1;
+  std::vector<nbs::ChannelSpec> specs;
   Compiled comp;
   CompileOptions opt;
+  Tuning tune;
   std::string err;
   int stage = ST_NEW;
   // device memory
   std::vector<DevBuf> bufs;
-  void* Nq = nullptr;
-  void* Ft = nullptr;
-  int* prog = nullptr;     // all int tables, concatenated
-  double* coef = nullptr;  // acc coefficients
-  unsigned* maxbits = nullptr;
-  int* exps = nullptr;
-  double* oscale = nullptr;
-  int* chan_nf = nullptr;
+  int* prog = nullptr;     // all int tables of the compiled program, concatenated
+  double* coef = nullptr;  // channel coefficients
+  int* chan_nf = nullptr;  // [n_ch][3] quark counts
+  nbs::ContractGeom* geo = nullptr;
   size_t dev_bytes = 0;
   std::map<std::string, size_t> prog_off;  // table name -> offset (ints) into prog
-  nbs::NbbArgs nbb{};
+  nbs::NbbArgs nbb{};                      // geometry-independent part
   nbs::ContractArgs con{};
+  // captured launch sequence (nbs_run_graph)
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<const void*> graph_key;
 };
 
 namespace {
@@ -88,9 +110,30 @@ nbs_status dev_alloc(nbs_plan p, size_t bytes, void** out, int* countdown) {
   return NBS_OK;
 }
 
+void dev_free(nbs_plan p, void* ptr) {
+  for (size_t i = 0; i < p->bufs.size(); ++i)
+    if (p->bufs[i].p == ptr) {
+      (void)hipFree(ptr);
+      p->dev_bytes -= p->bufs[i].bytes;
+      p->bufs.erase(p->bufs.begin() + i);
+      return;
+    }
+}
+
+void drop_graph(nbs_plan p) {
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->exec = nullptr;
+  p->graph = nullptr;
+  p->graph_key.clear();
+}
+
 void free_all(nbs_plan p) {
   if (p->device >= 0) {
     (void)hipSetDevice(p->device);
+    drop_graph(p);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    p->cap_stream = nullptr;
     for (auto& b : p->bufs) (void)hipFree(b.p);
   }
   p->bufs.clear();
@@ -100,10 +143,6 @@ nbs_status hip_check(nbs_plan p, hipError_t e, const char* what) {
   if (e == hipSuccess) return NBS_OK;
   return fail(p, NBS_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
-
-// Elements of one FFT tile in LDS (two FP64 buffers of this size per
-// workgroup): 1024 keeps four workgroups resident per CU.
-constexpr int kFftTile = 1024;
 
 constexpr long long kLineMinInner = 16;
 
@@ -129,7 +168,9 @@ nbs_status fft3d(nbs_plan p, int kind_first, int kind_rest, const void* in, void
     a.inner = inner;
     a.outer = batch * V / ((long long)L[ax] * (inner / inner0));
     a.IB = pick_ib(inner);
-    a.OB = std::max(1, kFftTile / (a.IB * a.n));
+    a.OB = std::max(1, p->tune.fft_tile / (a.IB * a.n));
+    // two FP64 tiles and the twiddles must fit the 160 KB of LDS
+    while (a.OB > 1 && 16.0 * (a.n + 2.0 * a.OB * a.IB * (a.n + 1)) > 160.0 * 1024) a.OB /= 2;
     a.sign = sign;
     a.gscale = ax == 2 ? gscale : 1.0;
     a.oscale = ax == 2 ? oscale : nullptr;
@@ -137,12 +178,142 @@ nbs_status fft3d(nbs_plan p, int kind_first, int kind_rest, const void* in, void
     // one line per thread in registers where the length has a kernel and the
     // lines are wide enough apart for adjacent threads to read one run
     const int kind = ax == 0 ? kind_first : kind_rest;
-    const bool line = nbs::fft_line_supported(a.n) && inner >= kLineMinInner;
+    const bool line = p->tune.fft_line && nbs::fft_line_supported(a.n) && inner >= kLineMinInner;
     nbs_status s = hip_check(p, line ? nbs::launch_fft_line(kind, a, st) : nbs::launch_fft_pass(kind, a, st),
                              "fft pass");
     if (s != NBS_OK) return s;
   }
   return NBS_OK;
+}
+
+// Compile the channel table with the plan's options and (device plans)
+// upload its tables, replacing earlier ones.
+nbs_status compile_and_upload(nbs_plan p) {
+  p->opt.waves = p->tune.waves;
+  p->opt.split = p->tune.split != 0;
+  Compiled comp;
+  std::string msg = nbs::compile_channels(p->specs, p->opt, &comp);
+  if (!msg.empty()) return fail(p, NBS_ERR_INVALID, msg);
+  p->comp = std::move(comp);
+  if (p->device < 0) return NBS_OK;
+  const auto& P = p->comp.prog;
+  std::vector<int> flat;
+  std::map<std::string, size_t> off;
+  auto put = [&](const char* name, const std::vector<int>& v) {
+    off[name] = flat.size();
+    flat.insert(flat.end(), v.begin(), v.end());
+    flat.push_back(0);  // keep empty tables addressable
+  };
+  put("group_op1", P.group_op1); put("group_op2", P.group_op2); put("group_prod", P.group_prod);
+  put("group_task", P.group_task); put("group_ch", P.group_ch); put("group_channels", P.group_channels);
+  put("ch_contrib", P.ch_contrib); put("contrib_prod", P.contrib_prod); put("prod_desc", P.prod_desc);
+  put("task_lanes", P.task_lanes);
+  int countdown = 0;
+  void* prog = nullptr;
+  void* coef = nullptr;
+  nbs_status s = dev_alloc(p, flat.size() * 4, &prog, &countdown);
+  if (s != NBS_OK) return s;
+  if ((s = dev_alloc(p, std::max<size_t>(8, P.contrib_coef.size() * 8), &coef, &countdown)) != NBS_OK) {
+    dev_free(p, prog);
+    return s;
+  }
+  hipError_t e = hipMemcpy(prog, flat.data(), flat.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess && !P.contrib_coef.empty())
+    e = hipMemcpy(coef, P.contrib_coef.data(), P.contrib_coef.size() * 8, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    dev_free(p, prog);
+    dev_free(p, coef);
+    return fail(p, NBS_ERR_DEVICE, "table upload");
+  }
+  if (p->prog) dev_free(p, p->prog);
+  if (p->coef) dev_free(p, p->coef);
+  p->prog = (int*)prog;
+  p->coef = (double*)coef;
+  p->prog_off = off;
+  nbs::ContractArgs& c = p->con;
+  auto T = [&](const char* name) { return (const int*)(p->prog + p->prog_off[name]); };
+  c.n_ops = P.n_ops;
+  c.n_groups = (int)P.group_prod.size() - 1;
+  c.group_op1 = T("group_op1"); c.group_op2 = T("group_op2"); c.group_prod = T("group_prod");
+  c.group_task = T("group_task"); c.group_ch = T("group_ch"); c.group_channels = T("group_channels");
+  c.ch_contrib = T("ch_contrib"); c.contrib_prod = T("contrib_prod"); c.prod_desc = T("prod_desc");
+  c.task_lanes = T("task_lanes");
+  c.contrib_coef = p->coef;
+  c.max_gprod = std::max(1, P.max_group_products);
+  c.max_gcontrib = std::max(1, P.max_group_contrib);
+  c.max_gch = std::max(1, P.max_group_channels);
+  c.waves = p->tune.waves;
+  const size_t lds = nbs::contract_lds_bytes(p->prec, c.max_gprod, c.max_gcontrib, c.max_gch);
+  if (lds > 160 * 1024) return fail(p, NBS_ERR_UNSUPPORTED, "a channel group needs more LDS than a CU has");
+  return hip_check(p, nbs::prepare_kernels(p->prec, c.waves, lds), "kernel attributes");
+}
+
+// ---- the three stages, enqueued on a stream --------------------------------
+
+nbs_status enqueue_build(nbs_plan p, const void* const* pu, const void* const* pd, const void* const* ps,
+                         hipStream_t st) {
+  nbs_status s;
+  for (size_t i = 0; i < p->gw.size(); ++i) {
+    GeomWork& w = p->gw[i];
+    const nbs_geometry& g = w.g;
+    nbs::NbbArgs a = p->nbb;
+    const void* S[3] = {pu[i], pd[i], ps[i]};
+    for (int f = 0; f < 3; ++f) a.S[f] = S[f];
+    a.Nq = w.Nq;
+    a.V = (int)w.V;
+    a.t_count = g.t_count;
+    a.scale_exp = nullptr;
+    if (p->prec == NBS_FP32_MFMA) {
+      if ((s = hip_check(p, nbs::launch_fill_u32(w.maxbits, 0u, 3LL * g.t_count, st), "fill")) != NBS_OK) return s;
+      for (int f = 0; f < 3; ++f) {
+        if (!a.flavour_used[f]) continue;
+        if ((s = hip_check(p, nbs::launch_absmax(S[f], w.maxbits + f * g.t_count, w.V * 144, g.t_count, st),
+                           "absmax")) != NBS_OK)
+          return s;
+      }
+      if ((s = hip_check(p, nbs::launch_scale_exps(w.maxbits, w.exps, 3 * g.t_count, st), "scale")) != NBS_OK)
+        return s;
+      a.scale_exp = w.exps;
+    }
+    if ((s = hip_check(p, nbs::launch_nbb(p->prec, a, st), "nbb")) != NBS_OK) return s;
+    const int kind = p->prec == NBS_FP64 ? 0 : 1;
+    s = fft3d(p, kind, kind, w.Nq, w.Nq, (long long)g.t_count * p->comp.prog.n_ops, g.L, nbs::kBlockEntries, -1,
+              nullptr, 1, 1.0, st);
+    if (s != NBS_OK) return s;
+  }
+  return NBS_OK;
+}
+
+nbs_status enqueue_contract(nbs_plan p, hipStream_t st) {
+  return hip_check(p, nbs::launch_contract(p->prec, p->con, st), "contract");
+}
+
+nbs_status enqueue_relsum(nbs_plan p, void* const* F_out, hipStream_t st) {
+  nbs_status s;
+  for (size_t i = 0; i < p->gw.size(); ++i) {
+    GeomWork& w = p->gw[i];
+    const nbs_geometry& g = w.g;
+    const double* osc = nullptr;
+    if (p->prec == NBS_FP32_MFMA) {
+      if ((s = hip_check(p, nbs::launch_channel_scale(w.exps, p->chan_nf, w.oscale, p->n_ch, g.t_count, st),
+                         "channel scale")) != NBS_OK)
+        return s;
+      osc = w.oscale;
+    }
+    const int kfirst = p->prec == NBS_FP64 ? 0 : 2;
+    s = fft3d(p, kfirst, 0, w.Ft, F_out[i], (long long)p->n_ch * g.t_count * 16, g.L, 1, +1, osc, 16,
+              1.0 / (double)w.V, st);
+    if (s != NBS_OK) return s;
+  }
+  return NBS_OK;
+}
+
+bool ptrs_ok(const void* const* a, size_t n) {
+  if (!a) return false;
+  for (size_t i = 0; i < n; ++i)
+    if (!a[i]) return false;
+  return true;
 }
 
 }  // namespace
@@ -168,47 +339,57 @@ nbs_status nbs_plan_create(nbs_plan* out, const nbs_geometry* g, int32_t n_geom,
   if (!out) return NBS_ERR_INVALID;
   *out = nullptr;
   if (!g || !ch || n_ch <= 0 || n_geom <= 0) return NBS_ERR_INVALID;
-  if (n_geom != 1) return NBS_ERR_UNSUPPORTED;
+  if (n_geom > nbs::kMaxGeom) return NBS_ERR_UNSUPPORTED;
   if (prec != NBS_FP64 && prec != NBS_FP32_MFMA) return NBS_ERR_INVALID;
-  for (int k = 0; k < 3; ++k)
-    if (!good_extent(g->L[k])) return NBS_ERR_INVALID;
-  if (g->T < 1 || g->t0 < 0 || g->t0 >= g->T || g->t_begin < 0 || g->t_count < 1 ||
-      g->t_begin + g->t_count > g->T)
-    return NBS_ERR_INVALID;
-  const long long V = (long long)g->L[0] * g->L[1] * g->L[2];
-  if (V * g->t_count > (1LL << 31) / 32) return NBS_ERR_UNSUPPORTED;
+  for (int i = 0; i < n_geom; ++i) {
+    for (int k = 0; k < 3; ++k)
+      if (!good_extent(g[i].L[k])) return NBS_ERR_INVALID;
+    if (g[i].T < 1 || g[i].t0 < 0 || g[i].t0 >= g[i].T || g[i].t_begin < 0 || g[i].t_count < 1 ||
+        g[i].t_begin + g[i].t_count > g[i].T)
+      return NBS_ERR_INVALID;
+    const long long V = (long long)g[i].L[0] * g[i].L[1] * g[i].L[2];
+    if (V * g[i].t_count > (1LL << 31) / 32) return NBS_ERR_UNSUPPORTED;
+  }
 
   nbs_plan p = new (std::nothrow) nbs_plan_s;
   if (!p) return NBS_ERR_NOMEM;
-  p->geom = *g;
   p->n_ch = n_ch;
   p->prec = prec;
   p->device = device;
-  std::vector<nbs::ChannelSpec> specs(n_ch);
-  for (int c = 0; c < n_ch; ++c) {
-    for (int k = 0; k < 2; ++k) {
-      specs[c].sink[k] = ch[c].sink[k];
-      specs[c].src[k] = ch[c].src[k];
-    }
+  p->gw.resize(n_geom);
+  for (int i = 0; i < n_geom; ++i) {
+    p->gw[i].g = g[i];
+    p->gw[i].V = (long long)g[i].L[0] * g[i].L[1] * g[i].L[2];
   }
-  p->opt.waves = nbs::contract_waves(prec == NBS_FP64 ? 0 : 1);
-  std::string msg = nbs::compile_channels(specs, p->opt, &p->comp);
-  if (!msg.empty()) {
-    delete p;
-    return NBS_ERR_INVALID;
+  p->specs.resize(n_ch);
+  for (int c = 0; c < n_ch; ++c)
+    for (int k = 0; k < 2; ++k) {
+      p->specs[c].sink[k] = ch[c].sink[k];
+      p->specs[c].src[k] = ch[c].src[k];
+    }
+  p->tune.waves = nbs::contract_waves(prec == NBS_FP64 ? 0 : 1);
+  if (device < -1) { delete p; return NBS_ERR_INVALID; }
+  if (device >= 0) {
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev) {
+      (void)hipGetLastError();
+      delete p;
+      return NBS_ERR_INVALID;
+    }
+    if (hipSetDevice(device) != hipSuccess) { delete p; return NBS_ERR_DEVICE; }
+  }
+  {
+    // compile only (device tables come after the workspace)
+    const int dev = p->device;
+    p->device = -1;
+    const nbs_status s = compile_and_upload(p);
+    p->device = dev;
+    if (s != NBS_OK) { delete p; return s; }
   }
   if (device < 0) {
-    if (device != -1) { delete p; return NBS_ERR_INVALID; }
     *out = p;
     return NBS_OK;
   }
-  int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev) {
-    (void)hipGetLastError();
-    delete p;
-    return NBS_ERR_INVALID;
-  }
-  if (hipSetDevice(device) != hipSuccess) { delete p; return NBS_ERR_DEVICE; }
 
   const auto& P = p->comp.prog;
   const int nt = P.n_ops;
@@ -238,97 +419,70 @@ nbs_status nbs_plan_create(nbs_plan* out, const nbs_geometry* g, int32_t n_geom,
   }
   nb.n_dq = (int)dq.size();
   nb.n_ops = nt;
-  nb.V = (int)V;
-  nb.t_count = g->t_count;
 
+  // workspace of every geometry
   const size_t el = prec == NBS_FP64 ? 16 : 8;
-  const size_t nq_bytes = (size_t)g->t_count * nt * V * nbs::kBlockEntries * el;
-  const size_t ft_bytes = (size_t)n_ch * g->t_count * 16 * V * el;
-  // program tables
-  std::vector<int> flat;
-  auto put = [&](const char* name, const std::vector<int>& v) {
-    p->prog_off[name] = flat.size();
-    flat.insert(flat.end(), v.begin(), v.end());
-    flat.push_back(0);  // keep empty tables addressable
-  };
-  put("group_op1", P.group_op1); put("group_op2", P.group_op2); put("group_prod", P.group_prod);
-  put("group_task", P.group_task); put("group_ch", P.group_ch); put("group_channels", P.group_channels);
-  put("ch_contrib", P.ch_contrib); put("contrib_prod", P.contrib_prod); put("prod_desc", P.prod_desc);
-  put("task_lanes", P.task_lanes);
-  std::vector<int> nf(p->comp.channel_flavour);
-
+  size_t need = (1 << 22);
+  long long n_blocks = 0;
+  const long long n_groups = (long long)P.group_prod.size() - 1;
+  for (auto& w : p->gw) {
+    need += (size_t)w.g.t_count * nt * w.V * nbs::kBlockEntries * el + (size_t)n_ch * w.g.t_count * 16 * w.V * el;
+    n_blocks += n_groups * w.V * w.g.t_count;
+  }
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) { (void)hipGetLastError(); free_b = (size_t)-1; }
-  const size_t need = nq_bytes + ft_bytes + flat.size() * 4 + P.contrib_coef.size() * 8 + (1 << 20);
   if (need > free_b) {
     delete p;
     return NBS_ERR_NOMEM;
   }
   int countdown = alloc_fail_countdown();
   nbs_status s = NBS_OK;
-  void* tmp;
-  if ((s = dev_alloc(p, nq_bytes, &p->Nq, &countdown)) != NBS_OK ||
-      (s = dev_alloc(p, ft_bytes, &p->Ft, &countdown)) != NBS_OK ||
-      (s = dev_alloc(p, flat.size() * 4, &tmp, &countdown)) != NBS_OK) {
+  void* tmp = nullptr;
+  auto bail = [&](nbs_status st) {
     free_all(p);
     delete p;
-    return s;
+    return st;
+  };
+  for (auto& w : p->gw) {
+    const int tc = w.g.t_count;
+    if ((s = dev_alloc(p, (size_t)tc * nt * w.V * nbs::kBlockEntries * el, &w.Nq, &countdown)) != NBS_OK ||
+        (s = dev_alloc(p, (size_t)n_ch * tc * 16 * w.V * el, &w.Ft, &countdown)) != NBS_OK)
+      return bail(s);
+    if ((s = dev_alloc(p, 3 * tc * 4, &tmp, &countdown)) != NBS_OK) return bail(s);
+    w.maxbits = (unsigned*)tmp;
+    if ((s = dev_alloc(p, 3 * tc * 4, &tmp, &countdown)) != NBS_OK) return bail(s);
+    w.exps = (int*)tmp;
+    if ((s = dev_alloc(p, (size_t)n_ch * tc * 8, &tmp, &countdown)) != NBS_OK) return bail(s);
+    w.oscale = (double*)tmp;
   }
-  p->prog = (int*)tmp;
-  if ((s = dev_alloc(p, std::max<size_t>(8, P.contrib_coef.size() * 8), &tmp, &countdown)) != NBS_OK) {
-    free_all(p); delete p; return s;
-  }
-  p->coef = (double*)tmp;
-  if ((s = dev_alloc(p, 3 * g->t_count * 4, &tmp, &countdown)) != NBS_OK) { free_all(p); delete p; return s; }
-  p->maxbits = (unsigned*)tmp;
-  if ((s = dev_alloc(p, 3 * g->t_count * 4, &tmp, &countdown)) != NBS_OK) { free_all(p); delete p; return s; }
-  p->exps = (int*)tmp;
-  if ((s = dev_alloc(p, (size_t)n_ch * g->t_count * 8, &tmp, &countdown)) != NBS_OK) { free_all(p); delete p; return s; }
-  p->oscale = (double*)tmp;
-  if ((s = dev_alloc(p, nf.size() * 4, &tmp, &countdown)) != NBS_OK) { free_all(p); delete p; return s; }
+  const std::vector<int>& nf = p->comp.channel_flavour;
+  if ((s = dev_alloc(p, nf.size() * 4, &tmp, &countdown)) != NBS_OK) return bail(s);
   p->chan_nf = (int*)tmp;
-
-  hipError_t e = hipMemcpy(p->prog, flat.data(), flat.size() * 4, hipMemcpyHostToDevice);
-  if (e == hipSuccess && !P.contrib_coef.empty())
-    e = hipMemcpy(p->coef, P.contrib_coef.data(), P.contrib_coef.size() * 8, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(p->chan_nf, nf.data(), nf.size() * 4, hipMemcpyHostToDevice);
+  if ((s = dev_alloc(p, sizeof(nbs::ContractGeom) * n_geom, &tmp, &countdown)) != NBS_OK) return bail(s);
+  p->geo = (nbs::ContractGeom*)tmp;
+  std::vector<nbs::ContractGeom> geo(n_geom);
+  long long b0 = 0;
+  for (int i = 0; i < n_geom; ++i) {
+    const GeomWork& w = p->gw[i];
+    geo[i].Nq = w.Nq;
+    geo[i].Ft = w.Ft;
+    geo[i].V = (int)w.V;
+    geo[i].Lx = w.g.L[0]; geo[i].Ly = w.g.L[1]; geo[i].Lz = w.g.L[2];
+    geo[i].t_count = w.g.t_count;
+    geo[i].pad = 0;
+    geo[i].block0 = b0;
+    b0 += n_groups * w.V * w.g.t_count;
+  }
+  hipError_t e = hipMemcpy(p->chan_nf, nf.data(), nf.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->geo, geo.data(), sizeof(nbs::ContractGeom) * n_geom, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipGetLastError();
-    free_all(p);
-    delete p;
-    return NBS_ERR_DEVICE;
+    return bail(NBS_ERR_DEVICE);
   }
-
-  nbs::ContractArgs& c = p->con;
-  auto T = [&](const char* name) { return (const int*)(p->prog + p->prog_off[name]); };
-  c.Nq = p->Nq;
-  c.Ft = p->Ft;
-  c.V = (int)V;
-  c.Lx = g->L[0]; c.Ly = g->L[1]; c.Lz = g->L[2];
-  c.t_count = g->t_count;
-  c.n_ops = nt;
-  c.n_groups = (int)P.group_prod.size() - 1;
-  c.n_blocks = (long long)c.n_groups * V * g->t_count;
-  if (c.n_blocks + 8 > 0x7fffffffLL) {
-    free_all(p);
-    delete p;
-    return NBS_ERR_UNSUPPORTED;
-  }
-  c.group_op1 = T("group_op1"); c.group_op2 = T("group_op2"); c.group_prod = T("group_prod");
-  c.group_task = T("group_task"); c.group_ch = T("group_ch"); c.group_channels = T("group_channels");
-  c.ch_contrib = T("ch_contrib"); c.contrib_prod = T("contrib_prod"); c.prod_desc = T("prod_desc");
-  c.task_lanes = T("task_lanes");
-  c.contrib_coef = p->coef;
-  c.max_gprod = std::max(1, P.max_group_products);
-  c.max_gcontrib = std::max(1, P.max_group_contrib);
-  c.max_gch = std::max(1, P.max_group_channels);
-  c.waves = p->opt.waves;
-  if (nbs::contract_lds_bytes(prec, c.max_gprod, c.max_gcontrib, c.max_gch) > 160 * 1024) {
-    free_all(p);
-    delete p;
-    return NBS_ERR_UNSUPPORTED;
-  }
-  p->nbb.Nq = p->Nq;
+  if ((s = compile_and_upload(p)) != NBS_OK) return bail(s);
+  p->con.geo = p->geo;
+  p->con.n_geom = n_geom;
+  p->con.n_blocks = n_blocks;
   *out = p;
   return NBS_OK;
 }
@@ -343,33 +497,11 @@ nbs_status nbs_build_blocks(nbs_plan p, const void* const* prop_u, const void* c
                             const void* const* prop_s, void* stream) {
   if (!p) return NBS_ERR_INVALID;
   if (p->device < 0) return fail(p, NBS_ERR_STATE, "host-only plan");
-  if (!prop_u || !prop_d || !prop_s || !prop_u[0] || !prop_d[0] || !prop_s[0])
+  const size_t n = p->gw.size();
+  if (!ptrs_ok(prop_u, n) || !ptrs_ok(prop_d, n) || !ptrs_ok(prop_s, n))
     return fail(p, NBS_ERR_INVALID, "null propagator pointer");
-  hipStream_t st = (hipStream_t)stream;
   if (hipSetDevice(p->device) != hipSuccess) return fail(p, NBS_ERR_DEVICE, "hipSetDevice");
-  const nbs_geometry& g = p->geom;
-  const long long V = (long long)g.L[0] * g.L[1] * g.L[2];
-  nbs::NbbArgs a = p->nbb;
-  const void* S[3] = {prop_u[0], prop_d[0], prop_s[0]};
-  for (int f = 0; f < 3; ++f) a.S[f] = S[f];
-  a.scale_exp = nullptr;
-  nbs_status s;
-  if (p->prec == NBS_FP32_MFMA) {
-    if ((s = hip_check(p, nbs::launch_fill_u32(p->maxbits, 0u, 3LL * g.t_count, st), "fill")) != NBS_OK) return s;
-    for (int f = 0; f < 3; ++f) {
-      if (!a.flavour_used[f]) continue;
-      if ((s = hip_check(p, nbs::launch_absmax(S[f], p->maxbits + f * g.t_count, V * 144, g.t_count, st),
-                         "absmax")) != NBS_OK)
-        return s;
-    }
-    if ((s = hip_check(p, nbs::launch_scale_exps(p->maxbits, p->exps, 3 * g.t_count, st), "scale")) != NBS_OK)
-      return s;
-    a.scale_exp = p->exps;
-  }
-  if ((s = hip_check(p, nbs::launch_nbb(p->prec, a, st), "nbb")) != NBS_OK) return s;
-  const int kind = p->prec == NBS_FP64 ? 0 : 1;
-  s = fft3d(p, kind, kind, p->Nq, p->Nq, (long long)g.t_count * p->comp.prog.n_ops, g.L, nbs::kBlockEntries,
-            -1, nullptr, 1, 1.0, st);
+  const nbs_status s = enqueue_build(p, prop_u, prop_d, prop_s, (hipStream_t)stream);
   if (s != NBS_OK) return s;
   p->stage = ST_BUILT;
   return NBS_OK;
@@ -380,7 +512,7 @@ nbs_status nbs_contract_channels(nbs_plan p, void* stream) {
   if (p->device < 0) return fail(p, NBS_ERR_STATE, "host-only plan");
   if (p->stage < ST_BUILT) return fail(p, NBS_ERR_STATE, "nbs_build_blocks must come first");
   if (hipSetDevice(p->device) != hipSuccess) return fail(p, NBS_ERR_DEVICE, "hipSetDevice");
-  nbs_status s = hip_check(p, nbs::launch_contract(p->prec, p->con, (hipStream_t)stream), "contract");
+  const nbs_status s = enqueue_contract(p, (hipStream_t)stream);
   if (s != NBS_OK) return s;
   p->stage = ST_CONTRACTED;
   return NBS_OK;
@@ -390,22 +522,144 @@ nbs_status nbs_relative_sum(nbs_plan p, void* const* F_out, void* stream) {
   if (!p) return NBS_ERR_INVALID;
   if (p->device < 0) return fail(p, NBS_ERR_STATE, "host-only plan");
   if (p->stage < ST_CONTRACTED) return fail(p, NBS_ERR_STATE, "nbs_contract_channels must come first");
-  if (!F_out || !F_out[0]) return fail(p, NBS_ERR_INVALID, "null output pointer");
+  if (!ptrs_ok(F_out, p->gw.size())) return fail(p, NBS_ERR_INVALID, "null output pointer");
+  if (hipSetDevice(p->device) != hipSuccess) return fail(p, NBS_ERR_DEVICE, "hipSetDevice");
+  return enqueue_relsum(p, F_out, (hipStream_t)stream);
+}
+
+nbs_status nbs_run_graph(nbs_plan p, const void* const* prop_u, const void* const* prop_d, const void* const* prop_s,
+                         void* const* F_out, void* stream) {
+  if (!p) return NBS_ERR_INVALID;
+  if (p->device < 0) return fail(p, NBS_ERR_STATE, "host-only plan");
+  const size_t n = p->gw.size();
+  if (!ptrs_ok(prop_u, n) || !ptrs_ok(prop_d, n) || !ptrs_ok(prop_s, n))
+    return fail(p, NBS_ERR_INVALID, "null propagator pointer");
+  if (!ptrs_ok(F_out, n)) return fail(p, NBS_ERR_INVALID, "null output pointer");
+  if (hipSetDevice(p->device) != hipSuccess) return fail(p, NBS_ERR_DEVICE, "hipSetDevice");
+  std::vector<const void*> key;
+  for (size_t i = 0; i < n; ++i) {
+    key.push_back(prop_u[i]);
+    key.push_back(prop_d[i]);
+    key.push_back(prop_s[i]);
+    key.push_back(F_out[i]);
+  }
+  nbs_status s;
+  if (!p->exec || key != p->graph_key) {
+    drop_graph(p);
+    if (!p->cap_stream &&
+        (s = hip_check(p, hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking), "stream")) != NBS_OK)
+      return s;
+    if ((s = hip_check(p, hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal), "capture")) != NBS_OK)
+      return s;
+    s = enqueue_build(p, prop_u, prop_d, prop_s, p->cap_stream);
+    if (s == NBS_OK) s = enqueue_contract(p, p->cap_stream);
+    if (s == NBS_OK) s = enqueue_relsum(p, F_out, p->cap_stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(p->cap_stream, &graph);
+    if (s != NBS_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return s;
+    }
+    if ((s = hip_check(p, e, "end capture")) != NBS_OK) return s;
+    p->graph = graph;
+    if ((s = hip_check(p, hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0), "instantiate")) != NBS_OK) {
+      drop_graph(p);
+      return s;
+    }
+    p->graph_key = key;
+  }
+  if ((s = hip_check(p, hipGraphLaunch(p->exec, (hipStream_t)stream), "graph launch")) != NBS_OK) return s;
+  p->stage = ST_CONTRACTED;
+  return NBS_OK;
+}
+
+nbs_status nbs_plan_autotune(nbs_plan p, const void* const* prop_u, const void* const* prop_d,
+                             const void* const* prop_s, void* stream) {
+  if (!p) return NBS_ERR_INVALID;
+  if (p->device < 0) return fail(p, NBS_ERR_STATE, "host-only plan");
+  const size_t n = p->gw.size();
+  if (!ptrs_ok(prop_u, n) || !ptrs_ok(prop_d, n) || !ptrs_ok(prop_s, n))
+    return fail(p, NBS_ERR_INVALID, "null propagator pointer");
   if (hipSetDevice(p->device) != hipSuccess) return fail(p, NBS_ERR_DEVICE, "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
-  const nbs_geometry& g = p->geom;
-  const double V = (double)g.L[0] * g.L[1] * g.L[2];
-  const double* osc = nullptr;
+  drop_graph(p);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
   nbs_status s;
-  if (p->prec == NBS_FP32_MFMA) {
-    if ((s = hip_check(p, nbs::launch_channel_scale(p->exps, p->chan_nf, p->oscale, p->n_ch, g.t_count, st),
-                       "channel scale")) != NBS_OK)
-      return s;
-    osc = p->oscale;
+  if ((s = hip_check(p, hipEventCreate(&e0), "event")) != NBS_OK) return s;
+  if ((s = hip_check(p, hipEventCreate(&e1), "event")) != NBS_OK) { (void)hipEventDestroy(e0); return s; }
+  // time (ms) of fn, run twice after one warm-up
+  auto timed = [&](auto fn, float* ms) -> nbs_status {
+    nbs_status r = fn();
+    if (r != NBS_OK) return r;
+    if ((r = hip_check(p, hipEventRecord(e0, st), "event")) != NBS_OK) return r;
+    for (int k = 0; k < 2; ++k)
+      if ((r = fn()) != NBS_OK) return r;
+    if ((r = hip_check(p, hipEventRecord(e1, st), "event")) != NBS_OK) return r;
+    if ((r = hip_check(p, hipEventSynchronize(e1), "event")) != NBS_OK) return r;
+    return hip_check(p, hipEventElapsedTime(ms, e0, e1), "event");
+  };
+  auto finish = [&](nbs_status r) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return r;
+  };
+  // 1. forward transforms: register line kernel or LDS tiles of 512 .. 4096
+  //    elements (repeating the in-place transform only costs time; the blocks
+  //    are rebuilt at the end)
+  struct FftChoice { int line, tile; };
+  const FftChoice fft_cands[] = {{1, 1024}, {0, 512}, {0, 1024}, {0, 2048}, {0, 4096}};
+  float best_ms = 0;
+  FftChoice best_fft = fft_cands[0];
+  bool first = true;
+  for (const auto& c : fft_cands) {
+    p->tune.fft_line = c.line;
+    p->tune.fft_tile = c.tile;
+    float ms = 0;
+    s = timed([&]() {
+      for (auto& w : p->gw) {
+        const int kind = p->prec == NBS_FP64 ? 0 : 1;
+        nbs_status r = fft3d(p, kind, kind, w.Nq, w.Nq, (long long)w.g.t_count * p->comp.prog.n_ops, w.g.L,
+                             nbs::kBlockEntries, -1, nullptr, 1, 1.0, st);
+        if (r != NBS_OK) return r;
+      }
+      return NBS_OK;
+    }, &ms);
+    if (s != NBS_OK) return finish(s);
+    if (first || ms < best_ms) { best_ms = ms; best_fft = c; first = false; }
   }
-  const int kfirst = p->prec == NBS_FP64 ? 0 : 2;
-  s = fft3d(p, kfirst, 0, p->Ft, F_out[0], (long long)p->n_ch * g.t_count * 16, g.L, 1, +1, osc, 16, 1.0 / V, st);
-  if (s != NBS_OK) return s;
+  p->tune.fft_line = best_fft.line;
+  p->tune.fft_tile = best_fft.tile;
+  // 2. contraction: workgroup size (precision form) and index splitting
+  if ((s = enqueue_build(p, prop_u, prop_d, prop_s, st)) != NBS_OK) return finish(s);
+  struct ConChoice { int waves, split; };
+  std::vector<ConChoice> con_cands = {{8, 1}, {8, 0}};
+  if (p->prec == NBS_FP32_MFMA) con_cands = {{4, 1}, {4, 0}, {8, 1}, {8, 0}};
+  ConChoice best_con = con_cands[0];
+  first = true;
+  for (const auto& c : con_cands) {
+    p->tune.waves = c.waves;
+    p->tune.split = c.split;
+    if ((s = compile_and_upload(p)) != NBS_OK) return finish(s);
+    float ms = 0;
+    if ((s = timed([&]() { return enqueue_contract(p, st); }, &ms)) != NBS_OK) return finish(s);
+    if (first || ms < best_ms) { best_ms = ms; best_con = c; first = false; }
+  }
+  p->tune.waves = best_con.waves;
+  p->tune.split = best_con.split;
+  if ((s = compile_and_upload(p)) != NBS_OK) return finish(s);
+  // leave the plan built with the chosen shapes
+  if ((s = enqueue_build(p, prop_u, prop_d, prop_s, st)) != NBS_OK) return finish(s);
+  if ((s = hip_check(p, hipStreamSynchronize(st), "sync")) != NBS_OK) return finish(s);
+  p->stage = ST_BUILT;
+  return finish(NBS_OK);
+}
+
+nbs_status nbs_plan_tuning(const nbs_plan p, int32_t out[4]) {
+  if (!p || !out) return NBS_ERR_INVALID;
+  out[0] = p->tune.fft_line;
+  out[1] = p->tune.fft_tile;
+  out[2] = p->tune.waves;
+  out[3] = p->tune.split;
   return NBS_OK;
 }
 

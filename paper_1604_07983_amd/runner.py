@@ -37,6 +37,24 @@ def host_props(L, T, ts, decay=DECAY, same_ud=False, t0=0, source=0, dtype=np.co
     return out
 
 
+def _props_job(args):
+    L, T, ts, decay, t0, source, dtype = args
+    return host_props(L, T, ts, decay=decay, t0=t0, source=source, dtype=dtype)
+
+
+def host_props_many(geoms, decay=DECAY, dtype=np.complex128, workers=8):
+    """host_props for every geometry (source index = position in the list),
+    generated in a process pool."""
+    jobs = [(tuple(g["L"]), g["T"], list(range(g.get("t_begin", 0), g.get("t_begin", 0) + g["t_count"])), decay,
+             g.get("t0", 0), k, dtype) for k, g in enumerate(geoms)]
+    if workers <= 1 or len(jobs) == 1:
+        return [_props_job(j) for j in jobs]
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    with cf.ProcessPoolExecutor(max_workers=min(workers, len(jobs)), mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(_props_job, jobs))
+
+
 class Runner:
     """A plan plus its output buffer for one window of slices."""
 
@@ -67,6 +85,56 @@ class Runner:
         self.contract()
         self.relative_sum()
         return self.F
+
+    def close(self):
+        self.plan.close()
+
+
+class BatchRunner:
+    """The batching form: one plan over several geometries (uneven lattices,
+    source slices, windows), one output buffer per geometry."""
+
+    def __init__(self, geoms, chans, prec=binding.NBS_FP32_MFMA, device=0):
+        torch = _torch()
+        self.geoms = [dict(g) for g in geoms]
+        self.plan = binding.Plan(None, None, chans, prec=prec, device=device, geoms=self.geoms)
+        self.n_ch = len(chans)
+        self.F = []
+        for i, g in enumerate(self.geoms):
+            L = g["L"]
+            tc = self.plan.geoms[i].t_count
+            self.F.append(torch.empty((self.n_ch, tc, 16, L[2], L[1], L[0]), dtype=torch.complex128, device="cuda"))
+
+    def stream(self):
+        return _torch().cuda.current_stream().cuda_stream
+
+    @staticmethod
+    def _split(props):
+        return ([p[0].data_ptr() for p in props], [p[1].data_ptr() for p in props], [p[2].data_ptr() for p in props])
+
+    def build(self, props):
+        """props: per geometry the (u, d, s) device tensors."""
+        self.plan.build_blocks(*self._split(props), self.stream())
+
+    def contract(self):
+        self.plan.contract_channels(self.stream())
+
+    def relative_sum(self):
+        self.plan.relative_sum([f.data_ptr() for f in self.F], self.stream())
+
+    def run(self, props):
+        self.build(props)
+        self.contract()
+        self.relative_sum()
+        return self.F
+
+    def run_graph(self, props):
+        self.plan.run_graph(*self._split(props), [f.data_ptr() for f in self.F], self.stream())
+        return self.F
+
+    def autotune(self, props):
+        self.plan.autotune(*self._split(props), self.stream())
+        return self.plan.tuning()
 
     def close(self):
         self.plan.close()

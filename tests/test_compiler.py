@@ -137,12 +137,38 @@ def _create(L=(4, 4, 4), T=8, chans=(("p", "p", "p", "p"),), prec=0, device=-1, 
     (dict(L=(7, 4, 4)), 1), (dict(L=(1, 4, 4)), 1), (dict(L=(256, 4, 4)), 1),
     (dict(T=8, t_begin=6, t_count=4), 1), (dict(T=8, t0=8), 1), (dict(prec=5), 1),
     (dict(chans=(("p", "p", "p", "n"),)), 1), (dict(chans=((0, 0, 0, 11),)), 1),
-    (dict(n_geom=2), 2), (dict(device=-7), 1),
+    (dict(n_geom=33), 2), (dict(n_geom=0), 1), (dict(device=-7), 1),
 ])
 def test_plan_create_rejects_bad_arguments(kw, status):
     st, h = _create(**kw)
     assert st == status
     assert not h.value
+
+
+def _create_many(geoms, device=-1):
+    h = ctypes.c_void_p()
+    arr = (binding.Geometry * len(geoms))()
+    for i, g in enumerate(geoms):
+        arr[i] = binding.make_geometry(**g)
+    ch = binding.make_channels([("p", "p", "p", "p")])
+    st = binding.lib().nbs_plan_create(ctypes.byref(h), arr, len(geoms), ch, 1, 1, device)
+    return st, h
+
+
+def test_batched_plan_takes_uneven_geometries():
+    geoms = [dict(L=(24, 24, 24), T=48, t0=6 * k, t_begin=(6 * k + 3) % 48, t_count=1) for k in range(8)]
+    geoms += [dict(L=(40, 40, 40), T=40, t0=5 * k, t_begin=(5 * k + 3) % 40, t_count=1) for k in range(8)]
+    geoms += [dict(L=(6, 10, 9), T=8, t0=1, t_begin=0, t_count=8)]
+    st, h = _create_many(geoms)
+    assert st == 0 and h.value
+    binding.lib().nbs_plan_destroy(h)
+
+
+@pytest.mark.parametrize("bad", [dict(L=(7, 4, 4), T=8), dict(L=(4, 4, 4), T=8, t_begin=7, t_count=2)])
+def test_batched_plan_rejects_any_bad_geometry(bad):
+    geoms = [dict(L=(4, 4, 4), T=8), dict(L=(6, 6, 6), T=12), bad]
+    st, h = _create_many(geoms)
+    assert st == 1 and not h.value
 
 
 def test_compute_calls_on_host_only_plan_are_state_errors():
@@ -152,6 +178,10 @@ def test_compute_calls_on_host_only_plan_are_state_errors():
     assert L.nbs_build_blocks(p.handle, z, z, z, None) == 5
     assert L.nbs_contract_channels(p.handle, None) == 5
     assert L.nbs_relative_sum(p.handle, z, None) == 5
+    assert L.nbs_run_graph(p.handle, z, z, z, z, None) == 5
+    assert L.nbs_plan_autotune(p.handle, z, z, z, None) == 5
     assert b"host-only" in L.nbs_last_error(p.handle)
+    tune = p.tuning()
+    assert tune["fft_line"] == 1 and tune["fft_tile"] == 1024 and tune["split"] == 1
     assert L.nbs_plan_destroy(None) == 0
     assert L.nbs_status_string(3) == b"out of device memory"
