@@ -43,10 +43,10 @@ def _props_job(args):
 
 
 def host_props_many(geoms, decay=DECAY, dtype=np.complex128, workers=8):
-    """host_props for every geometry (source index = position in the list),
-    generated in a process pool."""
+    """host_props for every geometry (source index: the geometry's "source"
+    key, else its position in the list), generated in a process pool."""
     jobs = [(tuple(g["L"]), g["T"], list(range(g.get("t_begin", 0), g.get("t_begin", 0) + g["t_count"])), decay,
-             g.get("t0", 0), k, dtype) for k, g in enumerate(geoms)]
+             g.get("t0", 0), g.get("source", k), dtype) for k, g in enumerate(geoms)]
     if workers <= 1 or len(jobs) == 1:
         return [_props_job(j) for j in jobs]
     import concurrent.futures as cf

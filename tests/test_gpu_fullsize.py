@@ -83,3 +83,32 @@ def test_config3_fp32_32c64_bench_window():
     props, Fg = run_window(L, T, binding.NBS_FP32_MFMA, 0, 16, chans)
     assert np.isfinite(Fg).all()
     check_sampled_momenta(L, props, Fg, chans, slices=(0, 15), qs=((0, 0, 0), (31, 5, 17)), tol=1e-5)
+
+
+def test_config5_96cubed_slice_closed_form():
+    """One slice of the 96^3 slab (the precision form, one GPU's share of a
+    time-split 96^3 x 64 run), every channel against the closed form of
+    separable propagators phi_f(x) M_f (the oracle's channel constants times
+    a scalar correlation): the 96-point transforms, 196 GB of blocks and
+    the 17.7 M-workgroup contraction at their real size."""
+    import gc
+    import torch
+    from tests import separable
+    gc.collect()
+    torch.cuda.empty_cache()
+    announce("96^3 slice, separable propagators")
+    L, T = (96, 96, 96), 64
+    chans = channels.r52()
+    props, M, phi = separable.make(L, seed=11, dtype=np.complex64)
+    dp = runner.device_props(props, binding.NBS_FP32_MFMA)
+    r = runner.Runner(L, T, chans, prec=binding.NBS_FP32_MFMA, t_begin=0, t_count=1)
+    F = r.run(*dp)
+    torch.cuda.synchronize()
+    r.close()
+    del dp
+    C = separable.constants(chans, M)
+    for c, ch in enumerate(chans):
+        got = F[c, 0].cpu().numpy()
+        want = separable.channel(ch, C[c], phi)
+        err = np.linalg.norm(got - want) / np.linalg.norm(want)
+        assert err <= 1e-5, (c, ch, float(err))
