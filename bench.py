@@ -73,6 +73,23 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 5}), flush=True)
 
 
+def measured_traffic(config):
+    """HBM bytes of one nbs_contract_channels call from the byte counters
+    recorded in profiles/k_contract_traffic.json, or None when the kernel
+    source has changed since they were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_contract_traffic.json")
+    src = os.path.join(ROOT, "paper_1604_07983_amd", "csrc", "kernels.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != sha or config not in rec.get("configs", {}):
+        return None
+    return rec["configs"][config]["bytes_per_call"]
+
+
 def program_work(plan):
     """Algorithmic work per momentum site of the contraction: (EBB flops,
     MEB flops).  EBB: every distinct effective-block entry is a sum of
@@ -308,8 +325,9 @@ def main():
     total_flops = contract_flops + sites * (n_types * 3456 * 3 * 8 + n_types * 3456 * 5 * np.log2(V) * 1.0)
     roof = {"bound": "alu", "achieved": contract_flops / (contract_ms * 1e-3) / 1e12,
             "peak": PEAK["fp64"] / 1e12 if prec == 0 else PEAK["fp32_vector"] / 1e12,
-            "unit": "TFLOP/s", "traffic": None,
-            "kernel": "k_contract (effective blocks + products)"}
+            "unit": "TFLOP/s", "traffic": measured_traffic(args.config),
+            "kernel": "k_contract (effective blocks + products)",
+            "algorithmic_bytes": float(sites * n_types * 3456 * el + len(chans) * 16 * sites * el)}
     roof["frac"] = roof["achieved"] / roof["peak"]
     out = {
         "metric": "NBS site-channels/sec + GFLOP/s, FP32-MFMA batched vs FP64 plain at stated rel err",
