@@ -98,7 +98,7 @@ def program_work(plan):
     each (products shared by several channels counted once)."""
     import numpy as np
     info = plan.info()
-    desc = plan.table("prod_desc").reshape(-1, 20)
+    desc = plan.table("prod_desc").reshape(-1, plan.params()["prod_ints"])
     return 4.0 * info["n_terms"], 8.0 * 16 * float(desc[:, 16].astype(np.int64).sum())
 
 

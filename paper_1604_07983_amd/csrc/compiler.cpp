@@ -1,5 +1,6 @@
 // compiler.cpp -- channel-table compiler (see compiler.hpp).
 #include "compiler.hpp"
+#include "kernels.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -177,6 +178,58 @@ void operator_slots(int op, int fl[3]) {
 }
 
 namespace {
+
+// Offset unit of source quark q in a block under map mp: the LDS stride of
+// the slot contracted with q, 0 if q is not in the block.
+int quark_unit(const Map& mp, int q) {
+  return (mp.m[0] == q ? nbs::kLdsJ0 : 0) + (mp.m[1] == q ? nbs::kLdsJ1 : 0) + (mp.m[2] == q ? 1 : 0);
+}
+
+// Row weights of a block's spin labels, least significant row bit first:
+// rows are r = (al n3 + a3) n4 + a4, and a label of quark 2 (5) moves the
+// spin of that quark's slot, i.e. 3 units of its stride.
+void label_weights(const Shape& sh, const Map& mp, int w[2]) {
+  int n = 0;
+  w[0] = w[1] = 0;
+  if (sh.lbl4) w[n++] = 3 * quark_unit(mp, 5);
+  if (sh.lbl3) w[n++] = 3 * quark_unit(mp, 2);
+}
+
+// Per-product offsets of a split product (descriptor entries 20..47).
+void fill_split_offsets(const Block& b1, const Block& b2, int* d) {
+  const Shape s1 = shape_of(b1.mask), s2 = shape_of(b2.mask);
+  const bool pairA = s1.kA == 2;
+  const int base1 = pairA ? 0 : 3, base2 = pairA ? 3 : 0;
+  const int lone1 = (pairA ? s1.loneA : s1.loneB) - base1;
+  const int lone2 = (pairA ? s2.loneB : s2.loneA) - base2;
+  const int p1 = base1 + (lone1 == 0 ? 1 : 0), q1 = base1 + (lone1 == 2 ? 1 : 2);
+  const int p2 = base2 + (lone2 == 0 ? 1 : 0), q2 = base2 + (lone2 == 2 ? 1 : 2);
+  const int ys = base1 + lone1, zs = base2 + lone2;
+  d[20] = lone1;
+  d[21] = lone2;
+  for (size_t m = 0; m < b1.maps.size() && m < 2; ++m) {
+    int* e = d + 24 + 6 * m;
+    int w[2];
+    label_weights(s1, b1.maps[m], w);
+    e[0] = quark_unit(b1.maps[m], p1);
+    e[1] = quark_unit(b1.maps[m], q1);
+    e[2] = quark_unit(b1.maps[m], zs);
+    e[3] = w[0];
+    e[4] = w[1];
+    e[5] = b1.maps[m].sign;
+  }
+  for (size_t m = 0; m < b2.maps.size() && m < 2; ++m) {
+    int* e = d + 36 + 6 * m;
+    int w[2];
+    label_weights(s2, b2.maps[m], w);
+    e[0] = quark_unit(b2.maps[m], ys);
+    e[1] = quark_unit(b2.maps[m], p2);
+    e[2] = quark_unit(b2.maps[m], q2);
+    e[3] = w[0];
+    e[4] = w[1];
+    e[5] = b2.maps[m].sign;
+  }
+}
 
 // Lane layout of one block product inside a task (see the lane word).
 struct TeamUnit {
@@ -380,6 +433,7 @@ std::string compile_channels(const std::vector<ChannelSpec>& chans, const Compil
         d[17] = s1.KB;
         d[18] = s1.rows();
         d[19] = (s1.lbl3 ? 1 : 0) | (s1.lbl4 ? 2 : 0);
+        if (s1.K() > 1) fill_split_offsets(prods[p].first, prods[p].second, d);
         P.prod_desc.insert(P.prod_desc.end(), d, d + kProdInts);
         C.product_k += s1.K();
       }

@@ -17,6 +17,8 @@
 // device, not from per-term tables.
 #pragma once
 
+#include "kernels.hpp"
+
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -57,9 +59,18 @@ struct DiagramInfo {
 // Integers per block-product descriptor (layout in kernels and tests):
 //  [0] mask1 [1] nmaps1 [2..7] maps1  [8] mask2 [9] nmaps2 [10..15] maps2
 //  [16] K [17] KB [18] rows1 [19] label flags of block 1 (bit0 a3, bit1 a4)
+//  and, for products with a shared index (K > 1), offsets in the kernel's
+//  LDS layout (kLdsJ0, kLdsJ1, 1 for the three slots of a block):
+//  [20] lone1, [21] lone2: local index of the lone quark of block 1's pair
+//       baryon (it sits in block 2) and of block 2's pair baryon
+//  [24 + 6 m + 0..5], map m of block 1: offset unit of the pair's first and
+//       second quark and of the walked (z) quark, the row weights of its
+//       spin labels (least significant first), sign
+//  [36 + 6 m + 0..5], map m of block 2: offset unit of the fixed (y) quark
+//       and of the pair's first and second quark, row weights, sign
 // A map packs m0 | m1 << 3 | m2 << 6 | (sign < 0) << 9: operator-block slot
-// i is contracted with source quark m_i.
-constexpr int kProdInts = 20;
+// i is contracted with source quark m_i.  kProdInts (48) is defined with
+// the kernel's LDS layout in kernels.hpp.
 // Lane word of a wavefront task: product (12 bits) | y << 12 (4 bits) |
 // log2(team) << 16 (3 bits) | z0 << 19 (4 bits) | zsl << 23 (3 bits) |
 // class << 26 (5 bits); product 0xfff = idle lane.  For K > 1, y is the

@@ -305,11 +305,6 @@ __device__ __forceinline__ int part_term(int in, int lone, int x, int al, int t,
   return 1;
 }
 
-// LDS layout of a staged block: odd strides for the two leading source
-// indices so the lanes of a team (which differ in those indices) spread over
-// the LDS banks instead of all hitting the same one (144 and 12 complex
-// entries are multiples of the bank cycle).
-constexpr int kLdsJ0 = 157, kLdsJ1 = 13, kLdsAl = 1888, kLdsBlock = 2 * kLdsAl;
 
 __device__ __forceinline__ int lds_index(int i) {
   const int al = i / 1728, j0 = (i / 144) % 12, j1 = (i / 12) % 12, j2 = i % 12;
@@ -514,31 +509,42 @@ __device__ __forceinline__ void lane_work_split(const cx<T>* slotA, const cx<T>*
 }
 
 // Class-specialised form of lane_work_split: rows, pair-term counts and map
-// counts are compile-time, so the loop over z is straight-line code.
+// counts are compile-time, so the loop over z is straight-line code, and the
+// per-map offsets come precomputed from the product descriptor.
+template <int R>
+__device__ __forceinline__ int row_offset(int r, int wlo, int whi) {
+  // rows r = (al n3 + a3) n4 + a4: label bits below the spin al
+  if constexpr (R == 2) return r * kLdsAl;
+  else if constexpr (R == 4) return (r & 1) * wlo + (r >> 1) * kLdsAl;
+  else return (r & 1) * wlo + ((r >> 1) & 1) * whi + (r >> 2) * kLdsAl;
+}
+
 template <typename T, int R1, int NP1, int NP2, int NM1, int NM2>
 __device__ __forceinline__ void lane_split_fixed(const cx<T>* slotA, const cx<T>* slotB, const int* d, const int* tp,
-                                        int y, int z0, int zstep, cx<T> acc[16]) {
+                                                 int y, int z0, int zstep, cx<T> acc[16]) {
   constexpr int R2 = 16 / R1;
   constexpr int KZ = NP2 == 8 ? 3 : 12;
-  const BlkShape s1 = decode_shape(d[0]), s2 = decode_shape(d[8]);
-  const bool pairA = s1.kA == 2;
-  const int base1 = pairA ? 0 : 3, base2 = pairA ? 3 : 0;
-  const int lone1 = pairA ? s1.loneA : s1.loneB;
-  const int lone2 = pairA ? s2.loneB : s2.loneA;
-  const int p1 = base1 + (lone1 == 0 ? 1 : 0), q1 = base1 + (lone1 == 2 ? 1 : 2);
-  const int p2 = base2 + (lone2 == 0 ? 1 : 0), q2 = base2 + (lone2 == 2 ? 1 : 2);
-  const int ys = base1 + lone1, zs = base2 + lone2;
-  int mp1[NM1], mp2[NM2];
+  const int lone1 = d[20], lone2 = d[21];
+  int e1d[NM1][6], e2d[NM2][6];
 #pragma unroll
-  for (int m = 0; m < NM1; ++m) mp1[m] = d[2 + m];
+  for (int m = 0; m < NM1; ++m)
 #pragma unroll
-  for (int m = 0; m < NM2; ++m) mp2[m] = d[10 + m];
+    for (int k = 0; k < 6; ++k) e1d[m][k] = d[24 + 6 * m + k];
+#pragma unroll
+  for (int m = 0; m < NM2; ++m)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) e2d[m][k] = d[36 + 6 * m + k];
   int ro1[NM1][R1], ro2[NM2][R2];
 #pragma unroll
-  for (int m = 0; m < NM1; ++m) row_offsets<R1>(s1, mp1[m], ro1[m]);
+  for (int m = 0; m < NM1; ++m)
 #pragma unroll
-  for (int m = 0; m < NM2; ++m) row_offsets<R2>(s2, mp2[m], ro2[m]);
-  int off1[NM1][NP1], zst1[NM1];
+    for (int r = 0; r < R1; ++r) ro1[m][r] = row_offset<R1>(r, e1d[m][3], e1d[m][4]);
+#pragma unroll
+  for (int m = 0; m < NM2; ++m)
+#pragma unroll
+    for (int r = 0; r < R2; ++r) ro2[m][r] = row_offset<R2>(r, e2d[m][3], e2d[m][4]);
+  // block 1: this lane's pair terms (fixed y), z moves its single quark
+  int off1[NM1][NP1];
   T cc1[NM1][NP1];
 #pragma unroll
   for (int t = 0; t < NP1; ++t) {
@@ -547,20 +553,16 @@ __device__ __forceinline__ void lane_split_fixed(const cx<T>* slotA, const cx<T>
     const int c = ((e >> 8) & 1) ? -1 : 1;
 #pragma unroll
     for (int m = 0; m < NM1; ++m) {
-      off1[m][t] = jp * quark_stride(mp1[m], p1) + jq * quark_stride(mp1[m], q1);
-      cc1[m][t] = (T)((((mp1[m] >> 9) & 1) ? -1 : 1) * c);
+      off1[m][t] = jp * e1d[m][0] + jq * e1d[m][1];
+      cc1[m][t] = (T)(e1d[m][5] * c);
     }
   }
-  int yo2[NM2], st2p[NM2], st2q[NM2];
+  int yo2[NM2];
   T sg2[NM2];
 #pragma unroll
-  for (int m = 0; m < NM1; ++m) zst1[m] = quark_stride(mp1[m], zs);
-#pragma unroll
   for (int m = 0; m < NM2; ++m) {
-    yo2[m] = y * quark_stride(mp2[m], ys);
-    st2p[m] = quark_stride(mp2[m], p2);
-    st2q[m] = quark_stride(mp2[m], q2);
-    sg2[m] = ((mp2[m] >> 9) & 1) ? (T)-1 : (T)1;
+    yo2[m] = y * e2d[m][0];
+    sg2[m] = (T)e2d[m][5];
   }
   const int tz0 = pair_index(lone2, 0, 0), tzs = NP2;  // table row of z is tz0 + z * NP2
 #pragma unroll 1
@@ -572,7 +574,7 @@ __device__ __forceinline__ void lane_split_fixed(const cx<T>* slotA, const cx<T>
     for (int r = 0; r < R2; ++r) e2[r] = cx<T>{0, 0};
 #pragma unroll
     for (int m = 0; m < NM1; ++m) {
-      const int zo = z * zst1[m];
+      const int zo = z * e1d[m][2];
 #pragma unroll
       for (int t = 0; t < NP1; ++t) add_rows<T, R1>(slotA, off1[m][t] + zo, cc1[m][t], ro1[m], e1);
     }
@@ -583,7 +585,7 @@ __device__ __forceinline__ void lane_split_fixed(const cx<T>* slotA, const cx<T>
       const int jp = e & 15, jq = (e >> 4) & 15;
 #pragma unroll
       for (int m = 0; m < NM2; ++m)
-        add_rows<T, R2>(slotB, yo2[m] + jp * st2p[m] + jq * st2q[m], sg2[m] * c, ro2[m], e2);
+        add_rows<T, R2>(slotB, yo2[m] + jp * e2d[m][1] + jq * e2d[m][2], sg2[m] * c, ro2[m], e2);
     }
 #pragma unroll
     for (int r1 = 0; r1 < R1; ++r1)
@@ -732,6 +734,81 @@ __device__ __forceinline__ ContractGeom find_geometry(const ContractGeom* geo, i
   return G;
 }
 
+// ---- team sums: reduce-scatter across the lanes of a team ----------------
+// Each step pairs every lane with a partner that differs in one lane bit
+// (row_mirror flips bits 0-3, row_half_mirror bits 0-2, the quad mirror bits
+// 0-1, the quad swap bit 0; all within a 16-lane row, as DPP moves), keeps
+// the half of its values selected by that bit and adds the partner's copy of
+// that half.  After the steps for bits 3..0 lane l of a row holds output
+// l & 15 summed over the row (4- and 8-lane teams take the steps for bits
+// 1..0 and 2..0 and keep 4 and 2 outputs per lane); rows of 32- and 64-lane
+// teams are added with cross-row shuffles.  About 15 complex
+// moves per lane instead of 16 per butterfly step, and a fixed order.
+template <int CTRL> __device__ __forceinline__ float dpp_move(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL> __device__ __forceinline__ double dpp_move(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+template <int CTRL, int NV, typename T>
+__device__ __forceinline__ void rs_step(const cx<T>* in, cx<T>* out, bool upper) {
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const cx<T> lo = in[i], hi = in[NV + i];
+    const cx<T> keep = upper ? hi : lo, send = upper ? lo : hi;
+    out[i] = cx<T>{keep.re + dpp_move<CTRL>(send.re), keep.im + dpp_move<CTRL>(send.im)};
+  }
+}
+
+constexpr int kDppRowMirror = 0x140, kDppRowHalfMirror = 0x141, kDppQuadMirror = 0x1B, kDppQuadSwap = 0xB1;
+
+template <typename T>
+__device__ __forceinline__ void team_reduce_store(const cx<T> acc[16], int lg, int lane, int p, cx<T>* R) {
+  const bool b3 = (lane >> 3) & 1, b2 = (lane >> 2) & 1, b1 = (lane >> 1) & 1, b0 = lane & 1;
+  if (lg == 2) {
+    cx<T> v8[8], v4[4];
+    rs_step<kDppQuadMirror, 8, T>(acc, v8, b1);
+    rs_step<kDppQuadSwap, 4, T>(v8, v4, b0);
+    if (p != 0xfff) {
+      const int o0 = 8 * b1 + 4 * b0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) R[p * 16 + o0 + k] = v4[k];
+    }
+    return;
+  }
+  if (lg == 3) {
+    cx<T> v8[8], v4[4], v2[2];
+    rs_step<kDppRowHalfMirror, 8, T>(acc, v8, b2);
+    rs_step<kDppQuadMirror, 4, T>(v8, v4, b1);
+    rs_step<kDppQuadSwap, 2, T>(v4, v2, b0);
+    if (p != 0xfff) {
+      const int o0 = 8 * b2 + 4 * b1 + 2 * b0;
+      R[p * 16 + o0] = v2[0];
+      R[p * 16 + o0 + 1] = v2[1];
+    }
+    return;
+  }
+  cx<T> v8[8], v4[4], v2[2], v1[1];
+  rs_step<kDppRowMirror, 8, T>(acc, v8, b3);
+  rs_step<kDppRowHalfMirror, 4, T>(v8, v4, b2);
+  rs_step<kDppQuadMirror, 2, T>(v4, v2, b1);
+  rs_step<kDppQuadSwap, 1, T>(v2, v1, b0);
+  cx<T> v = v1[0];
+  if (lg >= 5) {
+    v.re += __shfl_xor(v.re, 16);
+    v.im += __shfl_xor(v.im, 16);
+  }
+  if (lg >= 6) {
+    v.re += __shfl_xor(v.re, 32);
+    v.im += __shfl_xor(v.im, 32);
+  }
+  if (p != 0xfff && (lane & ((1 << lg) - 1)) < 16) R[p * 16 + (lane & 15)] = v;
+}
+
 // NT threads per workgroup: 512 for FP64 (the two staged blocks take most of
 // the LDS, one workgroup per CU), 256 for the precision form (two workgroups
 // per CU, so one stages while the other computes).  The channel compiler
@@ -827,7 +904,7 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
       // full projections: the whole wavefront runs the team code (it
       // shuffles); idle lanes compute on product 0 and drop the result
       const int y = (w >> 12) & 15;
-      const int* d = a.prod_desc + (long long)(pbase + (p != 0xfff ? p : 0)) * 20;
+      const int* d = a.prod_desc + (long long)(pbase + (p != 0xfff ? p : 0)) * kProdInts;
       run_product<T>(0, slotA, slotB, d, tp, y, 0, 1, acc);
       if (p == 0xfff) {
 #pragma unroll
@@ -835,18 +912,18 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
       }
     } else if (p != 0xfff) {
       const int y = (w >> 12) & 15, z0 = (w >> 19) & 15, zs = 1 << ((w >> 23) & 7);
-      run_product<T>(cls, slotA, slotB, a.prod_desc + (long long)(pbase + p) * 20, tp, y, z0, zs, acc);
+      run_product<T>(cls, slotA, slotB, a.prod_desc + (long long)(pbase + p) * kProdInts, tp, y, z0, zs, acc);
     }
-    for (int dd = 1; dd < (1 << lg); dd <<= 1) {
+    if (cls == 0) {
+      // lane_full left the whole product in the team's first lane
+      if (p != 0xfff && ((w >> 12) & 15) == 0) {
 #pragma unroll
-      for (int o = 0; o < 16; ++o) {
-        acc[o].re += __shfl_xor(acc[o].re, dd);
-        acc[o].im += __shfl_xor(acc[o].im, dd);
+        for (int o = 0; o < 16; ++o) R[p * 16 + o] = acc[o];
       }
-    }
-    if (p != 0xfff && (lane & ((1 << lg) - 1)) == 0) {
-#pragma unroll
-      for (int o = 0; o < 16; ++o) R[p * 16 + o] = acc[o];
+    } else {
+      // the team's product (its first lane is never idle)
+      const int pt = __shfl(p, lane & ~((1 << lg) - 1));
+      team_reduce_store<T>(acc, lg, lane, pt, R);
     }
   }
   __syncthreads();

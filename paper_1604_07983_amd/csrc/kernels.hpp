@@ -41,6 +41,15 @@ struct FftArgs {
 // issued as several launches with an offset.
 constexpr long long kMaxLaunchItems = 1LL << 31;
 
+// LDS layout of a staged operator block N~[al][j0][j1][j2] in the
+// contraction kernel: odd strides for the two leading source indices so the
+// lanes of a team (which differ in those indices) spread over the LDS banks
+// (144 and 12 complex entries are multiples of the bank cycle).  The channel
+// compiler precomputes per-product offsets in these units.
+constexpr int kLdsJ0 = 157, kLdsJ1 = 13, kLdsAl = 1888, kLdsBlock = 2 * kLdsAl;
+// Integers per block-product descriptor (layout documented in compiler.hpp).
+constexpr int kProdInts = 48;
+
 // One geometry of a contraction launch: its blocks, its F~ output and the
 // first logical workgroup it owns (logical workgroups of geometry i are
 // [block0, block0 + n_groups * V * t_count), in geometry order).

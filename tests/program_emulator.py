@@ -15,7 +15,7 @@ import numpy as np
 NAMES = ("op_code", "op_nterm", "op_term_trip", "op_term_perm", "op_term_w", "group_op1", "group_op2",
          "group_prod", "group_task", "group_ch", "group_channels", "ch_contrib", "contrib_prod",
          "contrib_coef", "prod_desc", "task_lanes")
-PROD_INTS = 20
+PROD_INTS = 48
 IDLE_CLASS = 30
 
 EPS = {(0, 1, 2): 1, (1, 2, 0): 1, (2, 0, 1): 1, (0, 2, 1): -1, (2, 1, 0): -1, (1, 0, 2): -1}
@@ -183,3 +183,104 @@ def emulate_q(T, Nq_plus, Nq_minus, n_ch):
                     v += T["contrib_coef"][c] * R[p][r1 * rows2 + r2]
                 out[ch, s] = v
     return out
+
+
+LDS_J0, LDS_J1 = 157, 13
+
+
+def split_offsets(d):
+    """Independent derivation of descriptor entries 20..47 of a product with
+    a shared index (the per-map offsets in the kernel's LDS units)."""
+    out = np.zeros(28, dtype=np.int64)
+    m1 = [int(x) for x in d[2:2 + d[1]]]
+    m2 = [int(x) for x in d[10:10 + d[9]]]
+    sh1, sh2 = _shape(int(d[0])), _shape(int(d[8]))
+    pair_a = sh1["in0"] == 2
+    base1, base2 = (0, 3) if pair_a else (3, 0)
+    lone1 = sh1["lone0"] if pair_a else sh1["lone1"]   # local index
+    lone2 = sh2["lone1"] if pair_a else sh2["lone0"]
+    others1 = [k for k in range(3) if k != lone1]
+    others2 = [k for k in range(3) if k != lone2]
+    p1, q1 = base1 + others1[0], base1 + others1[1]
+    p2, q2 = base2 + others2[0], base2 + others2[1]
+    ys, zs = base1 + lone1, base2 + lone2
+
+    def unit(mp, q):
+        slots = (mp & 7, (mp >> 3) & 7, (mp >> 6) & 7)
+        return sum(w for s, w in zip(slots, (LDS_J0, LDS_J1, 1)) if s == q)
+
+    def weights(sh, mp):
+        w = []
+        if sh["l4"]:
+            w.append(3 * unit(mp, 5))
+        if sh["l3"]:
+            w.append(3 * unit(mp, 2))
+        return (w + [0, 0])[:2]
+
+    out[0], out[1] = lone1, lone2
+    for m, mp in enumerate(m1):
+        sg = -1 if (mp >> 9) & 1 else 1
+        out[4 + 6 * m:10 + 6 * m] = [unit(mp, p1), unit(mp, q1), unit(mp, zs), *weights(sh1, mp), sg]
+    for m, mp in enumerate(m2):
+        sg = -1 if (mp >> 9) & 1 else 1
+        out[16 + 6 * m:22 + 6 * m] = [unit(mp, ys), unit(mp, p2), unit(mp, q2), *weights(sh2, mp), sg]
+    return out
+
+
+# ---- the kernel's team reduction, simulated lane by lane --------------------
+def _dpp_partner(ctrl, lane):
+    r, i = lane & ~15, lane & 15
+    if ctrl == "row_mirror":
+        return r | (15 - i)
+    if ctrl == "row_half_mirror":
+        return r | (i & 8) | (7 - (i & 7))
+    if ctrl == "quad_mirror":
+        return (lane & ~3) | (3 - (lane & 3))
+    if ctrl == "quad_swap":
+        return lane ^ 1
+    raise ValueError(ctrl)
+
+
+STEPS = {2: ("quad_mirror", "quad_swap"), 3: ("row_half_mirror", "quad_mirror", "quad_swap"),
+         4: ("row_mirror", "row_half_mirror", "quad_mirror", "quad_swap")}
+
+
+def team_reduce(vals, lg):
+    """vals: [64, 16] per-lane partial sums of a wavefront whose teams have
+    2^lg lanes.  Returns {(lane, output index): value} as the kernel writes."""
+    cur = {l: list(vals[l]) for l in range(64)}
+    steps = STEPS[min(lg, 4)]
+    for k, ctrl in zip(range(len(steps) - 1, -1, -1), steps):
+        nxt = {}
+        for l in range(64):
+            upper = (l >> k) & 1
+            n = len(cur[l]) // 2
+            mine, part = cur[l], cur[_dpp_partner(ctrl, l)]
+            keep = mine[n:] if upper else mine[:n]
+            # the partner sends the half it does not keep, i.e. the half I keep
+            recv = part[n:] if upper else part[:n]
+            nxt[l] = [a + b for a, b in zip(keep, recv)]
+        cur = nxt
+    out = {}
+    for l in range(64):
+        if (l & ((1 << lg) - 1)) >= 16:
+            continue
+        v = cur[l]
+        n = len(v)
+        base = 0
+        bits = min(lg, 4)
+        for k in range(bits):
+            base += ((l >> k) & 1) * (16 >> (bits - k))
+        for j in range(n):
+            out[(l, base + j)] = v[j]
+    # cross-row sums of 32- and 64-lane teams
+    if lg >= 5:
+        res = {}
+        for (l, o), v in out.items():
+            tot = v
+            for r in range(1, 1 << (lg - 4)):
+                tot = tot + cur[l + 16 * r][0]
+            res[(l, o)] = tot
+        out = res
+    return out
+

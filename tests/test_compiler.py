@@ -185,3 +185,38 @@ def test_compute_calls_on_host_only_plan_are_state_errors():
     assert tune["fft_line"] == 1 and tune["fft_tile"] == 1024 and tune["split"] == 1
     assert L.nbs_plan_destroy(None) == 0
     assert L.nbs_status_string(3) == b"out of device memory"
+
+
+def test_precomputed_split_offsets():
+    """Descriptor entries 20..47 (per-map LDS offsets the kernel uses for
+    split products) against an independent derivation from masks and maps."""
+    p = host_plan(channels.r52())
+    desc = p.table("prod_desc").reshape(-1, p.params()["prod_ints"])
+    n = 0
+    for d in desc:
+        if d[16] == 1:
+            assert not d[20:].any()
+            continue
+        want = emu.split_offsets(d)
+        assert np.array_equal(d[20:48], want), (d[:20], d[20:], want)
+        n += 1
+    assert n > 300
+
+
+@pytest.mark.parametrize("lg", [2, 3, 4, 5, 6])
+def test_team_reduce_scatter_owns_every_output_once(lg):
+    """The kernel's team sums (DPP reduce-scatter, then cross-row adds),
+    simulated lane by lane: every output of every team is written once, by a
+    lane of that team, with the sum over the team's lanes."""
+    rng = np.random.default_rng(lg)
+    vals = rng.standard_normal((64, 16))
+    out = emu.team_reduce(vals, lg)
+    T = 1 << lg
+    seen = {}
+    for (lane, o), v in out.items():
+        team = lane // T
+        assert (team, o) not in seen
+        seen[(team, o)] = v
+    for team in range(64 // T):
+        for o in range(16):
+            assert np.isclose(seen[(team, o)], vals[team * T:(team + 1) * T, o].sum())
