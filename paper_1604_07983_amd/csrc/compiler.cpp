@@ -407,8 +407,11 @@ std::string compile_channels(const std::vector<ChannelSpec>& chans, const Compil
       };
       auto cls_of = [&](int p) {
         const Shape s1 = shape_of(prods[p].first.mask), s2 = shape_of(prods[p].second.mask);
-        return product_class(s1.K(), s1.rows(), s1.kA == 2 ? s1.loneA : s1.loneB, s1.kA == 2 ? s2.loneB : s2.loneA,
-                             (int)prods[p].first.maps.size(), (int)prods[p].second.maps.size());
+        // lone quarks as local indices (0..2) within their source baryon
+        const bool pairA = s1.kA == 2;
+        const int lone1 = pairA ? s1.loneA : s1.loneB - 3, lone2 = pairA ? s2.loneB - 3 : s2.loneA;
+        return product_class(s1.K(), s1.rows(), lone1, lone2, (int)prods[p].first.maps.size(),
+                             (int)prods[p].second.maps.size());
       };
       std::stable_sort(order_p.begin(), order_p.end(), [&](int a, int b) {
         const int ta = team(a), tb = team(b);
@@ -455,7 +458,7 @@ std::string compile_channels(const std::vector<ChannelSpec>& chans, const Compil
         if (s1.K() == 1) {
           u.cell = 8.0 * (nm1 + nm2) + 64.0 + 32.0;
         } else {
-          const int lone1 = s1.kA == 2 ? s1.loneA : s1.loneB, lone2 = s1.kA == 2 ? s2.loneB : s2.loneA;
+          const int lone1 = s1.kA == 2 ? s1.loneA : s1.loneB - 3, lone2 = s1.kA == 2 ? s2.loneB - 3 : s2.loneA;
           const int np1 = lone1 == 2 ? 8 : 2, np2 = lone2 == 2 ? 8 : 2;
           u.cell = (double)s1.rows() * np1 * nm1 + (double)(16 / s1.rows()) * np2 * nm2 + 32.0;
         }

@@ -519,48 +519,48 @@ __device__ __forceinline__ int row_offset(int r, int wlo, int whi) {
   else return (r & 1) * wlo + ((r >> 1) & 1) * whi + (r >> 2) * kLdsAl;
 }
 
-template <typename T, int R1, int NP1, int NP2, int NM1, int NM2>
+template <typename T, int R1, int NP1, int NP2>
 __device__ __forceinline__ void lane_split_fixed(const cx<T>* slotA, const cx<T>* slotB, const int* d, const int* tp,
-                                                 int y, int z0, int zstep, cx<T> acc[16]) {
+                                                 int y, int z0, int zstep, int nm1, int nm2, cx<T> acc[16]) {
+  // nm1, nm2 (1 or 2 maps per block) are wavefront-uniform: the compiler
+  // packs tasks by class, and the class includes the map counts
   constexpr int R2 = 16 / R1;
   constexpr int KZ = NP2 == 8 ? 3 : 12;
   const int lone1 = d[20], lone2 = d[21];
-  int e1d[NM1][6], e2d[NM2][6];
+  int e1d[2][6], e2d[2][6];
 #pragma unroll
-  for (int m = 0; m < NM1; ++m)
+  for (int m = 0; m < 2; ++m)
 #pragma unroll
-    for (int k = 0; k < 6; ++k) e1d[m][k] = d[24 + 6 * m + k];
+    for (int k = 0; k < 6; ++k) {
+      e1d[m][k] = m < nm1 ? d[24 + 6 * m + k] : 0;
+      e2d[m][k] = m < nm2 ? d[36 + 6 * m + k] : 0;
+    }
+  int ro1[2][R1], ro2[2][R2];
 #pragma unroll
-  for (int m = 0; m < NM2; ++m)
-#pragma unroll
-    for (int k = 0; k < 6; ++k) e2d[m][k] = d[36 + 6 * m + k];
-  int ro1[NM1][R1], ro2[NM2][R2];
-#pragma unroll
-  for (int m = 0; m < NM1; ++m)
+  for (int m = 0; m < 2; ++m) {
 #pragma unroll
     for (int r = 0; r < R1; ++r) ro1[m][r] = row_offset<R1>(r, e1d[m][3], e1d[m][4]);
 #pragma unroll
-  for (int m = 0; m < NM2; ++m)
-#pragma unroll
     for (int r = 0; r < R2; ++r) ro2[m][r] = row_offset<R2>(r, e2d[m][3], e2d[m][4]);
+  }
   // block 1: this lane's pair terms (fixed y), z moves its single quark
-  int off1[NM1][NP1];
-  T cc1[NM1][NP1];
+  int off1[2][NP1];
+  T cc1[2][NP1];
 #pragma unroll
   for (int t = 0; t < NP1; ++t) {
     const int e = tp[pair_index(lone1, y, t)];
     const int jp = e & 15, jq = (e >> 4) & 15;
     const int c = ((e >> 8) & 1) ? -1 : 1;
 #pragma unroll
-    for (int m = 0; m < NM1; ++m) {
+    for (int m = 0; m < 2; ++m) {
       off1[m][t] = jp * e1d[m][0] + jq * e1d[m][1];
       cc1[m][t] = (T)(e1d[m][5] * c);
     }
   }
-  int yo2[NM2];
-  T sg2[NM2];
+  int yo2[2];
+  T sg2[2];
 #pragma unroll
-  for (int m = 0; m < NM2; ++m) {
+  for (int m = 0; m < 2; ++m) {
     yo2[m] = y * e2d[m][0];
     sg2[m] = (T)e2d[m][5];
   }
@@ -573,10 +573,12 @@ __device__ __forceinline__ void lane_split_fixed(const cx<T>* slotA, const cx<T>
 #pragma unroll
     for (int r = 0; r < R2; ++r) e2[r] = cx<T>{0, 0};
 #pragma unroll
-    for (int m = 0; m < NM1; ++m) {
-      const int zo = z * e1d[m][2];
+    for (int m = 0; m < 2; ++m) {
+      if (m < nm1) {
+        const int zo = z * e1d[m][2];
 #pragma unroll
-      for (int t = 0; t < NP1; ++t) add_rows<T, R1>(slotA, off1[m][t] + zo, cc1[m][t], ro1[m], e1);
+        for (int t = 0; t < NP1; ++t) add_rows<T, R1>(slotA, off1[m][t] + zo, cc1[m][t], ro1[m], e1);
+      }
     }
 #pragma unroll
     for (int t = 0; t < NP2; ++t) {
@@ -584,8 +586,8 @@ __device__ __forceinline__ void lane_split_fixed(const cx<T>* slotA, const cx<T>
       const T c = ((e >> 8) & 1) ? (T)-1 : (T)1;
       const int jp = e & 15, jq = (e >> 4) & 15;
 #pragma unroll
-      for (int m = 0; m < NM2; ++m)
-        add_rows<T, R2>(slotB, yo2[m] + jp * e2d[m][1] + jq * e2d[m][2], sg2[m] * c, ro2[m], e2);
+      for (int m = 0; m < 2; ++m)
+        if (m < nm2) add_rows<T, R2>(slotB, yo2[m] + jp * e2d[m][1] + jq * e2d[m][2], sg2[m] * c, ro2[m], e2);
     }
 #pragma unroll
     for (int r1 = 0; r1 < R1; ++r1)
@@ -660,14 +662,9 @@ __device__ __forceinline__ void lane_full(const cx<T>* slotA, const cx<T>* slotB
 
 // Dispatch on the (wavefront-uniform) product class.
 template <typename T, int R1, int NP1, int NP2>
-__device__ __forceinline__ void split_maps(int nmc, const cx<T>* sA, const cx<T>* sB, const int* d, const int* tp, int y,
-                                  int z0, int zs, cx<T> acc[16]) {
-  switch (nmc) {
-    case 0: lane_split_fixed<T, R1, NP1, NP2, 1, 1>(sA, sB, d, tp, y, z0, zs, acc); break;
-    case 1: lane_split_fixed<T, R1, NP1, NP2, 1, 2>(sA, sB, d, tp, y, z0, zs, acc); break;
-    case 2: lane_split_fixed<T, R1, NP1, NP2, 2, 1>(sA, sB, d, tp, y, z0, zs, acc); break;
-    default: lane_split_fixed<T, R1, NP1, NP2, 2, 2>(sA, sB, d, tp, y, z0, zs, acc); break;
-  }
+__device__ __forceinline__ void split_maps(int nmc, const cx<T>* sA, const cx<T>* sB, const int* d, const int* tp,
+                                           int y, int z0, int zs, cx<T> acc[16]) {
+  lane_split_fixed<T, R1, NP1, NP2>(sA, sB, d, tp, y, z0, zs, 1 + (nmc >> 1), 1 + (nmc & 1), acc);
 }
 
 template <typename T>
