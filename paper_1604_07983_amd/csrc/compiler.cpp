@@ -120,14 +120,14 @@ int flavour_count(const Triplet& t, int f) { return (t.f[0] == f) + (t.f[1] == f
 
 // Kernel dispatch class of a block product (see compiler.hpp).
 int product_class(int K, int rows1, int lone1, int lone2, int nm1, int nm2) {
-  if (K == 1) return kClassFull;
   if (nm1 < 1 || nm1 > 2 || nm2 < 1 || nm2 > 2) return kClassSplitAny;
+  if (K == 1) return (nm1 - 1) * 2 + (nm2 - 1);
   const int np1 = lone1 == 2 ? 8 : 2, np2 = lone2 == 2 ? 8 : 2;
   int base = -1;
-  if (rows1 == 4 && np1 == 2 && np2 == 2) base = 1;
-  if (rows1 == 8 && np1 == 2 && np2 == 8) base = 5;
-  if (rows1 == 2 && np1 == 8 && np2 == 2) base = 9;
-  if (rows1 == 4 && np1 == 8 && np2 == 8) base = 13;
+  if (rows1 == 4 && np1 == 2 && np2 == 2) base = 4;
+  if (rows1 == 8 && np1 == 2 && np2 == 8) base = 8;
+  if (rows1 == 2 && np1 == 8 && np2 == 2) base = 12;
+  if (rows1 == 4 && np1 == 8 && np2 == 8) base = 16;
   if (base < 0) return kClassSplitAny;
   return base + (nm1 - 1) * 2 + (nm2 - 1);
 }
@@ -470,7 +470,7 @@ std::string compile_channels(const std::vector<ChannelSpec>& chans, const Compil
         if (!opt.split) break;
         std::vector<TeamUnit> trial = units;
         for (auto& u : trial) {
-          if (u.cls == kClassFull) continue;
+          if (u.cls < kClassFullEnd) continue;
           while ((u.kz + (1 << u.zsl) - 1) >> u.zsl > target && (u.kypad << (u.zsl + 1)) <= kLanesPerTask) ++u.zsl;
         }
         const double t = pack_tasks(trial, opt.waves, nullptr);

@@ -82,12 +82,13 @@ struct DiagramInfo {
 // empty.
 constexpr int kLanesPerTask = 64;
 
-// Product classes (kernel template dispatch): kClassFull = two full
-// projections (K = 1); 1 + 4 b + 2 (nmaps1 - 1) + (nmaps2 - 1) for the split
-// shapes b = 0: 4 x 4 rows, 2 + 2 pair terms (K = 144); b = 1: 8 x 2 rows,
-// 2 + 8 (K = 36); b = 2: 2 x 8 rows, 8 + 2 (K = 36); b = 3: 4 x 4 rows,
-// 8 + 8 (K = 9); kClassSplitAny = any other split product.
-constexpr int kClassFull = 0;
+// Product classes (kernel dispatch; every task holds one class, so the
+// dispatch is wavefront-uniform): 0 .. 3 = two full projections (K = 1),
+// 2 (nmaps1 - 1) + (nmaps2 - 1); 4 + 4 b + 2 (nmaps1 - 1) + (nmaps2 - 1) for
+// the split shapes b = 0: 4 x 4 rows, 2 + 2 pair terms (K = 144); b = 1:
+// 8 x 2 rows, 2 + 8 (K = 36); b = 2: 2 x 8 rows, 8 + 2 (K = 36); b = 3: 4 x 4
+// rows, 8 + 8 (K = 9); kClassSplitAny = any other split product.
+constexpr int kClassFullEnd = 4;
 constexpr int kClassIdle = 30;
 constexpr int kClassSplitAny = 31;
 int product_class(int K, int rows1, int lone1, int lone2, int nm1, int nm2);

@@ -601,8 +601,10 @@ __device__ __forceinline__ void lane_split_fixed(const cx<T>* slotA, const cx<T>
 // shares the terms (lane u takes terms u and u + 16), reduces E1 and E2
 // across the team, and lane 0 forms the 4 x 4 outer product (the other lanes
 // contribute zero to the team sum that follows).
-template <typename T, int NM1, int NM2>
-__device__ __forceinline__ void lane_full(const cx<T>* slotA, const cx<T>* slotB, const int* d, int u, cx<T> acc[16]) {
+template <typename T>
+__device__ __forceinline__ void lane_full(const cx<T>* slotA, const cx<T>* slotB, const int* d, int u, int nm1, int nm2,
+                                          cx<T> acc[16]) {
+  // nm1, nm2 are wavefront-uniform (part of the product class)
   const BlkShape s1 = decode_shape(d[0]), s2 = decode_shape(d[8]);
   int mp1[2] = {d[2], d[3]}, mp2[2] = {d[10], d[11]};
   cx<T> e1[4], e2[4];
@@ -617,13 +619,15 @@ __device__ __forceinline__ void lane_full(const cx<T>* slotA, const cx<T>* slotB
         int j0 = 0, j1 = 0, j2 = 0, j3 = 0, j4 = 0, j5 = 0;
         const int c = s1.kA == 3 ? part_term(3, -1, 0, 0, t, j0, j1, j2) : part_term(3, -1, 0, 0, t, j3, j4, j5);
 #pragma unroll
-        for (int m = 0; m < NM1; ++m) {
-          int ro[4];
-          row_offsets<4>(s1, mp1[m], ro);
-          const int b = pick6(mp1[m] & 7, j0, j1, j2, j3, j4, j5) * kLdsJ0 +
-                        pick6((mp1[m] >> 3) & 7, j0, j1, j2, j3, j4, j5) * kLdsJ1 +
-                        pick6((mp1[m] >> 6) & 7, j0, j1, j2, j3, j4, j5);
-          add_rows<T, 4>(slotA, b, (T)((((mp1[m] >> 9) & 1) ? -1 : 1) * c), ro, e1);
+        for (int m = 0; m < 2; ++m) {
+          if (m < nm1) {
+            int ro[4];
+            row_offsets<4>(s1, mp1[m], ro);
+            const int b = pick6(mp1[m] & 7, j0, j1, j2, j3, j4, j5) * kLdsJ0 +
+                          pick6((mp1[m] >> 3) & 7, j0, j1, j2, j3, j4, j5) * kLdsJ1 +
+                          pick6((mp1[m] >> 6) & 7, j0, j1, j2, j3, j4, j5);
+            add_rows<T, 4>(slotA, b, (T)((((mp1[m] >> 9) & 1) ? -1 : 1) * c), ro, e1);
+          }
         }
       }
       // block 2
@@ -631,13 +635,15 @@ __device__ __forceinline__ void lane_full(const cx<T>* slotA, const cx<T>* slotB
         int j0 = 0, j1 = 0, j2 = 0, j3 = 0, j4 = 0, j5 = 0;
         const int c = s2.kA == 3 ? part_term(3, -1, 0, 0, t, j0, j1, j2) : part_term(3, -1, 0, 0, t, j3, j4, j5);
 #pragma unroll
-        for (int m = 0; m < NM2; ++m) {
-          int ro[4];
-          row_offsets<4>(s2, mp2[m], ro);
-          const int b = pick6(mp2[m] & 7, j0, j1, j2, j3, j4, j5) * kLdsJ0 +
-                        pick6((mp2[m] >> 3) & 7, j0, j1, j2, j3, j4, j5) * kLdsJ1 +
-                        pick6((mp2[m] >> 6) & 7, j0, j1, j2, j3, j4, j5);
-          add_rows<T, 4>(slotB, b, (T)((((mp2[m] >> 9) & 1) ? -1 : 1) * c), ro, e2);
+        for (int m = 0; m < 2; ++m) {
+          if (m < nm2) {
+            int ro[4];
+            row_offsets<4>(s2, mp2[m], ro);
+            const int b = pick6(mp2[m] & 7, j0, j1, j2, j3, j4, j5) * kLdsJ0 +
+                          pick6((mp2[m] >> 3) & 7, j0, j1, j2, j3, j4, j5) * kLdsJ1 +
+                          pick6((mp2[m] >> 6) & 7, j0, j1, j2, j3, j4, j5);
+            add_rows<T, 4>(slotB, b, (T)((((mp2[m] >> 9) & 1) ? -1 : 1) * c), ro, e2);
+          }
         }
       }
     }
@@ -670,20 +676,16 @@ __device__ __forceinline__ void split_maps(int nmc, const cx<T>* sA, const cx<T>
 template <typename T>
 __device__ __forceinline__ void run_product(int cls, const cx<T>* sA, const cx<T>* sB, const int* d, const int* tp, int y,
                                    int z0, int zs, cx<T> acc[16]) {
-  if (cls == 0) {
-    const int nmc = (d[1] - 1) * 2 + (d[9] - 1);
-    if (nmc == 0) lane_full<T, 1, 1>(sA, sB, d, y, acc);
-    else if (nmc == 1) lane_full<T, 1, 2>(sA, sB, d, y, acc);
-    else if (nmc == 2) lane_full<T, 2, 1>(sA, sB, d, y, acc);
-    else lane_full<T, 2, 2>(sA, sB, d, y, acc);
-  } else if (cls < 5) {
-    split_maps<T, 4, 2, 2>(cls - 1, sA, sB, d, tp, y, z0, zs, acc);
-  } else if (cls < 9) {
-    split_maps<T, 8, 2, 8>(cls - 5, sA, sB, d, tp, y, z0, zs, acc);
-  } else if (cls < 13) {
-    split_maps<T, 2, 8, 2>(cls - 9, sA, sB, d, tp, y, z0, zs, acc);
-  } else if (cls < 17) {
-    split_maps<T, 4, 8, 8>(cls - 13, sA, sB, d, tp, y, z0, zs, acc);
+  if (cls < 4) {
+    lane_full<T>(sA, sB, d, y, 1 + (cls >> 1), 1 + (cls & 1), acc);
+  } else if (cls < 8) {
+    split_maps<T, 4, 2, 2>(cls - 4, sA, sB, d, tp, y, z0, zs, acc);
+  } else if (cls < 12) {
+    split_maps<T, 8, 2, 8>(cls - 8, sA, sB, d, tp, y, z0, zs, acc);
+  } else if (cls < 16) {
+    split_maps<T, 2, 8, 2>(cls - 12, sA, sB, d, tp, y, z0, zs, acc);
+  } else if (cls < 20) {
+    split_maps<T, 4, 8, 8>(cls - 16, sA, sB, d, tp, y, z0, zs, acc);
   } else {
     const int rows1 = d[18];
     if (rows1 == 4)
@@ -897,12 +899,12 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
     cx<T> acc[16];
 #pragma unroll
     for (int o = 0; o < 16; ++o) acc[o] = cx<T>{0, 0};
-    if (cls == 0) {
+    if (cls < 4) {
       // full projections: the whole wavefront runs the team code (it
       // shuffles); idle lanes compute on product 0 and drop the result
       const int y = (w >> 12) & 15;
       const int* d = a.prod_desc + (long long)(pbase + (p != 0xfff ? p : 0)) * kProdInts;
-      run_product<T>(0, slotA, slotB, d, tp, y, 0, 1, acc);
+      run_product<T>(cls, slotA, slotB, d, tp, y, 0, 1, acc);
       if (p == 0xfff) {
 #pragma unroll
         for (int o = 0; o < 16; ++o) acc[o] = cx<T>{0, 0};
@@ -911,7 +913,7 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
       const int y = (w >> 12) & 15, z0 = (w >> 19) & 15, zs = 1 << ((w >> 23) & 7);
       run_product<T>(cls, slotA, slotB, a.prod_desc + (long long)(pbase + p) * kProdInts, tp, y, z0, zs, acc);
     }
-    if (cls == 0) {
+    if (cls < 4) {
       // lane_full left the whole product in the team's first lane
       if (p != 0xfff && ((w >> 12) & 15) == 0) {
 #pragma unroll
