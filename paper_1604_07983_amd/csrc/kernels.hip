@@ -842,50 +842,52 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
   const int mq = (G.Lx - qx) % G.Lx + G.Lx * ((G.Ly - qy) % G.Ly + G.Ly * ((G.Lz - qz) % G.Lz));
   const int tid = threadIdx.x;
 
-  // stage the two operator blocks (all loads in flight before the LDS
-  // stores), the group's channel contributions and the pair table
+  // stage the two operator blocks, the group's channel contributions and
+  // the pair table
   const cx<T>* Nq = reinterpret_cast<const cx<T>*>(G.Nq);
   const cx<T>* srcA = Nq + ((long long)(t * a.n_ops + a.group_op1[g]) * G.V + q) * kBlockEntries;
   const cx<T>* srcB = Nq + ((long long)(t * a.n_ops + a.group_op2[g]) * G.V + mq) * kBlockEntries;
   constexpr int kPer = (kBlockEntries + kContractThreads - 1) / kContractThreads;
+  const int gc0 = a.group_ch[g], nch = a.group_ch[g + 1] - gc0;
+  const int cbase = a.ch_contrib[gc0], ncon = a.ch_contrib[gc0 + nch] - cbase;
   {
-    // the block pointers come from the geometry table: state that they
-    // address global memory, so the loads are global loads that may all be
-    // in flight before the LDS stores
+    // every global load of the staging (both blocks, the group's channel
+    // contributions) is issued before the first LDS store.  The block
+    // pointers come from the geometry table: state that they address global
+    // memory, so the loads are global loads that may all be in flight.
     using gptr = const __attribute__((address_space(1))) cx<T>*;
     const gptr gA = (gptr)srcA;
     const gptr gB = (gptr)srcB;
-    cx<T> va[kPer];
+    cx<T> va[kPer], vb[kPer];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       const int i = tid + k * kContractThreads;
       const int ii = i < kBlockEntries ? i : kBlockEntries - 1;
       va[k] = cx<T>{gA[ii].re, gA[ii].im};
+      vb[k] = cx<T>{gB[ii].re, gB[ii].im};
     }
+    const bool has_con = tid < ncon;
+    const int cw = has_con ? a.contrib_prod[cbase + tid] : 0;
+    const double cc = has_con ? a.contrib_coef[cbase + tid] : 0.0;
+    const int co = tid <= nch ? a.ch_contrib[gc0 + tid] - cbase : 0;
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       const int i = tid + k * kContractThreads;
-      if (i < kBlockEntries) slotA[lds_index(i)] = va[k];
+      if (i < kBlockEntries) {
+        slotA[lds_index(i)] = va[k];
+        slotB[lds_index(i)] = vb[k];
+      }
     }
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      const int i = tid + k * kContractThreads;
-      const int ii = i < kBlockEntries ? i : kBlockEntries - 1;
-      va[k] = cx<T>{gB[ii].re, gB[ii].im};
+    if (has_con) {
+      cword[tid] = cw;
+      ccoef[tid] = (T)cc;
     }
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      const int i = tid + k * kContractThreads;
-      if (i < kBlockEntries) slotB[lds_index(i)] = va[k];
+    if (tid <= nch) coff[tid] = co;
+    for (int i = tid + kContractThreads; i < ncon; i += kContractThreads) {
+      cword[i] = a.contrib_prod[cbase + i];
+      ccoef[i] = (T)a.contrib_coef[cbase + i];
     }
   }
-  const int gc0 = a.group_ch[g], nch = a.group_ch[g + 1] - gc0;
-  const int cbase = a.ch_contrib[gc0], ncon = a.ch_contrib[gc0 + nch] - cbase;
-  for (int i = tid; i < ncon; i += kContractThreads) {
-    cword[i] = a.contrib_prod[cbase + i];
-    ccoef[i] = (T)a.contrib_coef[cbase + i];
-  }
-  for (int i = tid; i <= nch; i += kContractThreads) coff[i] = a.ch_contrib[gc0 + i] - cbase;
   build_pair_table(tp, tid, kContractThreads);
   __syncthreads();
 
