@@ -503,6 +503,7 @@ std::string compile_channels(const std::vector<ChannelSpec>& chans, const Compil
       P.max_group_products = std::max(P.max_group_products, (int)prods.size());
       P.max_group_contrib = std::max(P.max_group_contrib, P.ch_contrib.back() - P.ch_contrib[P.group_ch[P.group_ch.size() - 2]]);
       P.max_group_channels = std::max(P.max_group_channels, (int)gch.size());
+      P.max_group_tasks = std::max(P.max_group_tasks, P.group_task.back() - P.group_task[P.group_task.size() - 2]);
       (void)gbase_prod;
       prod_id.clear();
       prods.clear();

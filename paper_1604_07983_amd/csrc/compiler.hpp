@@ -117,6 +117,7 @@ struct Program {
   int max_group_products = 0;
   int max_group_channels = 0;
   int max_group_contrib = 0;
+  int max_group_tasks = 0;
 };
 
 struct CompileOptions {

@@ -697,11 +697,11 @@ __device__ __forceinline__ void run_product(int cls, const cx<T>* sA, const cx<T
   }
 }
 
-size_t contract_lds_bytes(int prec, int max_gprod, int max_gcontrib, int max_gch) {
+size_t contract_lds_bytes(int prec, int max_gprod, int max_gcontrib, int max_gch, int max_gtask) {
   const size_t el = prec == 0 ? sizeof(cd) : sizeof(cf);
   const size_t real = prec == 0 ? sizeof(double) : sizeof(float);
   return el * (2 * (size_t)kLdsBlock + (size_t)max_gprod * 16) + real * max_gcontrib +
-         sizeof(int) * (kPairTable + max_gcontrib + max_gch + 1);
+         sizeof(int) * (kPairTable + max_gcontrib + max_gch + 1 + (size_t)max_gtask * 64);
 }
 
 // The geometry owning logical workgroup `logical` (geometries in order of
@@ -825,6 +825,7 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
   int* tp = reinterpret_cast<int*>(ccoef + a.max_gcontrib);
   int* cword = tp + kPairTable;
   int* coff = cword + a.max_gcontrib;
+  int* tword = coff + a.max_gch + 1;  // the group's task lane words
 
   // consecutive logical workgroups on one XCD (hardware deals workgroups
   // round-robin over the 8 XCDs)
@@ -870,6 +871,14 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
     const int cw = has_con ? a.contrib_prod[cbase + tid] : 0;
     const double cc = has_con ? a.contrib_coef[cbase + tid] : 0.0;
     const int co = tid <= nch ? a.ch_contrib[gc0 + tid] - cbase : 0;
+    const int tw0 = a.group_task[g], ntw = (a.group_task[g + 1] - tw0) * 64;
+    constexpr int kTwPer = 3;  // lane words per thread staged with the blocks
+    int tw[kTwPer];
+#pragma unroll
+    for (int k = 0; k < kTwPer; ++k) {
+      const int i = tid + k * kContractThreads;
+      tw[k] = i < ntw ? a.task_lanes[(long long)tw0 * 64 + i] : 0;
+    }
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       const int i = tid + k * kContractThreads;
@@ -883,6 +892,13 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
       ccoef[tid] = (T)cc;
     }
     if (tid <= nch) coff[tid] = co;
+#pragma unroll
+    for (int k = 0; k < kTwPer; ++k) {
+      const int i = tid + k * kContractThreads;
+      if (i < ntw) tword[i] = tw[k];
+    }
+    for (int i = tid + kTwPer * kContractThreads; i < ntw; i += kContractThreads)
+      tword[i] = a.task_lanes[(long long)tw0 * 64 + i];
     for (int i = tid + kContractThreads; i < ncon; i += kContractThreads) {
       cword[i] = a.contrib_prod[cbase + i];
       ccoef[i] = (T)a.contrib_coef[cbase + i];
@@ -894,7 +910,7 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
   const int pbase = a.group_prod[g];
   const int wave = tid >> 6, lane = tid & 63;
   for (int task = a.group_task[g] + wave; task < a.group_task[g + 1]; task += kContractThreads / 64) {
-    const int w = a.task_lanes[(long long)task * 64 + lane];
+    const int w = tword[(task - a.group_task[g]) * 64 + lane];
     const int p = w & 0xfff, lg = (w >> 16) & 7;
     const int cls = __builtin_amdgcn_readfirstlane((w >> 26) & 31);
     if (cls == kIdleClass) continue;
@@ -1117,7 +1133,7 @@ template <typename T, int NT> hipError_t launch_contract_t(const ContractArgs& a
 }  // namespace
 
 hipError_t launch_contract(int prec, const ContractArgs& a, hipStream_t st) {
-  const size_t lds = contract_lds_bytes(prec, a.max_gprod, a.max_gcontrib, a.max_gch);
+  const size_t lds = contract_lds_bytes(prec, a.max_gprod, a.max_gcontrib, a.max_gch, a.max_gtask);
   if (prec == 0) return a.waves == 8 ? launch_contract_t<double, 512>(a, lds, st) : hipErrorInvalidValue;
   if (a.waves == 4) return launch_contract_t<float, 256>(a, lds, st);
   if (a.waves == 8) return launch_contract_t<float, 512>(a, lds, st);

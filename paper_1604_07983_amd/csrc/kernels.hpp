@@ -70,7 +70,7 @@ struct ContractArgs {
   const int *group_op1, *group_op2, *group_prod, *group_task, *group_ch, *group_channels;
   const int *ch_contrib, *contrib_prod, *prod_desc, *task_lanes;
   const double* contrib_coef;
-  int max_gprod, max_gcontrib, max_gch;
+  int max_gprod, max_gcontrib, max_gch, max_gtask;
   int waves;  // wavefronts the compiled tasks are balanced over
   long long block0, n_chunk;  // logical workgroups [block0, block0 + n_chunk) in this launch
 };
@@ -88,7 +88,7 @@ hipError_t launch_fft_pass(int kind, const FftArgs& a, hipStream_t st);
 // the forward precision-form kind takes sign -1, the mixed kind sign +1).
 bool fft_line_supported(int n);
 hipError_t launch_fft_line(int kind, const FftArgs& a, hipStream_t st);
-size_t contract_lds_bytes(int prec, int max_gprod, int max_gcontrib, int max_gch);
+size_t contract_lds_bytes(int prec, int max_gprod, int max_gcontrib, int max_gch, int max_gtask);
 // Wavefronts per contraction workgroup for a precision (the channel compiler
 // balances each group's tasks over this many).
 int contract_waves(int prec);

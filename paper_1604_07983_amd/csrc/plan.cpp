@@ -243,8 +243,9 @@ nbs_status compile_and_upload(nbs_plan p) {
   c.max_gprod = std::max(1, P.max_group_products);
   c.max_gcontrib = std::max(1, P.max_group_contrib);
   c.max_gch = std::max(1, P.max_group_channels);
+  c.max_gtask = std::max(1, P.max_group_tasks);
   c.waves = p->tune.waves;
-  const size_t lds = nbs::contract_lds_bytes(p->prec, c.max_gprod, c.max_gcontrib, c.max_gch);
+  const size_t lds = nbs::contract_lds_bytes(p->prec, c.max_gprod, c.max_gcontrib, c.max_gch, c.max_gtask);
   if (lds > 160 * 1024) return fail(p, NBS_ERR_UNSUPPORTED, "a channel group needs more LDS than a CU has");
   return hip_check(p, nbs::prepare_kernels(p->prec, c.waves, lds), "kernel attributes");
 }
