@@ -249,10 +249,10 @@ int team_lg(const TeamUnit& u) {
 }
 
 // Packs the products into 64-lane tasks (teams of one size and one class per
-// task), assigns the tasks to the workgroup's wavefronts by longest
-// processing time first and, if lanes is given, emits them round-robin (wave
-// w takes tasks w, w + W, ...; empty slots are all-idle tasks).  Returns the
-// estimated time of the busiest wavefront.
+// task) and, if lanes is given, emits them longest first.  Returns the
+// estimated time of the busiest wavefront when W wavefronts take the tasks
+// in that order, each the next one when it is free (longest processing time
+// first).
 double pack_tasks(const std::vector<TeamUnit>& units, int waves, std::vector<int>* lanes) {
   constexpr double kShuffleStep = 32.0;  // one team-reduction step, same units as cell
   std::vector<int> ord(units.size());
@@ -300,17 +300,9 @@ double pack_tasks(const std::vector<TeamUnit>& units, int waves, std::vector<int
     load[w] += tcost[ti];
   }
   if (lanes) {
-    size_t rounds = 0;
-    for (auto& b : bins) rounds = std::max(rounds, b.size());
-    for (size_t r = 0; r < rounds; ++r)
-      for (int w = 0; w < waves; ++w) {
-        if (r < bins[w].size()) {
-          const auto& tk = tasks[bins[w][r]];
-          lanes->insert(lanes->end(), tk.begin(), tk.end());
-        } else {
-          for (int l = 0; l < kLanesPerTask; ++l) lanes->push_back(0xfff | (kClassIdle << 26));
-        }
-      }
+    // longest first: the kernel's wavefronts claim tasks in this order from
+    // a workgroup counter (greedy list scheduling)
+    for (int ti : by_cost) lanes->insert(lanes->end(), tasks[ti].begin(), tasks[ti].end());
   }
   return *std::max_element(load.begin(), load.end());
 }

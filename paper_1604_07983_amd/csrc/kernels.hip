@@ -701,7 +701,7 @@ size_t contract_lds_bytes(int prec, int max_gprod, int max_gcontrib, int max_gch
   const size_t el = prec == 0 ? sizeof(cd) : sizeof(cf);
   const size_t real = prec == 0 ? sizeof(double) : sizeof(float);
   return el * (2 * (size_t)kLdsBlock + (size_t)max_gprod * 16) + real * max_gcontrib +
-         sizeof(int) * (kPairTable + max_gcontrib + max_gch + 1 + (size_t)max_gtask * 64);
+         sizeof(int) * (kPairTable + max_gcontrib + max_gch + 1 + (size_t)max_gtask * 64 + 1);
 }
 
 // The geometry owning logical workgroup `logical` (geometries in order of
@@ -817,7 +817,7 @@ constexpr int kIdleClass = 30;
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
   constexpr int kContractThreads = NT;
-  extern __shared__ char smem_raw[];
+  extern __shared__ __align__(16) char smem_raw[];
   cx<T>* slotA = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* slotB = slotA + kLdsBlock;
   cx<T>* R = slotB + kLdsBlock;
@@ -826,6 +826,7 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
   int* cword = tp + kPairTable;
   int* coff = cword + a.max_gcontrib;
   int* tword = coff + a.max_gch + 1;  // the group's task lane words
+  int& task_counter = tword[a.max_gtask * 64];
 
   // consecutive logical workgroups on one XCD (hardware deals workgroups
   // round-robin over the 8 XCDs)
@@ -905,12 +906,20 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
     }
   }
   build_pair_table(tp, tid, kContractThreads);
+  if (tid == 0) task_counter = 0;
   __syncthreads();
 
   const int pbase = a.group_prod[g];
-  const int wave = tid >> 6, lane = tid & 63;
-  for (int task = a.group_task[g] + wave; task < a.group_task[g + 1]; task += kContractThreads / 64) {
-    const int w = tword[(task - a.group_task[g]) * 64 + lane];
+  const int lane = tid & 63;
+  const int ntask = a.group_task[g + 1] - a.group_task[g];
+  // every wavefront claims the next task (tasks come longest first); which
+  // wavefront runs a task does not change its arithmetic
+  for (;;) {
+    int claim = 0;
+    if (lane == 0) claim = atomicAdd(&task_counter, 1);
+    const int tix = __builtin_amdgcn_readfirstlane(__shfl(claim, 0));
+    if (tix >= ntask) break;
+    const int w = tword[tix * 64 + lane];
     const int p = w & 0xfff, lg = (w >> 16) & 7;
     const int cls = __builtin_amdgcn_readfirstlane((w >> 26) & 31);
     if (cls == kIdleClass) continue;
