@@ -133,8 +133,9 @@ nbs_status nbs_run_graph(nbs_plan plan, const void* const* prop_u, const void* c
                          const void* const* prop_s, void* const* F_out, void* stream);
 
 /* Measure launch-shape candidates on the device with the caller's
- * propagators and keep the fastest: for the block transforms, the register
- * line kernel or LDS tiles of 512, 1024, 2048 or 4096 elements; for the
+ * propagators and keep the fastest: for the block transforms, the fused x-y
+ * pass over square planes, the register line kernel or LDS tiles of 512,
+ * 1024, 2048 or 4096 elements; for the
  * contraction, with or without splitting a product's walked index over
  * lanes and (precision form) 256- or 512-thread workgroups.  Synchronous;
  * leaves the plan as after nbs_build_blocks.  Results are unchanged up to
@@ -142,9 +143,9 @@ nbs_status nbs_run_graph(nbs_plan plan, const void* const* prop_u, const void* c
 nbs_status nbs_plan_autotune(nbs_plan plan, const void* const* prop_u, const void* const* prop_d,
                              const void* const* prop_s, void* stream);
 
-/* The plan's launch shapes: out[0] register line FFT on/off, out[1] LDS FFT
- * tile elements, out[2] wavefronts per contraction workgroup, out[3] index
- * splitting on/off. */
+/* The plan's launch shapes: out[0] bit 0 register line FFT on/off, bit 1
+ * fused x-y pass for square planes on/off; out[1] LDS FFT tile elements;
+ * out[2] wavefronts per contraction workgroup; out[3] index splitting on/off. */
 nbs_status nbs_plan_tuning(const nbs_plan plan, int32_t out[4]);
 
 /* Release everything the plan owns (waits for its device work). NULL is ok. */

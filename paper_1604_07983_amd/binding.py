@@ -189,7 +189,8 @@ class Plan:
     def tuning(self):
         out = (ctypes.c_int32 * 4)()
         self._check(lib().nbs_plan_tuning(self._h, out), "nbs_plan_tuning")
-        return {"fft_line": out[0], "fft_tile": out[1], "waves": out[2], "split": out[3]}
+        return {"fft_line": out[0] & 1, "fft_plane": (out[0] >> 1) & 1, "fft_tile": out[1], "waves": out[2],
+                "split": out[3]}
 
     def info(self):
         inf = PlanInfo()

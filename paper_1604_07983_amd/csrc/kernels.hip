@@ -220,6 +220,56 @@ __global__ __launch_bounds__(kThreads) void k_fft_line(FftArgs a) {
   for (int k = 0; k < N; ++k) out[base + k * a.inner] = conv<Tout>(cd{v[k].re * f, v[k].im * f});
 }
 
+// The x and y axes of a forward transform in one pass.  Workgroup (plane,
+// field tile) loads the N x N x IB tile (runs of IB fields, so adjacent
+// threads read adjacent fields), transforms every x line, then every y line,
+// each thread one line in registers (fft_reg), and stores the tile back:
+// one HBM read and one write for two axes.  The tile is kept in LDS in the
+// storage type (the precision form keeps complex64 between the axes, as it
+// does between passes); arithmetic is FP64.
+template <int N, int IB, typename T>
+__global__ __launch_bounds__(kThreads) void k_fft_plane(FftPlaneArgs a) {
+  extern __shared__ __align__(16) char smem_plane[];
+  cx<T>* tile = reinterpret_cast<cx<T>*>(smem_plane);  // [y][x][f]
+  const long long n_ftiles = a.inner / IB;
+  const long long wg = a.unit0 + blockIdx.x;
+  const long long plane = wg / n_ftiles, f0 = (wg % n_ftiles) * IB;
+  const cx<T>* in = reinterpret_cast<const cx<T>*>(a.in) + plane * N * N * a.inner + f0;
+  cx<T>* out = reinterpret_cast<cx<T>*>(a.out) + plane * N * N * a.inner + f0;
+  constexpr int kTile = N * N * IB;
+  for (int e = threadIdx.x; e < kTile; e += kThreads) {
+    const int f = e % IB, xy = e / IB;
+    tile[e] = in[(long long)xy * a.inner + f];
+  }
+  __syncthreads();
+  // lines along x: (y, f) -> elements (y N + x) IB + f
+  for (int l = threadIdx.x; l < N * IB; l += kThreads) {
+    const int f = l % IB, y = l / IB;
+    cd v[N];
+#pragma unroll
+    for (int x = 0; x < N; ++x) v[x] = conv<double>(tile[(y * N + x) * IB + f]);
+    fft_reg<N, -1>(v);
+#pragma unroll
+    for (int x = 0; x < N; ++x) tile[(y * N + x) * IB + f] = conv<T>(v[x]);
+  }
+  __syncthreads();
+  // lines along y: (x, f)
+  for (int l = threadIdx.x; l < N * IB; l += kThreads) {
+    const int f = l % IB, x = l / IB;
+    cd v[N];
+#pragma unroll
+    for (int y = 0; y < N; ++y) v[y] = conv<double>(tile[(y * N + x) * IB + f]);
+    fft_reg<N, -1>(v);
+#pragma unroll
+    for (int y = 0; y < N; ++y) tile[(y * N + x) * IB + f] = conv<T>(v[y]);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kTile; e += kThreads) {
+    const int f = e % IB, xy = e / IB;
+    out[(long long)xy * a.inner + f] = tile[e];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Effective blocks and their products (Sec. 3(ii)-(iii), Eqs. (9)-(10)).
 //
@@ -1064,6 +1114,66 @@ bool fft_line_supported(int n) {
   return false;
 }
 
+namespace {
+// fields per workgroup: runs of at least 128 bytes (16 fields at most) in a
+// tile of at most 128 KB of LDS
+template <typename T> constexpr int plane_ib(int n) {
+  int ib = 1;
+  while (ib < 16 && ib * (int)sizeof(cx<T>) < 128) ib *= 2;
+  while (ib > 1 && (long long)n * n * ib * (long long)sizeof(cx<T>) > 128 * 1024) ib /= 2;
+  return ib;
+}
+
+template <int N, typename T> hipError_t launch_plane_t(const FftPlaneArgs& a, hipStream_t st) {
+  constexpr int IB = plane_ib<T>(N);
+  if (a.IB != IB) return hipErrorInvalidValue;
+  const size_t lds = sizeof(cx<T>) * N * N * IB;
+  const long long wgs = a.planes * (a.inner / IB);
+  const long long chunk = kMaxLaunchItems / kThreads;
+  for (long long w0 = 0; w0 < wgs; w0 += chunk) {
+    FftPlaneArgs c = a;
+    c.unit0 = w0;
+    hipLaunchKernelGGL((k_fft_plane<N, IB, T>), dim3((unsigned)(wgs - w0 < chunk ? wgs - w0 : chunk)), dim3(kThreads),
+                       lds, st, c);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+}  // namespace
+
+int fft_plane_fields(int n, long long inner, int kind) {
+  if (kind != 0 && kind != 1) return 0;
+  if (n != 8 && n != 16 && n != 24 && n != 32 && n != 40) return 0;
+  const int ib = kind == 0 ? (n == 8 ? plane_ib<double>(8) : n == 16 ? plane_ib<double>(16) : n == 24 ? plane_ib<double>(24)
+                                      : n == 32 ? plane_ib<double>(32) : plane_ib<double>(40))
+                           : (n == 8 ? plane_ib<float>(8) : n == 16 ? plane_ib<float>(16) : n == 24 ? plane_ib<float>(24)
+                                      : n == 32 ? plane_ib<float>(32) : plane_ib<float>(40));
+  const int el = kind == 0 ? 16 : 8;
+  return inner % ib == 0 && ib * el >= 64 ? ib : 0;
+}
+
+hipError_t launch_fft_plane(int kind, int n, const FftPlaneArgs& a, hipStream_t st) {
+  if (kind == 0) {
+    switch (n) {
+      case 8: return launch_plane_t<8, double>(a, st);
+      case 16: return launch_plane_t<16, double>(a, st);
+      case 24: return launch_plane_t<24, double>(a, st);
+      case 32: return launch_plane_t<32, double>(a, st);
+      case 40: return launch_plane_t<40, double>(a, st);
+    }
+  } else if (kind == 1) {
+    switch (n) {
+      case 8: return launch_plane_t<8, float>(a, st);
+      case 16: return launch_plane_t<16, float>(a, st);
+      case 24: return launch_plane_t<24, float>(a, st);
+      case 32: return launch_plane_t<32, float>(a, st);
+      case 40: return launch_plane_t<40, float>(a, st);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_fft_line(int kind, const FftArgs& a, hipStream_t st) {
   if ((kind == 1 && a.sign > 0) || (kind == 2 && a.sign < 0)) return hipErrorInvalidValue;
   switch (a.n) {
@@ -1116,6 +1226,16 @@ hipError_t prepare_kernels(int prec, int waves, size_t contract_lds) {
   set((const void*)k_fft_pass<double, double>, mx);
   set((const void*)k_fft_pass<float, float>, mx);
   set((const void*)k_fft_pass<float, double>, mx);
+  set((const void*)k_fft_plane<8, plane_ib<double>(8), double>, 128 * 1024);
+  set((const void*)k_fft_plane<16, plane_ib<double>(16), double>, 128 * 1024);
+  set((const void*)k_fft_plane<24, plane_ib<double>(24), double>, 128 * 1024);
+  set((const void*)k_fft_plane<32, plane_ib<double>(32), double>, 128 * 1024);
+  set((const void*)k_fft_plane<40, plane_ib<double>(40), double>, 128 * 1024);
+  set((const void*)k_fft_plane<8, plane_ib<float>(8), float>, 128 * 1024);
+  set((const void*)k_fft_plane<16, plane_ib<float>(16), float>, 128 * 1024);
+  set((const void*)k_fft_plane<24, plane_ib<float>(24), float>, 128 * 1024);
+  set((const void*)k_fft_plane<32, plane_ib<float>(32), float>, 128 * 1024);
+  set((const void*)k_fft_plane<40, plane_ib<float>(40), float>, 128 * 1024);
   if (prec == 0)
     set((const void*)k_contract<double, 512>, (int)contract_lds);
   else if (waves == 8)

@@ -36,6 +36,17 @@ struct FftArgs {
   long long unit0;        // first tile (LDS kernel) or line (register kernel) of this launch
 };
 
+// The x and y axes of a batched transform in one pass: the array is
+// [planes][Ly][Lx][inner]; a workgroup transforms IB consecutive fields of
+// one plane through LDS.  in may equal out.
+struct FftPlaneArgs {
+  const void* in;
+  void* out;
+  long long planes, inner;
+  int IB;
+  long long unit0;  // first workgroup of this launch
+};
+
 // Workgroups per launch stay below this bound, so that workgroups x threads
 // stays below the 2^32 work-items a dispatch can address; larger grids are
 // issued as several launches with an offset.
@@ -87,6 +98,10 @@ hipError_t launch_fft_pass(int kind, const FftArgs& a, hipStream_t st);
 // Lengths with a register-resident kernel, and its launcher (kind as above;
 // the forward precision-form kind takes sign -1, the mixed kind sign +1).
 bool fft_line_supported(int n);
+// Square planes with a fused x-y kernel (forward transforms of the blocks,
+// kinds 0 and 1); fields per workgroup for an inner extent, 0 if none fits.
+int fft_plane_fields(int n, long long inner, int kind);
+hipError_t launch_fft_plane(int kind, int n, const FftPlaneArgs& a, hipStream_t st);
 hipError_t launch_fft_line(int kind, const FftArgs& a, hipStream_t st);
 size_t contract_lds_bytes(int prec, int max_gprod, int max_gcontrib, int max_gch, int max_gtask);
 // Wavefronts per contraction workgroup for a precision (the channel compiler

@@ -41,6 +41,7 @@ struct GeomWork {
 struct Tuning {
   int fft_tile = 1024;  // elements of an LDS tile of k_fft_pass (FP64 pairs)
   int fft_line = 1;     // 1: register line kernel where the length has one
+  int fft_plane = 1;    // 1: fused x-y pass for square planes of the block transforms
   int split = 1;        // 1: compiler may split the walked index of a product over lanes
   int waves = 8;        // wavefronts per contraction workgroup
 };
@@ -158,9 +159,26 @@ nbs_status fft3d(nbs_plan p, int kind_first, int kind_rest, const void* in, void
                  const int L[3], long long inner0, int sign, const double* oscale, long long oscale_div,
                  double gscale, hipStream_t st) {
   const long long V = (long long)L[0] * L[1] * L[2];
-  for (int ax = 0; ax < 3; ++ax) {
+  int ax0 = 0;
+  // square x-y planes of a forward block transform: both axes in one pass
+  const int pib = p->tune.fft_plane && L[0] == L[1] && sign < 0 && oscale == nullptr && gscale == 1.0 &&
+                          kind_first == kind_rest
+                      ? nbs::fft_plane_fields(L[0], inner0, kind_first)
+                      : 0;
+  if (pib > 0) {
+    nbs::FftPlaneArgs pa{};
+    pa.in = in;
+    pa.out = out;
+    pa.planes = batch * L[2];
+    pa.inner = inner0;
+    pa.IB = pib;
+    nbs_status s = hip_check(p, nbs::launch_fft_plane(kind_first, L[0], pa, st), "fft plane");
+    if (s != NBS_OK) return s;
+    ax0 = 2;
+  }
+  for (int ax = ax0; ax < 3; ++ax) {
     nbs::FftArgs a{};
-    a.in = ax == 0 ? in : out;
+    a.in = ax == 0 ? in : out;  // after the fused x-y pass the data is in out
     a.out = out;
     a.n = L[ax];
     long long inner = inner0;
@@ -369,6 +387,9 @@ nbs_status nbs_plan_create(nbs_plan* out, const nbs_geometry* g, int32_t n_geom,
       p->specs[c].src[k] = ch[c].src[k];
     }
   p->tune.waves = nbs::contract_waves(prec == NBS_FP64 ? 0 : 1);
+  // the fused x-y pass pays off for FP64 storage (128-byte runs in 64 KB
+  // tiles at 16^3); for complex64 the separate passes measured faster
+  p->tune.fft_plane = prec == NBS_FP64 ? 1 : 0;
   if (device < -1) { delete p; return NBS_ERR_INVALID; }
   if (device >= 0) {
     int ndev = 0;
@@ -607,12 +628,13 @@ nbs_status nbs_plan_autotune(nbs_plan p, const void* const* prop_u, const void* 
   // 1. forward transforms: register line kernel or LDS tiles of 512 .. 4096
   //    elements (repeating the in-place transform only costs time; the blocks
   //    are rebuilt at the end)
-  struct FftChoice { int line, tile; };
-  const FftChoice fft_cands[] = {{1, 1024}, {0, 512}, {0, 1024}, {0, 2048}, {0, 4096}};
+  struct FftChoice { int plane, line, tile; };
+  const FftChoice fft_cands[] = {{1, 1, 1024}, {0, 1, 1024}, {0, 0, 512}, {0, 0, 1024}, {0, 0, 2048}, {0, 0, 4096}};
   float best_ms = 0;
   FftChoice best_fft = fft_cands[0];
   bool first = true;
   for (const auto& c : fft_cands) {
+    p->tune.fft_plane = c.plane;
     p->tune.fft_line = c.line;
     p->tune.fft_tile = c.tile;
     float ms = 0;
@@ -628,6 +650,7 @@ nbs_status nbs_plan_autotune(nbs_plan p, const void* const* prop_u, const void* 
     if (s != NBS_OK) return finish(s);
     if (first || ms < best_ms) { best_ms = ms; best_fft = c; first = false; }
   }
+  p->tune.fft_plane = best_fft.plane;
   p->tune.fft_line = best_fft.line;
   p->tune.fft_tile = best_fft.tile;
   // 2. contraction: workgroup size (precision form) and index splitting
@@ -657,7 +680,7 @@ nbs_status nbs_plan_autotune(nbs_plan p, const void* const* prop_u, const void* 
 
 nbs_status nbs_plan_tuning(const nbs_plan p, int32_t out[4]) {
   if (!p || !out) return NBS_ERR_INVALID;
-  out[0] = p->tune.fft_line;
+  out[0] = p->tune.fft_line | (p->tune.fft_plane << 1);
   out[1] = p->tune.fft_tile;
   out[2] = p->tune.waves;
   out[3] = p->tune.split;

@@ -103,3 +103,17 @@ def test_state_errors_on_device_plan():
     assert r.plan.workspace_bytes() > 0
     r.close()
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("prec", [binding.NBS_FP64, binding.NBS_FP32_MFMA])
+def test_square_plane_lattice(prec):
+    """8 x 8 x 3: square x-y planes take the fused two-axis transform."""
+    announce("square plane 8x8x3 prec=%d" % prec)
+    L, T = (8, 8, 3), 2
+    dt = np.complex128 if prec == binding.NBS_FP64 else np.complex64
+    props = runner.host_props(L, T, range(T), dtype=dt)
+    chans = channels.r52()
+    Fg = run_gpu(L, T, chans, props, prec)
+    Fo = oracle_F(L, props, chans)
+    err = rel_err_per_channel(Fg, Fo)
+    assert err.max() <= TOL[prec], (err.max(), int(err.argmax()))
