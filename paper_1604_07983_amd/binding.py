@@ -21,7 +21,7 @@ STATUS = {0: "NBS_OK", 1: "NBS_ERR_INVALID", 2: "NBS_ERR_UNSUPPORTED", 3: "NBS_E
 SYMBOLS = ("nbs_plan_create", "nbs_workspace_bytes", "nbs_build_blocks", "nbs_contract_channels",
            "nbs_relative_sum", "nbs_plan_destroy", "nbs_status_string", "nbs_last_error",
            "nbs_plan_info", "nbs_plan_diagrams", "nbs_plan_table", "nbs_plan_params", "nbs_run_graph",
-           "nbs_plan_autotune", "nbs_plan_tuning")
+           "nbs_plan_autotune", "nbs_plan_tuning", "nbs_plan_set_tuning")
 
 
 class NbsError(RuntimeError):
@@ -94,6 +94,8 @@ def lib():
         L.nbs_plan_autotune.restype = I32
         L.nbs_plan_tuning.argtypes = [P, ctypes.POINTER(I32)]
         L.nbs_plan_tuning.restype = I32
+        L.nbs_plan_set_tuning.argtypes = [P, ctypes.POINTER(I32)]
+        L.nbs_plan_set_tuning.restype = I32
         _lib = L
     return _lib
 
@@ -190,7 +192,15 @@ class Plan:
         out = (ctypes.c_int32 * 4)()
         self._check(lib().nbs_plan_tuning(self._h, out), "nbs_plan_tuning")
         return {"fft_line": out[0] & 1, "fft_plane": (out[0] >> 1) & 1, "fft_tile": out[1], "waves": out[2],
-                "split": out[3]}
+                "split": out[3] & 1, "mfma": (out[3] >> 1) & 1}
+
+    def set_tuning(self, **kw):
+        """Change some launch shapes (keys as returned by tuning())."""
+        t = self.tuning()
+        t.update(kw)
+        arr = (ctypes.c_int32 * 4)(int(t["fft_line"]) | (int(t["fft_plane"]) << 1), int(t["fft_tile"]),
+                                   int(t["waves"]), int(t["split"]) | (int(t["mfma"]) << 1))
+        self._check(lib().nbs_plan_set_tuning(self._h, arr), "nbs_plan_set_tuning")
 
     def info(self):
         inf = PlanInfo()

@@ -239,12 +239,13 @@ struct TeamUnit {
   int kypad;    // ky rounded up to 4 or 16
   int kz;       // values of the walked index
   int zsl;      // the walked index is split over 2^zsl lane sets
+  int quad;     // lanes per walker: 4 for matrix-core classes, else 1
   double cell;  // estimated cost of one step of one lane
 };
 
 int team_lg(const TeamUnit& u) {
   int lg = 0;
-  while ((1 << lg) < (u.kypad << u.zsl)) ++lg;
+  while ((1 << lg) < (u.quad * u.kypad << u.zsl)) ++lg;
   return lg;
 }
 
@@ -282,8 +283,9 @@ double pack_tasks(const std::vector<TeamUnit>& units, int waves, std::vector<int
     for (int zs = 0; zs < (1 << u.zsl); ++zs)
       for (int y = 0; y < u.kypad; ++y) {
         const bool busy = y < u.ky && zs < u.kz;
-        tasks.back().push_back(busy ? (u.p | (y << 12) | (lg << 16) | (zs << 19) | (u.zsl << 23) | (u.cls << 26))
-                                    : idle);
+        for (int r = 0; r < u.quad; ++r)
+          tasks.back().push_back(busy ? (u.p | (y << 12) | (lg << 16) | (zs << 19) | (u.zsl << 23) | (u.cls << 26))
+                                      : idle);
       }
     tcost.back() = std::max(tcost.back(), steps(u) * u.cell + lg * kShuffleStep);
   }
@@ -402,8 +404,11 @@ std::string compile_channels(const std::vector<ChannelSpec>& chans, const Compil
         // lone quarks as local indices (0..2) within their source baryon
         const bool pairA = s1.kA == 2;
         const int lone1 = pairA ? s1.loneA : s1.loneB - 3, lone2 = pairA ? s2.loneB - 3 : s2.loneA;
-        return product_class(s1.K(), s1.rows(), lone1, lone2, (int)prods[p].first.maps.size(),
-                             (int)prods[p].second.maps.size());
+        const int c = product_class(s1.K(), s1.rows(), lone1, lone2, (int)prods[p].first.maps.size(),
+                                    (int)prods[p].second.maps.size());
+        if (opt.mfma && c >= 4 && c < 8) return kClassMfmaBegin + (c - 4);
+        if (opt.mfma && c >= 16 && c < 20) return kClassMfmaBegin + 4 + (c - 16);
+        return c;
       };
       std::stable_sort(order_p.begin(), order_p.end(), [&](int a, int b) {
         const int ta = team(a), tb = team(b);
@@ -446,13 +451,15 @@ std::string compile_channels(const std::vector<ChannelSpec>& chans, const Compil
         u.kypad = team(p);
         u.kz = kz_of(p);
         u.zsl = 0;
+        u.quad = class_is_mfma(u.cls) ? 4 : 1;
         const int nm1 = (int)prods[p].first.maps.size(), nm2 = (int)prods[p].second.maps.size();
         if (s1.K() == 1) {
           u.cell = 8.0 * (nm1 + nm2) + 64.0 + 32.0;
         } else {
           const int lone1 = s1.kA == 2 ? s1.loneA : s1.loneB - 3, lone2 = s1.kA == 2 ? s2.loneB - 3 : s2.loneA;
           const int np1 = lone1 == 2 ? 8 : 2, np2 = lone2 == 2 ? 8 : 2;
-          u.cell = (double)s1.rows() * np1 * nm1 + (double)(16 / s1.rows()) * np2 * nm2 + 32.0;
+          u.cell = u.quad == 4 ? (double)np1 * nm1 + np2 * nm2 + 8.0
+                               : (double)s1.rows() * np1 * nm1 + (double)(16 / s1.rows()) * np2 * nm2 + 32.0;
         }
         units.push_back(u);
       }
@@ -463,7 +470,8 @@ std::string compile_channels(const std::vector<ChannelSpec>& chans, const Compil
         std::vector<TeamUnit> trial = units;
         for (auto& u : trial) {
           if (u.cls < kClassFullEnd) continue;
-          while ((u.kz + (1 << u.zsl) - 1) >> u.zsl > target && (u.kypad << (u.zsl + 1)) <= kLanesPerTask) ++u.zsl;
+          while ((u.kz + (1 << u.zsl) - 1) >> u.zsl > target && (u.quad * u.kypad << (u.zsl + 1)) <= kLanesPerTask)
+            ++u.zsl;
         }
         const double t = pack_tasks(trial, opt.waves, nullptr);
         if (t < best_t) {

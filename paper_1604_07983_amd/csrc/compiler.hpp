@@ -89,6 +89,13 @@ constexpr int kLanesPerTask = 64;
 // 8 x 2 rows, 2 + 8 (K = 36); b = 2: 2 x 8 rows, 8 + 2 (K = 36); b = 3: 4 x 4
 // rows, 8 + 8 (K = 9); kClassSplitAny = any other split product.
 constexpr int kClassFullEnd = 4;
+// Precision form with matrix cores: the 4 x 4-row split shapes (b = 0, 3)
+// as 20 + 4 b' + 2 (nmaps1 - 1) + (nmaps2 - 1), b' = 0 for b = 0 and 1 for
+// b = 3.  Their teams are quads: the four lanes of a quad walk one stream of
+// shared indices, lane r building row r of both effective blocks, and the
+// quad's outer products go to v_mfma_f32_4x4x1f32 (16 blocks of 4 x 4).
+constexpr int kClassMfmaBegin = 20, kClassMfmaEnd = 28;
+inline bool class_is_mfma(int c) { return c >= kClassMfmaBegin && c < kClassMfmaEnd; }
 constexpr int kClassIdle = 30;
 constexpr int kClassSplitAny = 31;
 int product_class(int K, int rows1, int lone1, int lone2, int nm1, int nm2);
@@ -124,6 +131,7 @@ struct CompileOptions {
   int max_group_products = 88;  // LDS result buffer bound per group
   int waves = 8;                // wavefronts of a contraction workgroup
   bool split = true;            // may split a product's walked index over lanes
+  bool mfma = false;            // 4 x 4-row split products on matrix cores (precision form)
 };
 
 struct Compiled {

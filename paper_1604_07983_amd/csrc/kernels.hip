@@ -646,6 +646,99 @@ __device__ __forceinline__ void lane_split_fixed(const cx<T>* slotA, const cx<T>
   }
 }
 
+// The 4 x 4-row split shapes of the precision form on matrix cores.  A quad
+// of lanes walks one stream of shared indices (fixed y, z = z0, z0 + zstep,
+// ...); quad lane r builds row r of both effective blocks, E1[r](y, z) and
+// E2[r](y, z), and v_mfma_f32_4x4x1f32 (16 independent 4 x 4 outer products,
+// one per quad: lane 4b + i gives row i of A and column i of B of block b)
+// accumulates E1 E2^T as re.re, re.im, im.re, im.im.  Every lane of the
+// wavefront runs the loop (the matrix instruction is wavefront-wide); lanes
+// of idle quads feed zeros.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int NP1, int NP2>
+__device__ __forceinline__ void lane_split_mfma(const cf* slotA, const cf* slotB, const int* d, const int* tp, int y,
+                                                int z0, int zstep, int nm1, int nm2, int r, bool live, f32x4& crr,
+                                                f32x4& cri, f32x4& cir, f32x4& cii) {
+  constexpr int KZ = NP2 == 8 ? 3 : 12;
+  const int lone1 = d[20], lone2 = d[21];
+  int e1d[2][6], e2d[2][6];
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      e1d[m][k] = m < nm1 ? d[24 + 6 * m + k] : 0;
+      e2d[m][k] = m < nm2 ? d[36 + 6 * m + k] : 0;
+    }
+  int ro1[2], ro2[2];
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    ro1[m] = row_offset<4>(r, e1d[m][3], e1d[m][4]);
+    ro2[m] = row_offset<4>(r, e2d[m][3], e2d[m][4]);
+  }
+  int off1[2][NP1];
+  float cc1[2][NP1];
+#pragma unroll
+  for (int t = 0; t < NP1; ++t) {
+    const int e = tp[pair_index(lone1, y, t)];
+    const int jp = e & 15, jq = (e >> 4) & 15;
+    const int c = ((e >> 8) & 1) ? -1 : 1;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      off1[m][t] = jp * e1d[m][0] + jq * e1d[m][1] + ro1[m];
+      cc1[m][t] = (float)(e1d[m][5] * c);
+    }
+  }
+  int yo2[2];
+  float sg2[2];
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    yo2[m] = y * e2d[m][0] + ro2[m];
+    sg2[m] = (float)e2d[m][5];
+  }
+  const int tz0 = pair_index(lone2, 0, 0);
+  const int nsteps = (KZ + zstep - 1) / zstep;  // the same for every lane of the task
+#pragma unroll 1
+  for (int s = 0; s < nsteps; ++s) {
+    const int zt = z0 + s * zstep;
+    const bool ok = live && zt < KZ;
+    const int z = ok ? zt : 0;
+    cf e1{0.f, 0.f}, e2{0.f, 0.f};
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      if (m < nm1) {
+        const int zo = z * e1d[m][2];
+#pragma unroll
+        for (int t = 0; t < NP1; ++t) {
+          const cf x = slotA[off1[m][t] + zo];
+          e1.re = fmaf(cc1[m][t], x.re, e1.re);
+          e1.im = fmaf(cc1[m][t], x.im, e1.im);
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NP2; ++t) {
+      const int e = tp[tz0 + z * NP2 + t];
+      const float c = ((e >> 8) & 1) ? -1.f : 1.f;
+      const int jp = e & 15, jq = (e >> 4) & 15;
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        if (m < nm2) {
+          const cf x = slotB[yo2[m] + jp * e2d[m][1] + jq * e2d[m][2]];
+          const float cs = sg2[m] * c;
+          e2.re = fmaf(cs, x.re, e2.re);
+          e2.im = fmaf(cs, x.im, e2.im);
+        }
+      }
+    }
+    if (!ok) e1 = e2 = cf{0.f, 0.f};
+    crr = __builtin_amdgcn_mfma_f32_4x4x1f32(e1.re, e2.re, crr, 0, 0, 0);
+    cri = __builtin_amdgcn_mfma_f32_4x4x1f32(e1.re, e2.im, cri, 0, 0, 0);
+    cir = __builtin_amdgcn_mfma_f32_4x4x1f32(e1.im, e2.re, cir, 0, 0, 0);
+    cii = __builtin_amdgcn_mfma_f32_4x4x1f32(e1.im, e2.im, cii, 0, 0, 0);
+  }
+}
+
 // Product of two full projections (K = 1): E1[a1 a3'] and E2[a2 a4'] are
 // sums of the 24 source-tensor terms of one baryon each.  A 16-lane team
 // shares the terms (lane u takes terms u and u + 16), reduces E1 and E2
@@ -858,6 +951,48 @@ __device__ __forceinline__ void team_reduce_store(const cx<T> acc[16], int lg, i
   if (p != 0xfff && (lane & ((1 << lg) - 1)) < 16) R[p * 16 + (lane & 15)] = v;
 }
 
+// Team sums of the matrix-core classes: lane 4 q + j of a quad holds
+// R[i][j] for i = 0..3 of its quad's shared indices.  The four quads of a
+// 16-lane row are added by two DPP row shifts (Hillis-Steele: afterwards the
+// row's last quad holds the row's sum), rows by cross-row shuffles; the last
+// quad of the team's first row writes.
+constexpr int kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+
+__device__ __forceinline__ void quad_team_store(const cf v_in[4], int lg, int lane, int p, cf* R) {
+  cf v[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    v[i] = v_in[i];
+    v[i].re += dpp_move<kDppRowShr4>(v[i].re);
+    v[i].im += dpp_move<kDppRowShr4>(v[i].im);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    v[i].re += dpp_move<kDppRowShr8>(v[i].re);
+    v[i].im += dpp_move<kDppRowShr8>(v[i].im);
+  }
+  if (lg >= 5) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      v[i].re += __shfl_xor(v[i].re, 16);
+      v[i].im += __shfl_xor(v[i].im, 16);
+    }
+  }
+  if (lg >= 6) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      v[i].re += __shfl_xor(v[i].re, 32);
+      v[i].im += __shfl_xor(v[i].im, 32);
+    }
+  }
+  const int tl = lane & ((1 << lg) - 1);
+  if (p != 0xfff && tl >= 12 && tl < 16) {
+    const int j = lane & 3;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) R[p * 16 + i * 4 + j] = v[i];
+  }
+}
+
 // NT threads per workgroup: 512 for FP64 (the two staged blocks take most of
 // the LDS, one workgroup per CU), 256 for the precision form (two workgroups
 // per CU, so one stages while the other computes).  The channel compiler
@@ -976,6 +1111,29 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
     cx<T> acc[16];
 #pragma unroll
     for (int o = 0; o < 16; ++o) acc[o] = cx<T>{0, 0};
+    if constexpr (sizeof(T) == 4) {
+      if (cls >= 20 && cls < 28) {
+        // matrix-core classes (20 + 4 b' + map counts): the whole wavefront
+        // runs the loop; idle lanes use product 0's descriptor and feed zeros
+        const bool live = p != 0xfff;
+        const int* d = a.prod_desc + (long long)(pbase + (live ? p : 0)) * kProdInts;
+        const int y = live ? (w >> 12) & 15 : 0, z0 = (w >> 19) & 15, zs = 1 << ((w >> 23) & 7);
+        const int nmc = (cls - 20) & 3, nm1 = 1 + (nmc >> 1), nm2 = 1 + (nmc & 1);
+        f32x4 crr = {0.f, 0.f, 0.f, 0.f}, cri = crr, cir = crr, cii = crr;
+        const cf* sA = reinterpret_cast<const cf*>(slotA);
+        const cf* sB = reinterpret_cast<const cf*>(slotB);
+        if (cls < 24)
+          lane_split_mfma<2, 2>(sA, sB, d, tp, y, z0, zs, nm1, nm2, lane & 3, live, crr, cri, cir, cii);
+        else
+          lane_split_mfma<8, 8>(sA, sB, d, tp, y, z0, zs, nm1, nm2, lane & 3, live, crr, cri, cir, cii);
+        cf v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = cf{crr[i] - cii[i], cri[i] + cir[i]};
+        const int pt = __shfl(p, lane & ~((1 << lg) - 1));
+        quad_team_store(v, lg, lane, pt, reinterpret_cast<cf*>(R));
+        continue;
+      }
+    }
     if (cls < 4) {
       // full projections: the whole wavefront runs the team code (it
       // shuffles); idle lanes compute on product 0 and drop the result

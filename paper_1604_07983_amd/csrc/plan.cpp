@@ -44,6 +44,7 @@ struct Tuning {
   int fft_plane = 1;    // 1: fused x-y pass for square planes of the block transforms
   int split = 1;        // 1: compiler may split the walked index of a product over lanes
   int waves = 8;        // wavefronts per contraction workgroup
+  int mfma = 0;         // precision form: 4 x 4-row products on matrix cores
 };
 
 }  // namespace
@@ -209,6 +210,7 @@ nbs_status fft3d(nbs_plan p, int kind_first, int kind_rest, const void* in, void
 nbs_status compile_and_upload(nbs_plan p) {
   p->opt.waves = p->tune.waves;
   p->opt.split = p->tune.split != 0;
+  p->opt.mfma = p->prec == NBS_FP32_MFMA && p->tune.mfma != 0;
   Compiled comp;
   std::string msg = nbs::compile_channels(p->specs, p->opt, &comp);
   if (!msg.empty()) return fail(p, NBS_ERR_INVALID, msg);
@@ -390,6 +392,10 @@ nbs_status nbs_plan_create(nbs_plan* out, const nbs_geometry* g, int32_t n_geom,
   // the fused x-y pass pays off for FP64 storage (128-byte runs in 64 KB
   // tiles at 16^3); for complex64 the separate passes measured faster
   p->tune.fft_plane = prec == NBS_FP64 ? 1 : 0;
+  // matrix-core products are an autotuner candidate: measured slower than
+  // the vector loops for these 4 x 4 products (a quad walks a product's
+  // shared indices one step at a time, four times the steps of a lane team)
+  p->tune.mfma = 0;
   if (device < -1) { delete p; return NBS_ERR_INVALID; }
   if (device >= 0) {
     int ndev = 0;
@@ -655,14 +661,16 @@ nbs_status nbs_plan_autotune(nbs_plan p, const void* const* prop_u, const void* 
   p->tune.fft_tile = best_fft.tile;
   // 2. contraction: workgroup size (precision form) and index splitting
   if ((s = enqueue_build(p, prop_u, prop_d, prop_s, st)) != NBS_OK) return finish(s);
-  struct ConChoice { int waves, split; };
-  std::vector<ConChoice> con_cands = {{8, 1}, {8, 0}};
-  if (p->prec == NBS_FP32_MFMA) con_cands = {{4, 1}, {4, 0}, {8, 1}, {8, 0}};
+  struct ConChoice { int waves, split, mfma; };
+  std::vector<ConChoice> con_cands = {{8, 1, 0}, {8, 0, 0}};
+  if (p->prec == NBS_FP32_MFMA)
+    con_cands = {{4, 1, 1}, {4, 0, 1}, {8, 1, 1}, {4, 1, 0}, {4, 0, 0}, {8, 1, 0}, {8, 0, 0}};
   ConChoice best_con = con_cands[0];
   first = true;
   for (const auto& c : con_cands) {
     p->tune.waves = c.waves;
     p->tune.split = c.split;
+    p->tune.mfma = c.mfma;
     if ((s = compile_and_upload(p)) != NBS_OK) return finish(s);
     float ms = 0;
     if ((s = timed([&]() { return enqueue_contract(p, st); }, &ms)) != NBS_OK) return finish(s);
@@ -670,6 +678,7 @@ nbs_status nbs_plan_autotune(nbs_plan p, const void* const* prop_u, const void* 
   }
   p->tune.waves = best_con.waves;
   p->tune.split = best_con.split;
+  p->tune.mfma = best_con.mfma;
   if ((s = compile_and_upload(p)) != NBS_OK) return finish(s);
   // leave the plan built with the chosen shapes
   if ((s = enqueue_build(p, prop_u, prop_d, prop_s, st)) != NBS_OK) return finish(s);
@@ -683,7 +692,33 @@ nbs_status nbs_plan_tuning(const nbs_plan p, int32_t out[4]) {
   out[0] = p->tune.fft_line | (p->tune.fft_plane << 1);
   out[1] = p->tune.fft_tile;
   out[2] = p->tune.waves;
-  out[3] = p->tune.split;
+  out[3] = p->tune.split | (p->tune.mfma << 1);
+  return NBS_OK;
+}
+
+nbs_status nbs_plan_set_tuning(nbs_plan p, const int32_t in[4]) {
+  if (!p || !in) return NBS_ERR_INVALID;
+  const int tile = in[1];
+  if (tile != 512 && tile != 1024 && tile != 2048 && tile != 4096) return fail(p, NBS_ERR_INVALID, "fft tile");
+  const int waves = in[2];
+  if (p->prec == NBS_FP64 ? waves != 8 : (waves != 4 && waves != 8)) return fail(p, NBS_ERR_INVALID, "waves");
+  if ((in[3] >> 1) & 1 && p->prec != NBS_FP32_MFMA) return fail(p, NBS_ERR_INVALID, "matrix cores need the precision form");
+  if (p->device >= 0 && hipSetDevice(p->device) != hipSuccess) return fail(p, NBS_ERR_DEVICE, "hipSetDevice");
+  if (p->device >= 0 && hipDeviceSynchronize() != hipSuccess) return fail(p, NBS_ERR_DEVICE, "synchronize");
+  const Tuning old = p->tune;
+  p->tune.fft_line = in[0] & 1;
+  p->tune.fft_plane = (in[0] >> 1) & 1;
+  p->tune.fft_tile = tile;
+  p->tune.waves = waves;
+  p->tune.split = in[3] & 1;
+  p->tune.mfma = (in[3] >> 1) & 1;
+  drop_graph(p);
+  const nbs_status s = compile_and_upload(p);
+  if (s != NBS_OK) {
+    p->tune = old;
+    (void)compile_and_upload(p);
+    return s;
+  }
   return NBS_OK;
 }
 

@@ -16,6 +16,7 @@ NAMES = ("op_code", "op_nterm", "op_term_trip", "op_term_perm", "op_term_w", "gr
          "group_prod", "group_task", "group_ch", "group_channels", "ch_contrib", "contrib_prod",
          "contrib_coef", "prod_desc", "task_lanes")
 PROD_INTS = 48
+MFMA_BEGIN, MFMA_END = 20, 28
 IDLE_CLASS = 30
 
 EPS = {(0, 1, 2): 1, (1, 2, 0): 1, (2, 0, 1): 1, (0, 2, 1): -1, (2, 1, 0): -1, (1, 0, 2): -1}
@@ -129,6 +130,7 @@ def emulate_q(T, Nq_plus, Nq_minus, n_ch):
             assert len(lgs) == 1, "a task mixes team sizes"
             assert len(cls) == 1, "a task mixes product classes"
             tl = 1 << lgs.pop()
+            cls_t = cls.pop()
             for t0 in range(0, 64, tl):
                 team = [int(w) for w in words[t0:t0 + tl]]
                 ps = {w & 0xFFF for w in team} - {0xFFF}
@@ -145,6 +147,9 @@ def emulate_q(T, Nq_plus, Nq_minus, n_ch):
                 pairA = _shape(int(d[0]))["in0"] == 2
                 covered = []
                 acc = np.zeros(16, dtype=np.complex128)
+                if MFMA_BEGIN <= cls_t < MFMA_END:  # quads: four lanes walk one stream
+                    assert tl >= 16 and all(team[i] == team[i - i % 4] for i in range(len(team)))
+                    team = team[::4]
                 if K == 1:  # the team shares one full-projection product
                     assert sorted(((w >> 12) & 15) for w in team if w & 0xFFF != 0xFFF) == list(range(16))
                     team = [w for w in team if (w >> 12) & 15 == 0]
@@ -284,3 +289,27 @@ def team_reduce(vals, lg):
         out = res
     return out
 
+
+
+def quad_team_reduce(vals, lg):
+    """Matrix-core classes: vals [64, 4] holds, per lane 4 q + j, R[i][j] for
+    i = 0..3 of its quad.  Two DPP row shifts (by 4 and 8 lanes, zero fill)
+    then cross-row adds; returns {(lane, i * 4 + j): value} as written."""
+    cur = [list(v) for v in vals]
+    for sh in (4, 8):
+        nxt = []
+        for l in range(64):
+            src = l - sh
+            same_row = src >= 0 and (src >> 4) == (l >> 4)
+            nxt.append([a + (cur[src][k] if same_row else 0) for k, a in enumerate(cur[l])])
+        cur = nxt
+    for x in (16, 32):
+        if (x == 16 and lg >= 5) or (x == 32 and lg >= 6):
+            cur = [[a + b for a, b in zip(cur[l], cur[l ^ x])] for l in range(64)]
+    out = {}
+    for l in range(64):
+        tl = l & ((1 << lg) - 1)
+        if 12 <= tl < 16:
+            for i in range(4):
+                out[(l, i * 4 + (l & 3))] = cur[l][i]
+    return out

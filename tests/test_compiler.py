@@ -21,8 +21,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 
-def host_plan(chans, L=(4, 4, 4), T=8):
-    return binding.Plan(L, T, chans, device=-1)
+def host_plan(chans, L=(4, 4, 4), T=8, prec=binding.NBS_FP64):
+    return binding.Plan(L, T, chans, prec=prec, device=-1)
 
 
 def test_library_exports_every_declared_symbol():
@@ -99,18 +99,21 @@ def _neg(L, q):
     return ((-x) % L[0]) + L[0] * (((-y) % L[1]) + L[1] * ((-z) % L[2]))
 
 
+@pytest.mark.parametrize("prec", [binding.NBS_FP64, binding.NBS_FP32_MFMA])
 @pytest.mark.parametrize("chans,L,qs", [
     ([channels.WORKED_EXAMPLE, ("p", "p", "p", "p")], (2, 2, 2), None),
     ([("Lambda", "Lambda", "Sigma+", "Sigma-"), ("Xi0", "Sigma0", "Xi-", "Sigma+"),
       ("n", "Xi0", "Lambda", "Lambda")], (2, 2, 2), [0, 3, 5]),
     (channels.r52(), (2, 3, 2), [0, 7]),
 ])
-def test_compiled_program_reproduces_oracle(chans, L, qs):
+def test_compiled_program_reproduces_oracle(chans, L, qs, prec, mfma=False):
     """The compiled program, run by the CPU emulator with the kernel's rules,
     gives the oracle's F~(q) (built from explicit Wick permutations)."""
     rng = np.random.default_rng(101)
     S = ref.random_props(rng, L)
-    p = host_plan(chans, L=L, T=4)
+    p = host_plan(chans, L=L, T=4, prec=prec)
+    if mfma:
+        p.set_tuning(mfma=1)
     T = emu.tables(p)
     Nt = _momentum_operator_blocks(L, S, T)
     V = int(np.prod(L))
@@ -220,3 +223,52 @@ def test_team_reduce_scatter_owns_every_output_once(lg):
     for team in range(64 // T):
         for o in range(16):
             assert np.isclose(seen[(team, o)], vals[team * T:(team + 1) * T, o].sum())
+
+
+@pytest.mark.parametrize("lg", [4, 5, 6])
+def test_quad_team_sums(lg):
+    """Team sums of the matrix-core classes, simulated lane by lane: each of a
+    team's 16 outputs is written once, with the sum over its quads."""
+    rng = np.random.default_rng(10 + lg)
+    vals = rng.standard_normal((64, 4))
+    out = emu.quad_team_reduce(vals, lg)
+    T = 1 << lg
+    seen = {}
+    for (lane, o), v in out.items():
+        key = (lane // T, o)
+        assert key not in seen
+        seen[key] = v
+    for team in range(64 // T):
+        for o in range(16):
+            i, j = divmod(o, 4)
+            want = sum(vals[l, i] for l in range(team * T, (team + 1) * T) if l % 4 == j)
+            assert np.isclose(seen[(team, o)], want)
+
+
+def test_matrix_core_classes_only_where_enabled():
+    """The matrix-core classes appear only in the precision form and only when
+    the tuning enables them (the autotuner's candidate; off by default)."""
+    p = host_plan(channels.r52(), prec=binding.NBS_FP32_MFMA)
+    assert p.tuning()["mfma"] == 0
+    c32 = (p.table("task_lanes") >> 26) & 31
+    assert not ((c32 >= 20) & (c32 < 28)).any()
+    q = host_plan(channels.r52())
+    c64 = (q.table("task_lanes") >> 26) & 31
+    assert not ((c64 >= 20) & (c64 < 28)).any()
+
+
+def test_matrix_core_program_reproduces_oracle():
+    """The precision form's program with matrix-core classes (quad teams)."""
+    test_compiled_program_reproduces_oracle(channels.r52(), (2, 3, 2), [0, 7], binding.NBS_FP32_MFMA, mfma=True)
+    p = host_plan(channels.r52(), prec=binding.NBS_FP32_MFMA)
+    p.set_tuning(mfma=1)
+    c = (p.table("task_lanes") >> 26) & 31
+    assert ((c >= 20) & (c < 28)).mean() > 0.3
+
+
+def test_set_tuning_rejects_bad_shapes():
+    p = host_plan([("p", "p", "p", "p")])
+    for kw in (dict(fft_tile=300), dict(waves=4), dict(mfma=1)):
+        with pytest.raises(binding.NbsError):
+            p.set_tuning(**kw)
+    assert p.tuning()["waves"] == 8

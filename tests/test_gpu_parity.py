@@ -19,10 +19,12 @@ def announce(msg):
     print("[case] " + msg, flush=True)
 
 
-def run_gpu(L, T, chans, props_np, prec, t0=0, t_begin=0, t_count=None):
+def run_gpu(L, T, chans, props_np, prec, t0=0, t_begin=0, t_count=None, tuning=None):
     import torch
     dp = runner.device_props(props_np, prec)
     r = runner.Runner(L, T, chans, prec=prec, t0=t0, t_begin=t_begin, t_count=t_count)
+    if tuning:
+        r.plan.set_tuning(**tuning)
     F = r.run(*dp)
     torch.cuda.synchronize()
     out = F.cpu().numpy()
@@ -117,3 +119,19 @@ def test_square_plane_lattice(prec):
     Fo = oracle_F(L, props, chans)
     err = rel_err_per_channel(Fg, Fo)
     assert err.max() <= TOL[prec], (err.max(), int(err.argmax()))
+
+
+@pytest.mark.parametrize("tuning", [dict(mfma=1), dict(mfma=1, waves=8), dict(split=0, fft_line=0, fft_tile=2048),
+                                    dict(fft_plane=1)])
+def test_precision_form_launch_shapes(tuning):
+    """The precision form under other launch shapes (matrix-core products,
+    512-thread workgroups, no index splitting, LDS-tile transforms, the
+    fused x-y pass) on every R52 channel."""
+    announce("precision form shapes %s" % tuning)
+    L, T = (8, 8, 3), 2
+    props = runner.host_props(L, T, range(T), dtype=np.complex64)
+    chans = channels.r52()
+    Fg = run_gpu(L, T, chans, props, binding.NBS_FP32_MFMA, tuning=tuning)
+    Fo = oracle_F(L, props, chans)
+    err = rel_err_per_channel(Fg, Fo)
+    assert err.max() <= 1e-5, (err.max(), int(err.argmax()))
