@@ -49,3 +49,66 @@ def r52():
 
 # The paper's worked example, Eq. (7): <p Lambda | pbar Xu-bar>.
 WORKED_EXAMPLE = ("p", "Lambda", "p", "Xu")
+
+
+# ---- channel tables from quantum numbers, and from text --------------------
+# Strangeness and twice the third isospin component of the octet operators
+# (Eqs. (2)-(3)).
+OCTET = {
+    "p": (0, 1), "n": (0, -1), "Lambda": (-1, 0), "Sigma+": (-1, 2), "Sigma0": (-1, 0), "Sigma-": (-1, -2),
+    "Xi0": (-2, 1), "Xi-": (-2, -1),
+}
+
+
+def octet_pairs(S, two_Iz, ordered=False):
+    """Two-baryon states (B1, B2) of the octet with total strangeness S and
+    total 2 I_z.  Unordered pairs (B1 listed first in OCTET order) unless
+    ordered=True."""
+    names = list(OCTET)
+    out = []
+    for i, a in enumerate(names):
+        for j, b in enumerate(names):
+            if not ordered and j < i:
+                continue
+            if OCTET[a][0] + OCTET[b][0] == S and OCTET[a][1] + OCTET[b][1] == two_Iz:
+                out.append((a, b))
+    return out
+
+
+def coupled_channels(S, two_Iz, ordered=False):
+    """Every channel <B1 B2 | B3bar B4bar> of one (S, I_z) sector: all sink
+    pairs times all source pairs of the sector."""
+    pairs = octet_pairs(S, two_Iz, ordered)
+    return _block(pairs, pairs)
+
+
+def sectors():
+    """The (S, 2 I_z) sectors with at least one octet pair."""
+    out = []
+    for S in range(0, -5, -1):
+        for tz in range(-4, 5):
+            if octet_pairs(S, tz):
+                out.append((S, tz))
+    return out
+
+
+def parse_table(text):
+    """Channels from text: one per line, four operator names
+    (B1 B2 B3 B4 for <B1 B2 | B3bar B4bar>) separated by blanks or commas;
+    '#' starts a comment.  Unknown names raise ValueError; flavour
+    conservation is checked by the channel compiler (nbs_plan_create)."""
+    out = []
+    for k, line in enumerate(text.splitlines(), 1):
+        line = line.split("#", 1)[0].replace(",", " ").strip()
+        if not line:
+            continue
+        f = line.split()
+        if len(f) != 4 or any(x not in OPS for x in f):
+            raise ValueError("line %d: expected four operator names of %s, got %r" % (k, sorted(OPS), line))
+        out.append(tuple(f))
+    return out
+
+
+def load_table(path):
+    with open(path) as fh:
+        return parse_table(fh.read())
