@@ -107,8 +107,12 @@ nbs_status nbs_workspace_bytes(const nbs_plan plan, size_t* bytes);
  * prop_u/d/s[g]: device pointers, one per geometry, each
  * [t_count][Lz][Ly][Lx][12][12] complex (complex128 for NBS_FP64,
  * complex64 for NBS_FP32_MFMA), owned by the caller and read-only.
- * prop_d / prop_s may alias prop_u.  stream: a hipStream_t (NULL = the
- * default stream); the call is asynchronous on it. */
+ * prop_d / prop_s may alias prop_u.  When prop_d[g] == prop_u[g] for every
+ * geometry (the isospin-symmetric limit S_d = S_u of Sec. 3(i)), only the
+ * canonical operator blocks are built and transformed and n, Sigma-, Xi-
+ * are read as -p, Sigma+, -Xi0 by the contraction (nbs_plan_table
+ * "op_alias", "op_alias_coef").  stream: a hipStream_t (NULL = the default
+ * stream); the call is asynchronous on it. */
 nbs_status nbs_build_blocks(nbs_plan plan, const void* const* prop_u,
                             const void* const* prop_d, const void* const* prop_s,
                             void* stream);

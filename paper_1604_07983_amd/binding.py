@@ -219,7 +219,8 @@ class Plan:
         import numpy as np
         n = ctypes.c_int64()
         self._check(lib().nbs_plan_table(self._h, name.encode(), None, 0, ctypes.byref(n)), "nbs_plan_table")
-        arr = np.zeros(max(1, n.value), dtype=np.float64 if name in ("contrib_coef", "op_term_w") else np.int32)
+        dbl = ("contrib_coef", "op_term_w", "op_alias_coef", "contrib_coef_iso")
+        arr = np.zeros(max(1, n.value), dtype=np.float64 if name in dbl else np.int32)
         self._check(lib().nbs_plan_table(self._h, name.encode(), arr.ctypes.data_as(ctypes.c_void_p), n.value,
                                          ctypes.byref(n)), "nbs_plan_table")
         return arr[:n.value]

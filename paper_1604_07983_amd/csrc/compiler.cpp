@@ -356,6 +356,69 @@ std::string compile_channels(const std::vector<ChannelSpec>& chans, const Compil
   }
   P.n_ops = (int)P.op_code.size();
 
+  // ---- 1b. the isospin-symmetric limit: with S_d = S_u a block depends on
+  // its recipe with d read as u; slots whose recipes agree up to a common
+  // factor are one block (n = -p, Sigma- = Sigma+, Xi- = -Xi0).  Canonical
+  // slots are moved to the front.
+  {
+    const int n = P.n_ops;
+    std::vector<int> alias(n);
+    std::vector<double> coef(n, 1.0);
+    auto key = [&](int s, int k) {
+      const int code = P.op_term_trip[3 * s + k];
+      int f[3] = {code / 9, (code / 3) % 3, code % 3};
+      for (int& x : f) x = x == 1 ? 0 : x;
+      return std::make_pair((f[0] * 3 + f[1]) * 3 + f[2], P.op_term_perm[3 * s + k]);
+    };
+    for (int s = 0; s < n; ++s) {
+      alias[s] = s;
+      for (int s0 = 0; s0 < s; ++s0) {
+        if (alias[s0] != s0 || P.op_nterm[s0] != P.op_nterm[s]) continue;
+        bool same = true;
+        double c = 0.0;
+        for (int k = 0; k < P.op_nterm[s] && same; ++k) {
+          if (key(s, k) != key(s0, k)) same = false;
+          const double r = P.op_term_w[3 * s + k] / P.op_term_w[3 * s0 + k];
+          if (k == 0) c = r;
+          else if (std::fabs(r - c) > 1e-12 * std::fabs(c)) same = false;
+        }
+        if (same) {
+          alias[s] = s0;
+          coef[s] = c;
+          break;
+        }
+      }
+    }
+    // canonical slots first (stable), aliased after
+    std::vector<int> order;
+    for (int s = 0; s < n; ++s)
+      if (alias[s] == s) order.push_back(s);
+    P.n_canon = (int)order.size();
+    for (int s = 0; s < n; ++s)
+      if (alias[s] != s) order.push_back(s);
+    std::vector<int> newpos(n);
+    for (int i = 0; i < n; ++i) newpos[order[i]] = i;
+    Program Q = P;
+    for (int i = 0; i < n; ++i) {
+      const int s = order[i];
+      Q.op_code[i] = P.op_code[s];
+      Q.op_nterm[i] = P.op_nterm[s];
+      for (int k = 0; k < 3; ++k) {
+        Q.op_term_trip[3 * i + k] = P.op_term_trip[3 * s + k];
+        Q.op_term_perm[3 * i + k] = P.op_term_perm[3 * s + k];
+        Q.op_term_w[3 * i + k] = P.op_term_w[3 * s + k];
+      }
+    }
+    Q.op_alias.assign(n, 0);
+    Q.op_alias_coef.assign(n, 1.0);
+    for (int s = 0; s < n; ++s) {
+      Q.op_alias[newpos[s]] = newpos[alias[s]];
+      Q.op_alias_coef[newpos[s]] = coef[s];
+    }
+    P = Q;
+    for (auto& kv : op_slot) kv.second = newpos[kv.second];
+  }
+
   // ---- 2. diagrams and products per sink-operator group --------------------
   std::map<std::pair<int, int>, std::vector<int>> by_sink;
   std::vector<std::pair<int, int>> order;
@@ -497,6 +560,14 @@ std::string compile_channels(const std::vector<ChannelSpec>& chans, const Compil
       }
       P.group_op1.push_back(op_slot[sk.first]);
       P.group_op2.push_back(op_slot[sk.second]);
+      {
+        const int s1 = op_slot[sk.first], s2 = op_slot[sk.second];
+        P.group_op1_iso.push_back(P.op_alias[s1]);
+        P.group_op2_iso.push_back(P.op_alias[s2]);
+        const double f = P.op_alias_coef[s1] * P.op_alias_coef[s2];
+        for (size_t c = P.contrib_coef_iso.size(); c < P.contrib_coef.size(); ++c)
+          P.contrib_coef_iso.push_back(P.contrib_coef[c] * f);
+      }
       P.group_prod.push_back((int)(P.prod_desc.size() / kProdInts));
       P.group_task.push_back((int)(P.task_lanes.size() / kLanesPerTask));
       P.group_ch.push_back((int)P.group_channels.size());

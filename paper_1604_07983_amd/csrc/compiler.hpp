@@ -109,6 +109,12 @@ struct Program {
   std::vector<int> op_term_trip;    // [slot * 3 + k] triplet code
   std::vector<int> op_term_perm;    // [slot * 3 + k] pi(0) | pi(1) << 2 | pi(2) << 4
   std::vector<double> op_term_w;    // [slot * 3 + k]
+  // Isospin-symmetric limit (S_d = S_u, Sec. 3(i)): slot s equals
+  // op_alias_coef[s] times slot op_alias[s]; the n_canon canonical slots
+  // come first and are the only ones built in that limit.
+  std::vector<int> op_alias;
+  std::vector<double> op_alias_coef;
+  int n_canon = 0;
 
   // groups: channels sharing a sink operator pair
   std::vector<int> group_op1, group_op2;  // operator slots (momentum +q, -q)
@@ -119,6 +125,10 @@ struct Program {
   std::vector<int> ch_contrib;            // per group-channel slot + 1, into contrib_*
   std::vector<int> contrib_prod;          // product (local) | rows1 << 16 | label flags << 20
   std::vector<double> contrib_coef;
+  // the same groups read from canonical slots, the alias coefficients of
+  // both operators folded into the channel coefficients
+  std::vector<int> group_op1_iso, group_op2_iso;
+  std::vector<double> contrib_coef_iso;
   std::vector<int> prod_desc;
   std::vector<int> task_lanes;
   int max_group_products = 0;

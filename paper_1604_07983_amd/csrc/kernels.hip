@@ -114,7 +114,7 @@ __global__ __launch_bounds__(kThreads) void k_nbb(NbbArgs a) {
   }
   __syncthreads();
   for (int op = 0; op < a.n_ops; ++op) {
-    cx<T>* out = reinterpret_cast<cx<T>*>(a.Nq) + ((long long)(t * a.n_ops + op) * a.V + site) * kBlockEntries;
+    cx<T>* out = reinterpret_cast<cx<T>*>(a.Nq) + ((long long)(op * a.t_count + t) * a.V + site) * kBlockEntries;
     const int nt = a.op_nterm[op];
     for (int o = threadIdx.x; o < kBlockEntries; o += kThreads) {
       const int al = o / 1728, j0 = (o / 144) % 12, j1 = (o / 12) % 12, j2 = o % 12;
@@ -1032,8 +1032,8 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
   // stage the two operator blocks, the group's channel contributions and
   // the pair table
   const cx<T>* Nq = reinterpret_cast<const cx<T>*>(G.Nq);
-  const cx<T>* srcA = Nq + ((long long)(t * a.n_ops + a.group_op1[g]) * G.V + q) * kBlockEntries;
-  const cx<T>* srcB = Nq + ((long long)(t * a.n_ops + a.group_op2[g]) * G.V + mq) * kBlockEntries;
+  const cx<T>* srcA = Nq + ((long long)(a.group_op1[g] * G.t_count + t) * G.V + q) * kBlockEntries;
+  const cx<T>* srcB = Nq + ((long long)(a.group_op2[g] * G.t_count + t) * G.V + mq) * kBlockEntries;
   constexpr int kPer = (kBlockEntries + kContractThreads - 1) / kContractThreads;
   const int gc0 = a.group_ch[g], nch = a.group_ch[g + 1] - gc0;
   const int cbase = a.ch_contrib[gc0], ncon = a.ch_contrib[gc0 + nch] - cbase;

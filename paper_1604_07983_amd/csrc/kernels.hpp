@@ -13,7 +13,7 @@ constexpr int kThreads = 256;
 constexpr int kMaxOps = 11;
 struct NbbArgs {
   const void* S[3];      // u, d, s propagators: [t_count][V][12][12]
-  void* Nq;              // [t_count][n_ops][V][3456]
+  void* Nq;              // [n_ops][t_count][V][3456]
   int V, t_count, n_ops;
   int n_dq, dq_f1[4], dq_f2[4];    // diquark flavour pairs
   int op_nterm[kMaxOps];
@@ -65,7 +65,7 @@ constexpr int kProdInts = 48;
 // first logical workgroup it owns (logical workgroups of geometry i are
 // [block0, block0 + n_groups * V * t_count), in geometry order).
 struct ContractGeom {
-  const void* Nq;  // [t_count][n_ops][V][3456]
+  const void* Nq;  // [n_ops][t_count][V][3456]
   void* Ft;        // [n_ch][t_count][16][V]
   int V, Lx, Ly, Lz, t_count, pad;
   long long block0;

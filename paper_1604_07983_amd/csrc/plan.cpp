@@ -30,7 +30,7 @@ enum Stage { ST_NEW = 0, ST_BUILT = 1, ST_CONTRACTED = 2 };
 struct GeomWork {
   nbs_geometry g{};
   long long V = 0;
-  void* Nq = nullptr;          // [t_count][n_ops][V][3456] blocks, then N~(q) in place
+  void* Nq = nullptr;          // [n_ops][t_count][V][3456] blocks, then N~(q) in place
   void* Ft = nullptr;          // [n_ch][t_count][16][V] F~_c(q)
   unsigned* maxbits = nullptr; // precision form: [3][t_count] max |Re|, |Im| as float bits
   int* exps = nullptr;         // precision form: [3][t_count] power-of-two exponents
@@ -64,6 +64,8 @@ struct nbs_plan_s {
   std::vector<DevBuf> bufs;
   int* prog = nullptr;     // all int tables of the compiled program, concatenated
   double* coef = nullptr;  // channel coefficients
+  double* coef_iso = nullptr;  // the same with the isospin alias factors
+  bool iso = false;            // last build used the isospin-symmetric limit (prop_d == prop_u)
   int* chan_nf = nullptr;  // [n_ch][3] quark counts
   nbs::ContractGeom* geo = nullptr;
   size_t dev_bytes = 0;
@@ -228,28 +230,40 @@ nbs_status compile_and_upload(nbs_plan p) {
   put("group_task", P.group_task); put("group_ch", P.group_ch); put("group_channels", P.group_channels);
   put("ch_contrib", P.ch_contrib); put("contrib_prod", P.contrib_prod); put("prod_desc", P.prod_desc);
   put("task_lanes", P.task_lanes);
+  put("group_op1_iso", P.group_op1_iso); put("group_op2_iso", P.group_op2_iso);
   int countdown = 0;
   void* prog = nullptr;
   void* coef = nullptr;
   nbs_status s = dev_alloc(p, flat.size() * 4, &prog, &countdown);
   if (s != NBS_OK) return s;
+  void* coef_iso = nullptr;
   if ((s = dev_alloc(p, std::max<size_t>(8, P.contrib_coef.size() * 8), &coef, &countdown)) != NBS_OK) {
     dev_free(p, prog);
+    return s;
+  }
+  if ((s = dev_alloc(p, std::max<size_t>(8, P.contrib_coef_iso.size() * 8), &coef_iso, &countdown)) != NBS_OK) {
+    dev_free(p, prog);
+    dev_free(p, coef);
     return s;
   }
   hipError_t e = hipMemcpy(prog, flat.data(), flat.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess && !P.contrib_coef.empty())
     e = hipMemcpy(coef, P.contrib_coef.data(), P.contrib_coef.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess && !P.contrib_coef_iso.empty())
+    e = hipMemcpy(coef_iso, P.contrib_coef_iso.data(), P.contrib_coef_iso.size() * 8, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     dev_free(p, prog);
     dev_free(p, coef);
+    dev_free(p, coef_iso);
     return fail(p, NBS_ERR_DEVICE, "table upload");
   }
   if (p->prog) dev_free(p, p->prog);
   if (p->coef) dev_free(p, p->coef);
+  if (p->coef_iso) dev_free(p, p->coef_iso);
   p->prog = (int*)prog;
   p->coef = (double*)coef;
+  p->coef_iso = (double*)coef_iso;
   p->prog_off = off;
   nbs::ContractArgs& c = p->con;
   auto T = [&](const char* name) { return (const int*)(p->prog + p->prog_off[name]); };
@@ -272,9 +286,22 @@ nbs_status compile_and_upload(nbs_plan p) {
 
 // ---- the three stages, enqueued on a stream --------------------------------
 
+// The isospin-symmetric limit holds when every geometry's d propagator is
+// the u propagator (the same memory).
+bool isospin_limit(nbs_plan p, const void* const* pu, const void* const* pd) {
+  if (p->comp.prog.n_canon >= p->comp.prog.n_ops) return false;
+  for (size_t i = 0; i < p->gw.size(); ++i)
+    if (pu[i] != pd[i]) return false;
+  return true;
+}
+
 nbs_status enqueue_build(nbs_plan p, const void* const* pu, const void* const* pd, const void* const* ps,
                          hipStream_t st) {
   nbs_status s;
+  // in the isospin-symmetric limit only the canonical operator blocks (the
+  // first n_canon slots) are built and transformed (Sec. 3(i))
+  p->iso = isospin_limit(p, pu, pd);
+  const int n_build = p->iso ? p->comp.prog.n_canon : p->comp.prog.n_ops;
   for (size_t i = 0; i < p->gw.size(); ++i) {
     GeomWork& w = p->gw[i];
     const nbs_geometry& g = w.g;
@@ -284,6 +311,7 @@ nbs_status enqueue_build(nbs_plan p, const void* const* pu, const void* const* p
     a.Nq = w.Nq;
     a.V = (int)w.V;
     a.t_count = g.t_count;
+    a.n_ops = n_build;
     a.scale_exp = nullptr;
     if (p->prec == NBS_FP32_MFMA) {
       if ((s = hip_check(p, nbs::launch_fill_u32(w.maxbits, 0u, 3LL * g.t_count, st), "fill")) != NBS_OK) return s;
@@ -299,15 +327,21 @@ nbs_status enqueue_build(nbs_plan p, const void* const* pu, const void* const* p
     }
     if ((s = hip_check(p, nbs::launch_nbb(p->prec, a, st), "nbb")) != NBS_OK) return s;
     const int kind = p->prec == NBS_FP64 ? 0 : 1;
-    s = fft3d(p, kind, kind, w.Nq, w.Nq, (long long)g.t_count * p->comp.prog.n_ops, g.L, nbs::kBlockEntries, -1,
-              nullptr, 1, 1.0, st);
+    s = fft3d(p, kind, kind, w.Nq, w.Nq, (long long)g.t_count * n_build, g.L, nbs::kBlockEntries, -1, nullptr, 1,
+              1.0, st);
     if (s != NBS_OK) return s;
   }
   return NBS_OK;
 }
 
 nbs_status enqueue_contract(nbs_plan p, hipStream_t st) {
-  return hip_check(p, nbs::launch_contract(p->prec, p->con, st), "contract");
+  nbs::ContractArgs a = p->con;
+  if (p->iso) {
+    a.group_op1 = (const int*)(p->prog + p->prog_off["group_op1_iso"]);
+    a.group_op2 = (const int*)(p->prog + p->prog_off["group_op2_iso"]);
+    a.contrib_coef = p->coef_iso;
+  }
+  return hip_check(p, nbs::launch_contract(p->prec, a, st), "contract");
 }
 
 nbs_status enqueue_relsum(nbs_plan p, void* const* F_out, hipStream_t st) {
@@ -773,7 +807,11 @@ nbs_status nbs_plan_table(const nbs_plan p, const char* name, void* buf, int64_t
   if (!p || !name || !n || (cap > 0 && !buf)) return NBS_ERR_INVALID;
   const auto& P = p->comp.prog;
   const std::string nm(name);
-  const std::vector<double>* dt = nm == "contrib_coef" ? &P.contrib_coef : nm == "op_term_w" ? &P.op_term_w : nullptr;
+  const std::vector<double>* dt = nm == "contrib_coef"       ? &P.contrib_coef
+                                  : nm == "op_term_w"        ? &P.op_term_w
+                                  : nm == "op_alias_coef"    ? &P.op_alias_coef
+                                  : nm == "contrib_coef_iso" ? &P.contrib_coef_iso
+                                                             : nullptr;
   if (dt) {
     *n = (int64_t)dt->size();
     if (cap > 0) std::memcpy(buf, dt->data(), sizeof(double) * std::min<int64_t>(cap, *n));
@@ -784,7 +822,8 @@ nbs_status nbs_plan_table(const nbs_plan p, const char* name, void* buf, int64_t
       {"op_term_perm", &P.op_term_perm}, {"group_op1", &P.group_op1}, {"group_op2", &P.group_op2},
       {"group_prod", &P.group_prod}, {"group_task", &P.group_task}, {"group_ch", &P.group_ch},
       {"group_channels", &P.group_channels}, {"ch_contrib", &P.ch_contrib}, {"contrib_prod", &P.contrib_prod},
-      {"prod_desc", &P.prod_desc}, {"task_lanes", &P.task_lanes}};
+      {"prod_desc", &P.prod_desc}, {"task_lanes", &P.task_lanes}, {"op_alias", &P.op_alias},
+      {"group_op1_iso", &P.group_op1_iso}, {"group_op2_iso", &P.group_op2_iso}};
   auto it = tabs.find(nm);
   if (it == tabs.end()) return NBS_ERR_INVALID;
   *n = (int64_t)it->second->size();

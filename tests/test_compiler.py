@@ -272,3 +272,42 @@ def test_set_tuning_rejects_bad_shapes():
         with pytest.raises(binding.NbsError):
             p.set_tuning(**kw)
     assert p.tuning()["waves"] == 8
+
+
+def test_isospin_aliases_of_the_octet():
+    """With S_d = S_u: n = -p, Sigma- = Sigma+, Xi- = -Xi0 (Sec. 3(i)); the
+    canonical slots come first."""
+    p = host_plan(channels.r52())
+    codes = list(p.table("op_code"))
+    alias = p.table("op_alias")
+    coef = p.table("op_alias_coef")
+    name = {v: k for k, v in channels.OPS.items()}
+    got = {name[c]: (name[codes[alias[s]]], coef[s]) for s, c in enumerate(codes) if alias[s] != s}
+    assert got == {"n": ("p", -1.0), "Sigma-": ("Sigma+", 1.0), "Xi-": ("Xi0", -1.0)}
+    canon = [s for s in range(len(codes)) if alias[s] == s]
+    assert canon == list(range(len(canon))) and len(canon) == 5
+
+
+def test_isospin_program_reproduces_oracle():
+    """The aliased group tables on blocks of the canonical slots only, with
+    S_d = S_u, against the oracle."""
+    rng = np.random.default_rng(202)
+    L = (2, 3, 2)
+    S = ref.random_props(rng, L)
+    S = [S[0], S[0], S[2]]
+    chans = channels.r52()
+    p = host_plan(chans, L=L, T=4)
+    T = emu.tables(p)
+    Nt = _momentum_operator_blocks(L, S, T)
+    Ti = dict(T)
+    Ti["group_op1"], Ti["group_op2"] = p.table("group_op1_iso"), p.table("group_op2_iso")
+    Ti["contrib_coef"] = p.table("contrib_coef_iso")
+    alias = p.table("op_alias")
+    assert all(alias[s] < len([a for a in range(len(alias)) if alias[a] == a]) for s in range(len(alias)))
+    for q in (0, 5):
+        mq = _neg(L, q)
+        got = emu.emulate_q(Ti, [n[q] for n in Nt], [n[mq] for n in Nt], len(chans))
+        qv = (q % L[0], (q // L[0]) % L[1], q // (L[0] * L[1]))
+        want = oracle.correlators_at_q(L, S, chans, qv)
+        err = np.linalg.norm(got - want, axis=1) / np.linalg.norm(want, axis=1)
+        assert err.max() < 1e-12, (q, err.max())
