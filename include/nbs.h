@@ -142,7 +142,8 @@ nbs_status nbs_run_graph(nbs_plan plan, const void* const* prop_u, const void* c
  * 1024, 2048 or 4096 elements; for the
  * contraction, with or without splitting a product's walked index over
  * lanes and (precision form) 256- or 512-thread workgroups and matrix-core
- * products on or off.  Synchronous;
+ * products on or off, then the ranges of sink-operator groups one
+ * workgroup walks.  Synchronous;
  * leaves the plan as after nbs_build_blocks.  Results are unchanged up to
  * rounding order (the channel sums keep their order). */
 nbs_status nbs_plan_autotune(nbs_plan plan, const void* const* prop_u, const void* const* prop_d,
@@ -151,14 +152,19 @@ nbs_status nbs_plan_autotune(nbs_plan plan, const void* const* prop_u, const voi
 /* The plan's launch shapes: out[0] bit 0 register line FFT on/off, bit 1
  * fused x-y pass for square planes on/off; out[1] LDS FFT tile elements;
  * out[2] wavefronts per contraction workgroup; out[3] bit 0 index splitting
- * on/off, bit 1 (precision form) 4 x 4-row products on matrix cores on/off. */
+ * on/off, bit 1 (precision form) 4 x 4-row products on matrix cores on/off,
+ * bits 2-3 the contraction workgroups per (slice, momentum): 0 one that
+ * walks every sink-operator group, keeping an operator block in LDS while
+ * consecutive groups share it; 1 one per run of groups with the same first
+ * operator; 2 one per group. */
 nbs_status nbs_plan_tuning(const nbs_plan plan, int32_t out[4]);
 
 /* Set the launch shapes (same encoding as nbs_plan_tuning) instead of
  * measuring them: waits for the plan's device work, recompiles the channel
  * program for the new shapes; blocks already built stay valid.  Rejects
  * unknown tiles, wavefront counts other than 8 (FP64) or 4 / 8 (precision
- * form), and matrix-core products outside the precision form. */
+ * form), matrix-core products outside the precision form and group-range
+ * modes above 2. */
 nbs_status nbs_plan_set_tuning(nbs_plan plan, const int32_t in[4]);
 
 /* Release everything the plan owns (waits for its device work). NULL is ok. */

@@ -435,6 +435,11 @@ std::string compile_channels(const std::vector<ChannelSpec>& chans, const Compil
   P.ch_contrib.push_back(0);
   std::set<Block> all_blocks[2];
 
+  // groups sorted by their operator slots: consecutive groups that share the
+  // first operator let the contraction keep its block in LDS
+  std::stable_sort(order.begin(), order.end(), [&](const std::pair<int, int>& x, const std::pair<int, int>& y) {
+    return std::make_pair(op_slot[x.first], op_slot[x.second]) < std::make_pair(op_slot[y.first], op_slot[y.second]);
+  });
   for (auto& sk : order) {
     const std::vector<int>& chs = by_sink[sk];
     // a group is flushed when its product list would exceed the LDS result buffer

@@ -10,6 +10,8 @@
 //               scale of the precision form and its exact undo
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "cx.hpp"
 #include "fft.hpp"
 #include "fft_reg.hpp"
@@ -847,8 +849,8 @@ size_t contract_lds_bytes(int prec, int max_gprod, int max_gcontrib, int max_gch
          sizeof(int) * (kPairTable + max_gcontrib + max_gch + 1 + (size_t)max_gtask * 64 + 1);
 }
 
-// The geometry owning logical workgroup `logical` (geometries in order of
-// their first workgroup).  The table is read with vector loads; every field
+// The geometry owning (slice, momentum) pair `logical` (geometries in
+// order of their first pair).  The table is read with vector loads; every field
 // is moved to scalar registers explicitly (it is wavefront-uniform), which
 // keeps vector registers free for the product loops.
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -993,6 +995,30 @@ __device__ __forceinline__ void quad_team_store(const cf v_in[4], int lg, int la
   }
 }
 
+// The contraction's dynamic LDS: the two operator blocks, the group's
+// products, its channel contributions (coefficients, words, offsets per
+// channel), the pair table, the task lane words and the task counter.
+template <typename T> struct ContractLds {
+  cx<T>*slotA, *slotB, *R;
+  T* ccoef;
+  int *tp, *cword, *coff, *tword, *counter;
+};
+
+template <typename T, typename Args>
+__device__ __forceinline__ ContractLds<T> contract_lds(char* base, const Args& a) {
+  ContractLds<T> l;
+  l.slotA = reinterpret_cast<cx<T>*>(base);
+  l.slotB = l.slotA + kLdsBlock;
+  l.R = l.slotB + kLdsBlock;
+  l.ccoef = reinterpret_cast<T*>(l.R + a.max_gprod * 16);
+  l.tp = reinterpret_cast<int*>(l.ccoef + a.max_gcontrib);
+  l.cword = l.tp + kPairTable;
+  l.coff = l.cword + a.max_gcontrib;
+  l.tword = l.coff + a.max_gch + 1;
+  l.counter = l.tword + a.max_gtask * 64;
+  return l;
+}
+
 // NT threads per workgroup: 512 for FP64 (the two staged blocks take most of
 // the LDS, one workgroup per CU), 256 for the precision form (two workgroups
 // per CU, so one stages while the other computes).  The channel compiler
@@ -1003,15 +1029,6 @@ template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
   constexpr int kContractThreads = NT;
   extern __shared__ __align__(16) char smem_raw[];
-  cx<T>* slotA = reinterpret_cast<cx<T>*>(smem_raw);
-  cx<T>* slotB = slotA + kLdsBlock;
-  cx<T>* R = slotB + kLdsBlock;
-  T* ccoef = reinterpret_cast<T*>(R + a.max_gprod * 16);
-  int* tp = reinterpret_cast<int*>(ccoef + a.max_gcontrib);
-  int* cword = tp + kPairTable;
-  int* coff = cword + a.max_gcontrib;
-  int* tword = coff + a.max_gch + 1;  // the group's task lane words
-  int& task_counter = tword[a.max_gtask * 64];
 
   // consecutive logical workgroups on one XCD (hardware deals workgroups
   // round-robin over the 8 XCDs)
@@ -1020,24 +1037,56 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
   const long long local = (b % 8) * (nb8 / 8) + b / 8;
   if (local >= a.n_chunk) return;
   const long long logical = a.block0 + local;
-  const ContractGeom G = find_geometry(a.geo, a.n_geom, logical);
-  const long long lb = logical - G.block0;
-  const int g = (int)(lb % a.n_groups);
-  const long long qt = lb / a.n_groups;
+  // consecutive logical workgroups share (slice, momentum): chunk-minor
+  const long long qtl = logical / a.n_gchunk;
+  const int chunk = (int)(logical - qtl * a.n_gchunk);
+  build_pair_table(contract_lds<T>(smem_raw, a).tp, threadIdx.x, kContractThreads);
+
+  // the workgroup walks its chunk of sink-operator groups for its (q,
+  // slice); groups come sorted by their first operator, and block A stays
+  // in LDS while it does not change
+  const ContractGeom G = find_geometry(a.geo, a.n_geom, qtl);
+  const long long qt = qtl - G.block0;
   const int t = (int)(qt / G.V), q = (int)(qt % G.V);
   const int qx = q % G.Lx, qy = (q / G.Lx) % G.Ly, qz = q / (G.Lx * G.Ly);
   const int mq = (G.Lx - qx) % G.Lx + G.Lx * ((G.Ly - qy) % G.Ly + G.Ly * ((G.Lz - qz) % G.Lz));
-  const int tid = threadIdx.x;
-
+  const int gbeg = a.gchunk[chunk], gend = a.gchunk[chunk + 1];
+  for (int g = gbeg; g < gend; ++g) {
+  // in double precision the arguments are read again from the argument
+  // segment in every group (through a pointer the compiler cannot follow),
+  // so that scalar registers need not hold them across the product loop
+  using kargs = const __attribute__((address_space(4))) ContractArgs*;
+  kargs ka = (kargs)__builtin_amdgcn_kernarg_segment_ptr();
+  if constexpr (sizeof(T) == 8) asm volatile("" : "+s"(ka));
+  const __attribute__((address_space(4))) ContractArgs& A = *ka;
+  const ContractLds<T> lds = contract_lds<T>(smem_raw, A);
+  cx<T>* const slotA = lds.slotA;
+  cx<T>* const slotB = lds.slotB;
+  cx<T>* const R = lds.R;
+  T* const ccoef = lds.ccoef;
+  const int* const tp = lds.tp;
+  int* const cword = lds.cword;
+  int* const coff = lds.coff;
+  int* const tword = lds.tword;
+  int& task_counter = *lds.counter;
+  const bool newA = g == gbeg || A.group_op1[g] != A.group_op1[g - 1];
+  // in double precision the thread index is made opaque per group so that
+  // per-thread addresses are recomputed here instead of being held in
+  // registers across the product loop (where they would spill)
+  int tid = threadIdx.x;
+  if constexpr (sizeof(T) == 8) asm volatile("" : "+v"(tid));
   // stage the two operator blocks, the group's channel contributions and
   // the pair table
   const cx<T>* Nq = reinterpret_cast<const cx<T>*>(G.Nq);
-  const cx<T>* srcA = Nq + ((long long)(a.group_op1[g] * G.t_count + t) * G.V + q) * kBlockEntries;
-  const cx<T>* srcB = Nq + ((long long)(a.group_op2[g] * G.t_count + t) * G.V + mq) * kBlockEntries;
+  const cx<T>* srcA = Nq + ((long long)(A.group_op1[g] * G.t_count + t) * G.V + q) * kBlockEntries;
+  const cx<T>* srcB = Nq + ((long long)(A.group_op2[g] * G.t_count + t) * G.V + mq) * kBlockEntries;
   constexpr int kPer = (kBlockEntries + kContractThreads - 1) / kContractThreads;
-  const int gc0 = a.group_ch[g], nch = a.group_ch[g + 1] - gc0;
-  const int cbase = a.ch_contrib[gc0], ncon = a.ch_contrib[gc0 + nch] - cbase;
-  {
+  const int gc0 = A.group_ch[g], nch = A.group_ch[g + 1] - gc0;
+  const int cbase = A.ch_contrib[gc0], ncon = A.ch_contrib[gc0 + nch] - cbase;
+  // two staging paths, with and without block A, so that neither keeps
+  // registers for a block it does not load
+  auto stage = [&](auto with_a) {
+    constexpr bool kA = decltype(with_a)::value;
     // every global load of the staging (both blocks, the group's channel
     // contributions) is issued before the first LDS store.  The block
     // pointers come from the geometry table: state that they address global
@@ -1045,31 +1094,31 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
     using gptr = const __attribute__((address_space(1))) cx<T>*;
     const gptr gA = (gptr)srcA;
     const gptr gB = (gptr)srcB;
-    cx<T> va[kPer], vb[kPer];
+    cx<T> va[kA ? kPer : 1], vb[kPer];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       const int i = tid + k * kContractThreads;
       const int ii = i < kBlockEntries ? i : kBlockEntries - 1;
-      va[k] = cx<T>{gA[ii].re, gA[ii].im};
+      if constexpr (kA) va[k] = cx<T>{gA[ii].re, gA[ii].im};
       vb[k] = cx<T>{gB[ii].re, gB[ii].im};
     }
     const bool has_con = tid < ncon;
-    const int cw = has_con ? a.contrib_prod[cbase + tid] : 0;
-    const double cc = has_con ? a.contrib_coef[cbase + tid] : 0.0;
-    const int co = tid <= nch ? a.ch_contrib[gc0 + tid] - cbase : 0;
-    const int tw0 = a.group_task[g], ntw = (a.group_task[g + 1] - tw0) * 64;
+    const int cw = has_con ? A.contrib_prod[cbase + tid] : 0;
+    const double cc = has_con ? A.contrib_coef[cbase + tid] : 0.0;
+    const int co = tid <= nch ? A.ch_contrib[gc0 + tid] - cbase : 0;
+    const int tw0 = A.group_task[g], ntw = (A.group_task[g + 1] - tw0) * 64;
     constexpr int kTwPer = 3;  // lane words per thread staged with the blocks
     int tw[kTwPer];
 #pragma unroll
     for (int k = 0; k < kTwPer; ++k) {
       const int i = tid + k * kContractThreads;
-      tw[k] = i < ntw ? a.task_lanes[(long long)tw0 * 64 + i] : 0;
+      tw[k] = i < ntw ? A.task_lanes[(long long)tw0 * 64 + i] : 0;
     }
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       const int i = tid + k * kContractThreads;
       if (i < kBlockEntries) {
-        slotA[lds_index(i)] = va[k];
+        if constexpr (kA) slotA[lds_index(i)] = va[k];
         slotB[lds_index(i)] = vb[k];
       }
     }
@@ -1084,19 +1133,22 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
       if (i < ntw) tword[i] = tw[k];
     }
     for (int i = tid + kTwPer * kContractThreads; i < ntw; i += kContractThreads)
-      tword[i] = a.task_lanes[(long long)tw0 * 64 + i];
+      tword[i] = A.task_lanes[(long long)tw0 * 64 + i];
     for (int i = tid + kContractThreads; i < ncon; i += kContractThreads) {
-      cword[i] = a.contrib_prod[cbase + i];
-      ccoef[i] = (T)a.contrib_coef[cbase + i];
+      cword[i] = A.contrib_prod[cbase + i];
+      ccoef[i] = (T)A.contrib_coef[cbase + i];
     }
-  }
-  build_pair_table(tp, tid, kContractThreads);
+  };
+  if (newA)
+    stage(std::true_type{});
+  else
+    stage(std::false_type{});
   if (tid == 0) task_counter = 0;
   __syncthreads();
 
-  const int pbase = a.group_prod[g];
+  const int pbase = A.group_prod[g];
   const int lane = tid & 63;
-  const int ntask = a.group_task[g + 1] - a.group_task[g];
+  const int ntask = A.group_task[g + 1] - A.group_task[g];
   // every wavefront claims the next task (tasks come longest first); which
   // wavefront runs a task does not change its arithmetic
   for (;;) {
@@ -1116,7 +1168,7 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
         // matrix-core classes (20 + 4 b' + map counts): the whole wavefront
         // runs the loop; idle lanes use product 0's descriptor and feed zeros
         const bool live = p != 0xfff;
-        const int* d = a.prod_desc + (long long)(pbase + (live ? p : 0)) * kProdInts;
+        const int* d = A.prod_desc + (long long)(pbase + (live ? p : 0)) * kProdInts;
         const int y = live ? (w >> 12) & 15 : 0, z0 = (w >> 19) & 15, zs = 1 << ((w >> 23) & 7);
         const int nmc = (cls - 20) & 3, nm1 = 1 + (nmc >> 1), nm2 = 1 + (nmc & 1);
         f32x4 crr = {0.f, 0.f, 0.f, 0.f}, cri = crr, cir = crr, cii = crr;
@@ -1138,7 +1190,7 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
       // full projections: the whole wavefront runs the team code (it
       // shuffles); idle lanes compute on product 0 and drop the result
       const int y = (w >> 12) & 15;
-      const int* d = a.prod_desc + (long long)(pbase + (p != 0xfff ? p : 0)) * kProdInts;
+      const int* d = A.prod_desc + (long long)(pbase + (p != 0xfff ? p : 0)) * kProdInts;
       run_product<T>(cls, slotA, slotB, d, tp, y, 0, 1, acc);
       if (p == 0xfff) {
 #pragma unroll
@@ -1146,7 +1198,7 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
       }
     } else if (p != 0xfff) {
       const int y = (w >> 12) & 15, z0 = (w >> 19) & 15, zs = 1 << ((w >> 23) & 7);
-      run_product<T>(cls, slotA, slotB, a.prod_desc + (long long)(pbase + p) * kProdInts, tp, y, z0, zs, acc);
+      run_product<T>(cls, slotA, slotB, A.prod_desc + (long long)(pbase + p) * kProdInts, tp, y, z0, zs, acc);
     }
     if (cls < 4) {
       // lane_full left the whole product in the team's first lane
@@ -1166,8 +1218,8 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
   // summing every 8th contribution, then a fixed-order shuffle reduction.
   // The geometry is read again here rather than kept live through the
   // product loop above, where registers are scarce.
-  const ContractGeom G2 = find_geometry(a.geo, a.n_geom, logical);
-  const long long qt2 = (logical - G2.block0) / a.n_groups;
+  const ContractGeom G2 = find_geometry(A.geo, A.n_geom, qtl);
+  const long long qt2 = qtl - G2.block0;
   const int t2 = (int)(qt2 / G2.V), q2 = (int)(qt2 % G2.V);
   cx<T>* Ft = reinterpret_cast<cx<T>*>(G2.Ft);
   for (int i0 = 0; i0 < nch * 16 * 8; i0 += kContractThreads) {
@@ -1195,9 +1247,11 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
       v.im += __shfl_xor(v.im, dd);
     }
     if (cl < nch && sub == 0) {
-      const int ch = a.group_channels[gc0 + cl];
+      const int ch = A.group_channels[gc0 + cl];
       Ft[(((long long)ch * G2.t_count + t2) * 16 + s) * G2.V + q2] = v;
     }
+  }
+  __syncthreads();  // LDS is restaged for the next group
   }
 }
 

@@ -61,9 +61,9 @@ constexpr int kLdsJ0 = 157, kLdsJ1 = 13, kLdsAl = 1888, kLdsBlock = 2 * kLdsAl;
 // Integers per block-product descriptor (layout documented in compiler.hpp).
 constexpr int kProdInts = 48;
 
-// One geometry of a contraction launch: its blocks, its F~ output and the
-// first logical workgroup it owns (logical workgroups of geometry i are
-// [block0, block0 + n_groups * V * t_count), in geometry order).
+// One geometry of a contraction launch: its blocks, its F~ output and its
+// first (slice, momentum) pair: geometry i owns the pairs [block0, block0 +
+// V * t_count), in geometry order.
 struct ContractGeom {
   const void* Nq;  // [n_ops][t_count][V][3456]
   void* Ft;        // [n_ch][t_count][16][V]
@@ -77,7 +77,11 @@ constexpr int kMaxGeom = 32;
 struct ContractArgs {
   const ContractGeom* geo;  // device table, n_geom entries
   int n_geom, n_ops, n_groups;
-  long long n_blocks;  // sum over geometries of n_groups * V * t_count
+  long long n_blocks;  // n_gchunk times the sum over geometries of V * t_count
+  // the sink-operator groups split into n_gchunk consecutive ranges
+  // [gchunk[c], gchunk[c + 1]), one workgroup per range and (slice, momentum)
+  const int* gchunk;
+  int n_gchunk;
   const int *group_op1, *group_op2, *group_prod, *group_task, *group_ch, *group_channels;
   const int *ch_contrib, *contrib_prod, *prod_desc, *task_lanes;
   const double* contrib_coef;

@@ -45,6 +45,10 @@ struct Tuning {
   int split = 1;        // 1: compiler may split the walked index of a product over lanes
   int waves = 8;        // wavefronts per contraction workgroup
   int mfma = 0;         // precision form: 4 x 4-row products on matrix cores
+  // contraction workgroups per (slice, momentum): 0 one walking every
+  // sink-operator group, 1 one per run of groups with the same first
+  // operator, 2 one per group
+  int gchunk = 0;
 };
 
 }  // namespace
@@ -68,6 +72,7 @@ struct nbs_plan_s {
   bool iso = false;            // last build used the isospin-symmetric limit (prop_d == prop_u)
   int* chan_nf = nullptr;  // [n_ch][3] quark counts
   nbs::ContractGeom* geo = nullptr;
+  long long n_qt = 0;  // (slice, momentum) pairs over all geometries
   size_t dev_bytes = 0;
   std::map<std::string, size_t> prog_off;  // table name -> offset (ints) into prog
   nbs::NbbArgs nbb{};                      // geometry-independent part
@@ -207,6 +212,19 @@ nbs_status fft3d(nbs_plan p, int kind_first, int kind_rest, const void* in, void
   return NBS_OK;
 }
 
+// Boundaries of the ranges of groups one contraction workgroup walks (mode
+// as Tuning::gchunk): [0, n), the runs of equal first operator, or single
+// groups.
+std::vector<int> group_chunks(const std::vector<int>& op1, int mode) {
+  const int n = (int)op1.size();
+  std::vector<int> b{0};
+  for (int g = 1; g < n; ++g)
+    if (mode == 2 || (mode == 1 && op1[g] != op1[g - 1])) b.push_back(g);
+  b.push_back(n);
+  if (n == 0) b = {0, 0};
+  return b;
+}
+
 // Compile the channel table with the plan's options and (device plans)
 // upload its tables, replacing earlier ones.
 nbs_status compile_and_upload(nbs_plan p) {
@@ -231,6 +249,8 @@ nbs_status compile_and_upload(nbs_plan p) {
   put("ch_contrib", P.ch_contrib); put("contrib_prod", P.contrib_prod); put("prod_desc", P.prod_desc);
   put("task_lanes", P.task_lanes);
   put("group_op1_iso", P.group_op1_iso); put("group_op2_iso", P.group_op2_iso);
+  const std::vector<int> gchunk = group_chunks(P.group_op1, p->tune.gchunk);
+  put("gchunk", gchunk);
   int countdown = 0;
   void* prog = nullptr;
   void* coef = nullptr;
@@ -273,6 +293,9 @@ nbs_status compile_and_upload(nbs_plan p) {
   c.group_task = T("group_task"); c.group_ch = T("group_ch"); c.group_channels = T("group_channels");
   c.ch_contrib = T("ch_contrib"); c.contrib_prod = T("contrib_prod"); c.prod_desc = T("prod_desc");
   c.task_lanes = T("task_lanes");
+  c.gchunk = T("gchunk");
+  c.n_gchunk = (int)gchunk.size() - 1;
+  c.n_blocks = p->n_qt * c.n_gchunk;
   c.contrib_coef = p->coef;
   c.max_gprod = std::max(1, P.max_group_products);
   c.max_gcontrib = std::max(1, P.max_group_contrib);
@@ -430,6 +453,8 @@ nbs_status nbs_plan_create(nbs_plan* out, const nbs_geometry* g, int32_t n_geom,
   // the vector loops for these 4 x 4 products (a quad walks a product's
   // shared indices one step at a time, four times the steps of a lane team)
   p->tune.mfma = 0;
+  // workgroups that walk every group measured fastest in both forms
+  p->tune.gchunk = 0;
   if (device < -1) { delete p; return NBS_ERR_INVALID; }
   if (device >= 0) {
     int ndev = 0;
@@ -485,11 +510,10 @@ nbs_status nbs_plan_create(nbs_plan* out, const nbs_geometry* g, int32_t n_geom,
   // workspace of every geometry
   const size_t el = prec == NBS_FP64 ? 16 : 8;
   size_t need = (1 << 22);
-  long long n_blocks = 0;
-  const long long n_groups = (long long)P.group_prod.size() - 1;
+  long long n_qt = 0;
   for (auto& w : p->gw) {
     need += (size_t)w.g.t_count * nt * w.V * nbs::kBlockEntries * el + (size_t)n_ch * w.g.t_count * 16 * w.V * el;
-    n_blocks += n_groups * w.V * w.g.t_count;
+    n_qt += w.V * w.g.t_count;
   }
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) { (void)hipGetLastError(); free_b = (size_t)-1; }
@@ -533,7 +557,7 @@ nbs_status nbs_plan_create(nbs_plan* out, const nbs_geometry* g, int32_t n_geom,
     geo[i].t_count = w.g.t_count;
     geo[i].pad = 0;
     geo[i].block0 = b0;
-    b0 += n_groups * w.V * w.g.t_count;
+    b0 += w.V * w.g.t_count;
   }
   hipError_t e = hipMemcpy(p->chan_nf, nf.data(), nf.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->geo, geo.data(), sizeof(nbs::ContractGeom) * n_geom, hipMemcpyHostToDevice);
@@ -541,10 +565,10 @@ nbs_status nbs_plan_create(nbs_plan* out, const nbs_geometry* g, int32_t n_geom,
     (void)hipGetLastError();
     return bail(NBS_ERR_DEVICE);
   }
+  p->n_qt = n_qt;
   if ((s = compile_and_upload(p)) != NBS_OK) return bail(s);
   p->con.geo = p->geo;
   p->con.n_geom = n_geom;
-  p->con.n_blocks = n_blocks;
   *out = p;
   return NBS_OK;
 }
@@ -713,6 +737,18 @@ nbs_status nbs_plan_autotune(nbs_plan p, const void* const* prop_u, const void* 
   p->tune.waves = best_con.waves;
   p->tune.split = best_con.split;
   p->tune.mfma = best_con.mfma;
+  // 3. with those: the ranges of groups a workgroup walks
+  const int gdefault = p->tune.gchunk;
+  int best_g = gdefault;
+  for (int gc = 0; gc < 3; ++gc) {
+    if (gc == gdefault) continue;
+    p->tune.gchunk = gc;
+    if ((s = compile_and_upload(p)) != NBS_OK) return finish(s);
+    float ms = 0;
+    if ((s = timed([&]() { return enqueue_contract(p, st); }, &ms)) != NBS_OK) return finish(s);
+    if (ms < best_ms) { best_ms = ms; best_g = gc; }
+  }
+  p->tune.gchunk = best_g;
   if ((s = compile_and_upload(p)) != NBS_OK) return finish(s);
   // leave the plan built with the chosen shapes
   if ((s = enqueue_build(p, prop_u, prop_d, prop_s, st)) != NBS_OK) return finish(s);
@@ -726,7 +762,7 @@ nbs_status nbs_plan_tuning(const nbs_plan p, int32_t out[4]) {
   out[0] = p->tune.fft_line | (p->tune.fft_plane << 1);
   out[1] = p->tune.fft_tile;
   out[2] = p->tune.waves;
-  out[3] = p->tune.split | (p->tune.mfma << 1);
+  out[3] = p->tune.split | (p->tune.mfma << 1) | (p->tune.gchunk << 2);
   return NBS_OK;
 }
 
@@ -737,6 +773,7 @@ nbs_status nbs_plan_set_tuning(nbs_plan p, const int32_t in[4]) {
   const int waves = in[2];
   if (p->prec == NBS_FP64 ? waves != 8 : (waves != 4 && waves != 8)) return fail(p, NBS_ERR_INVALID, "waves");
   if ((in[3] >> 1) & 1 && p->prec != NBS_FP32_MFMA) return fail(p, NBS_ERR_INVALID, "matrix cores need the precision form");
+  if (in[3] < 0 || (in[3] >> 2) > 2) return fail(p, NBS_ERR_INVALID, "group ranges");
   if (p->device >= 0 && hipSetDevice(p->device) != hipSuccess) return fail(p, NBS_ERR_DEVICE, "hipSetDevice");
   if (p->device >= 0 && hipDeviceSynchronize() != hipSuccess) return fail(p, NBS_ERR_DEVICE, "synchronize");
   const Tuning old = p->tune;
@@ -746,6 +783,7 @@ nbs_status nbs_plan_set_tuning(nbs_plan p, const int32_t in[4]) {
   p->tune.waves = waves;
   p->tune.split = in[3] & 1;
   p->tune.mfma = (in[3] >> 1) & 1;
+  p->tune.gchunk = in[3] >> 2;
   drop_graph(p);
   const nbs_status s = compile_and_upload(p);
   if (s != NBS_OK) {

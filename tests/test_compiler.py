@@ -268,10 +268,26 @@ def test_matrix_core_program_reproduces_oracle():
 
 def test_set_tuning_rejects_bad_shapes():
     p = host_plan([("p", "p", "p", "p")])
-    for kw in (dict(fft_tile=300), dict(waves=4), dict(mfma=1)):
+    for kw in (dict(fft_tile=300), dict(waves=4), dict(mfma=1), dict(gchunk=3)):
         with pytest.raises(binding.NbsError):
             p.set_tuning(**kw)
     assert p.tuning()["waves"] == 8
+
+
+def test_group_range_modes():
+    """Contraction workgroups per (slice, momentum): by default one that
+    walks every group; every mode is accepted and reported back."""
+    assert host_plan([("p", "p", "p", "p")]).tuning()["gchunk"] == 0
+    p = host_plan(channels.r52(), prec=binding.NBS_FP32_MFMA)
+    assert p.tuning()["gchunk"] == 0
+    for m in (1, 2, 0):
+        p.set_tuning(gchunk=m)
+        assert p.tuning()["gchunk"] == m
+    # groups come sorted by their operator slots, so that a workgroup that
+    # walks them meets each first operator in one run
+    o1, o2 = p.table("group_op1"), p.table("group_op2")
+    pairs = list(zip(o1.tolist(), o2.tolist()))
+    assert pairs == sorted(pairs) and len(set(pairs)) == len(pairs)
 
 
 def test_isospin_aliases_of_the_octet():

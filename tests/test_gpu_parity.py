@@ -124,7 +124,7 @@ def test_square_plane_lattice(prec):
 
 
 @pytest.mark.parametrize("tuning", [dict(mfma=1), dict(mfma=1, waves=8), dict(split=0, fft_line=0, fft_tile=2048),
-                                    dict(fft_plane=1)])
+                                    dict(fft_plane=1), dict(gchunk=1), dict(gchunk=2, waves=8)])
 def test_precision_form_launch_shapes(tuning):
     """The precision form under other launch shapes (matrix-core products,
     512-thread workgroups, no index splitting, LDS-tile transforms, the
@@ -137,6 +137,21 @@ def test_precision_form_launch_shapes(tuning):
     Fo = oracle_F(L, props, chans)
     err = rel_err_per_channel(Fg, Fo)
     assert err.max() <= 1e-5, (err.max(), int(err.argmax()))
+
+
+@pytest.mark.parametrize("gchunk", [1, 2])
+def test_fp64_group_ranges(gchunk):
+    """Double precision with workgroups that walk one run of sink-operator
+    groups with the same first operator, or a single group, on every R52
+    channel."""
+    announce("fp64 group ranges %d" % gchunk)
+    L, T = (6, 4, 5), 2
+    props = runner.host_props(L, T, range(T), dtype=np.complex128)
+    chans = channels.r52()
+    Fg = run_gpu(L, T, chans, props, binding.NBS_FP64, tuning=dict(gchunk=gchunk))
+    Fo = oracle_F(L, props, chans)
+    err = rel_err_per_channel(Fg, Fo)
+    assert err.max() <= 1e-12, (err.max(), int(err.argmax()))
 
 
 @pytest.mark.parametrize("prec", [binding.NBS_FP64, binding.NBS_FP32_MFMA])
