@@ -155,8 +155,8 @@ nbs_status nbs_plan_autotune(nbs_plan plan, const void* const* prop_u, const voi
  * on/off, bit 1 (precision form) 4 x 4-row products on matrix cores on/off,
  * bits 2-3 the contraction workgroups per (slice, momentum): 0 one that
  * walks every sink-operator group, keeping an operator block in LDS while
- * consecutive groups share it; 1 one per run of groups with the same first
- * operator; 2 one per group. */
+ * consecutive groups share it; 1 one per run of groups in which one block
+ * stays; 2 one per group. */
 nbs_status nbs_plan_tuning(const nbs_plan plan, int32_t out[4]);
 
 /* Set the launch shapes (same encoding as nbs_plan_tuning) instead of

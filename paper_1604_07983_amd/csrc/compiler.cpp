@@ -249,6 +249,51 @@ int team_lg(const TeamUnit& u) {
   return lg;
 }
 
+// Order in which a contraction workgroup walks the sink-operator pairs
+// (operator slots at +q and -q).  A step that keeps one of the two blocks
+// loads one block instead of two, so the walk moves between pairs that share
+// a slot on the same side, choosing the candidate with the fewest unvisited
+// neighbours (so that few pairs are left stranded), and jumps only when no
+// such pair is left.  Every start is tried; the walk with the fewest block
+// loads (ties: the earlier start) is returned as indices into pairs.
+std::vector<int> walk_order(const std::vector<std::pair<int, int>>& pairs) {
+  const int n = (int)pairs.size();
+  auto shares = [&](int i, int j) { return pairs[i].first == pairs[j].first || pairs[i].second == pairs[j].second; };
+  std::vector<int> best;
+  int best_loads = 0;
+  for (int s = 0; s < n; ++s) {
+    std::vector<char> used(n, 0);
+    std::vector<int> walk{s};
+    used[s] = 1;
+    int loads = 2;
+    for (int step = 1; step < n; ++step) {
+      const int cur = walk.back();
+      int pick = -1, pick_deg = 0;
+      bool pick_shares = false;
+      for (int j = 0; j < n; ++j) {
+        if (used[j]) continue;
+        int deg = 0;
+        for (int k = 0; k < n; ++k)
+          if (!used[k] && k != j && shares(j, k)) ++deg;
+        const bool sh = shares(cur, j);
+        if (pick < 0 || (sh && !pick_shares) || (sh == pick_shares && deg < pick_deg)) {
+          pick = j;
+          pick_deg = deg;
+          pick_shares = sh;
+        }
+      }
+      loads += (pairs[pick].first != pairs[cur].first) + (pairs[pick].second != pairs[cur].second);
+      used[pick] = 1;
+      walk.push_back(pick);
+    }
+    if (best.empty() || loads < best_loads) {
+      best = walk;
+      best_loads = loads;
+    }
+  }
+  return best;
+}
+
 // Packs the products into 64-lane tasks (teams of one size and one class per
 // task) and, if lanes is given, emits them longest first.  Returns the
 // estimated time of the busiest wavefront when W wavefronts take the tasks
@@ -435,11 +480,14 @@ std::string compile_channels(const std::vector<ChannelSpec>& chans, const Compil
   P.ch_contrib.push_back(0);
   std::set<Block> all_blocks[2];
 
-  // groups sorted by their operator slots: consecutive groups that share the
-  // first operator let the contraction keep its block in LDS
-  std::stable_sort(order.begin(), order.end(), [&](const std::pair<int, int>& x, const std::pair<int, int>& y) {
-    return std::make_pair(op_slot[x.first], op_slot[x.second]) < std::make_pair(op_slot[y.first], op_slot[y.second]);
-  });
+  {
+    std::vector<std::pair<int, int>> slots;
+    for (const auto& k : order) slots.emplace_back(op_slot[k.first], op_slot[k.second]);
+    const std::vector<int> w = walk_order(slots);
+    std::vector<std::pair<int, int>> walked;
+    for (int i : w) walked.push_back(order[i]);
+    order = walked;
+  }
   for (auto& sk : order) {
     const std::vector<int>& chs = by_sink[sk];
     // a group is flushed when its product list would exceed the LDS result buffer

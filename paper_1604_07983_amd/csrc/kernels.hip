@@ -1043,8 +1043,9 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
   build_pair_table(contract_lds<T>(smem_raw, a).tp, threadIdx.x, kContractThreads);
 
   // the workgroup walks its chunk of sink-operator groups for its (q,
-  // slice); groups come sorted by their first operator, and block A stays
-  // in LDS while it does not change
+  // slice); the compiler orders the groups so that consecutive ones share an
+  // operator where possible, and a block stays in LDS while its operator
+  // does not change
   const ContractGeom G = find_geometry(a.geo, a.n_geom, qtl);
   const long long qt = qtl - G.block0;
   const int t = (int)(qt / G.V), q = (int)(qt % G.V);
@@ -1083,10 +1084,10 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
   constexpr int kPer = (kBlockEntries + kContractThreads - 1) / kContractThreads;
   const int gc0 = A.group_ch[g], nch = A.group_ch[g + 1] - gc0;
   const int cbase = A.ch_contrib[gc0], ncon = A.ch_contrib[gc0 + nch] - cbase;
-  // two staging paths, with and without block A, so that neither keeps
+  // staging paths with and without each block, so that none keeps
   // registers for a block it does not load
-  auto stage = [&](auto with_a) {
-    constexpr bool kA = decltype(with_a)::value;
+  auto stage = [&](auto with_a, auto with_b) {
+    constexpr bool kA = decltype(with_a)::value, kB = decltype(with_b)::value;
     // every global load of the staging (both blocks, the group's channel
     // contributions) is issued before the first LDS store.  The block
     // pointers come from the geometry table: state that they address global
@@ -1094,13 +1095,13 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
     using gptr = const __attribute__((address_space(1))) cx<T>*;
     const gptr gA = (gptr)srcA;
     const gptr gB = (gptr)srcB;
-    cx<T> va[kA ? kPer : 1], vb[kPer];
+    cx<T> va[kA ? kPer : 1], vb[kB ? kPer : 1];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       const int i = tid + k * kContractThreads;
       const int ii = i < kBlockEntries ? i : kBlockEntries - 1;
       if constexpr (kA) va[k] = cx<T>{gA[ii].re, gA[ii].im};
-      vb[k] = cx<T>{gB[ii].re, gB[ii].im};
+      if constexpr (kB) vb[k] = cx<T>{gB[ii].re, gB[ii].im};
     }
     const bool has_con = tid < ncon;
     const int cw = has_con ? A.contrib_prod[cbase + tid] : 0;
@@ -1119,7 +1120,7 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
       const int i = tid + k * kContractThreads;
       if (i < kBlockEntries) {
         if constexpr (kA) slotA[lds_index(i)] = va[k];
-        slotB[lds_index(i)] = vb[k];
+        if constexpr (kB) slotB[lds_index(i)] = vb[k];
       }
     }
     if (has_con) {
@@ -1139,10 +1140,15 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
       ccoef[i] = (T)A.contrib_coef[cbase + i];
     }
   };
-  if (newA)
-    stage(std::true_type{});
+  const bool newB = g == gbeg || A.group_op2[g] != A.group_op2[g - 1];
+  if (newA && newB)
+    stage(std::true_type{}, std::true_type{});
+  else if (newA)
+    stage(std::true_type{}, std::false_type{});
+  else if (newB)
+    stage(std::false_type{}, std::true_type{});
   else
-    stage(std::false_type{});
+    stage(std::false_type{}, std::false_type{});
   if (tid == 0) task_counter = 0;
   __syncthreads();
 

@@ -46,8 +46,8 @@ struct Tuning {
   int waves = 8;        // wavefronts per contraction workgroup
   int mfma = 0;         // precision form: 4 x 4-row products on matrix cores
   // contraction workgroups per (slice, momentum): 0 one walking every
-  // sink-operator group, 1 one per run of groups with the same first
-  // operator, 2 one per group
+  // sink-operator group, 1 one per run of groups in which one operator
+  // block stays, 2 one per group
   int gchunk = 0;
 };
 
@@ -213,13 +213,13 @@ nbs_status fft3d(nbs_plan p, int kind_first, int kind_rest, const void* in, void
 }
 
 // Boundaries of the ranges of groups one contraction workgroup walks (mode
-// as Tuning::gchunk): [0, n), the runs of equal first operator, or single
-// groups.
-std::vector<int> group_chunks(const std::vector<int>& op1, int mode) {
+// as Tuning::gchunk): [0, n), the runs in which one operator block stays,
+// or single groups.
+std::vector<int> group_chunks(const std::vector<int>& op1, const std::vector<int>& op2, int mode) {
   const int n = (int)op1.size();
   std::vector<int> b{0};
   for (int g = 1; g < n; ++g)
-    if (mode == 2 || (mode == 1 && op1[g] != op1[g - 1])) b.push_back(g);
+    if (mode == 2 || (mode == 1 && op1[g] != op1[g - 1] && op2[g] != op2[g - 1])) b.push_back(g);
   b.push_back(n);
   if (n == 0) b = {0, 0};
   return b;
@@ -249,7 +249,7 @@ nbs_status compile_and_upload(nbs_plan p) {
   put("ch_contrib", P.ch_contrib); put("contrib_prod", P.contrib_prod); put("prod_desc", P.prod_desc);
   put("task_lanes", P.task_lanes);
   put("group_op1_iso", P.group_op1_iso); put("group_op2_iso", P.group_op2_iso);
-  const std::vector<int> gchunk = group_chunks(P.group_op1, p->tune.gchunk);
+  const std::vector<int> gchunk = group_chunks(P.group_op1, P.group_op2, p->tune.gchunk);
   put("gchunk", gchunk);
   int countdown = 0;
   void* prog = nullptr;

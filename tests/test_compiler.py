@@ -283,11 +283,17 @@ def test_group_range_modes():
     for m in (1, 2, 0):
         p.set_tuning(gchunk=m)
         assert p.tuning()["gchunk"] == m
-    # groups come sorted by their operator slots, so that a workgroup that
-    # walks them meets each first operator in one run
+    # the groups come in an order in which consecutive groups share an
+    # operator block where possible: R52's 20 sink-operator pairs (7 operators
+    # at +q, 8 at -q) are walked with 21 block loads, one per group plus the
+    # first block, against 25 for the pairs in sorted order
     o1, o2 = p.table("group_op1"), p.table("group_op2")
     pairs = list(zip(o1.tolist(), o2.tolist()))
-    assert pairs == sorted(pairs) and len(set(pairs)) == len(pairs)
+    assert len(set(pairs)) == len(pairs) == 20
+
+    def loads(seq):
+        return 2 + sum((a[0] != b[0]) + (a[1] != b[1]) for a, b in zip(seq, seq[1:]))
+    assert loads(pairs) == 21 < loads(sorted(pairs)) == 25
 
 
 def test_isospin_aliases_of_the_octet():

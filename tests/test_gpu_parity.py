@@ -142,8 +142,8 @@ def test_precision_form_launch_shapes(tuning):
 @pytest.mark.parametrize("gchunk", [1, 2])
 def test_fp64_group_ranges(gchunk):
     """Double precision with workgroups that walk one run of sink-operator
-    groups with the same first operator, or a single group, on every R52
-    channel."""
+    groups in which one operator block stays, or a single group, on every
+    R52 channel."""
     announce("fp64 group ranges %d" % gchunk)
     L, T = (6, 4, 5), 2
     props = runner.host_props(L, T, range(T), dtype=np.complex128)
