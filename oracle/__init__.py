@@ -57,6 +57,7 @@ def _load():
         lib.ora_correlators.argtypes = [I, P, P, I, P, P]
         lib.ora_correlators_at_q.argtypes = [P, P, I, P, P, P]
         lib.ora_count_perms.argtypes = [P, P, P]
+        lib.ora_two_point.argtypes = [P, P, I, P, P]
         _lib = lib
     return _lib
 
@@ -150,3 +151,17 @@ def count_perms(chan):
     rc = _load().ora_count_perms(_ptr(c), _ptr(nt), _ptr(npm))
     assert rc == 0
     return int(nt[0]), int(npm[0])
+
+
+def two_point(L, S, pairs) -> np.ndarray:
+    """Zero-momentum single-baryon two-point functions on one time slice:
+    complex128 [n_pairs, 2, 2] (sink spin, source spin) for (sink, source)
+    operator pairs."""
+    arrs, ptrs = _props(S)
+    c = np.ascontiguousarray(np.array([[OPS[b] if isinstance(b, str) else int(b) for b in pr] for pr in pairs],
+                                      dtype=np.int32).reshape(-1, 2))
+    out = np.zeros((len(c), 2, 2), dtype=np.complex128)
+    rc = _load().ora_two_point(_ptr(_L(L)), ptrs, len(c), _ptr(c), _ptr(out))
+    if rc:
+        raise RuntimeError("oracle failed (%d)" % rc)
+    return out

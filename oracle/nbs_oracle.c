@@ -488,3 +488,60 @@ int ora_correlators_at_q(const int L[3], const double* const S[3], int n_ch,
   free(nterms);
   return 0;
 }
+
+/* ---- single-baryon two-point functions (zero momentum) ----------------- */
+
+int ora_two_point(const int L[3], const double* const S[3], int n_pairs,
+                  const int* pairs, double* out) {
+  const long V = (long)L[0] * L[1] * L[2];
+  src_term st[2][24];
+  for (int a = 0; a < 2; ++a)
+    if (source_terms(a, st[a]) != 24) return -2;
+  cplx* C = (cplx*)out;
+  cplx* blk = (cplx*)malloc(sizeof(cplx) * 3456 * (size_t)V);
+  if (!blk) return -3;
+  int rc = 0;
+  for (int k = 0; k < n_pairs && !rc; ++k) {
+    int fs[9], fc[9];
+    double ws[3], wc[3];
+    const int ns = ora_expand_op(pairs[2 * k], fs, ws);
+    const int nc = ora_expand_op(pairs[2 * k + 1], fc, wc);
+    if (ns <= 0 || nc <= 0) { rc = -1; break; }
+    cplx acc[2][2] = {{0, 0}, {0, 0}};
+    for (int ts = 0; ts < ns; ++ts) {
+      /* the sink term's normal block, summed over the sites of the slice */
+      if (ora_normal_blocks(L, S, fs[3 * ts], fs[3 * ts + 1], fs[3 * ts + 2], (double*)blk)) { rc = -1; break; }
+      cplx Nsum[3456];
+      for (int i = 0; i < 3456; ++i) Nsum[i] = 0;
+      for (long x = 0; x < V; ++x)
+        for (int i = 0; i < 3456; ++i) Nsum[i] += blk[3456 * x + i];
+      for (int tc = 0; tc < nc; ++tc) {
+        /* permutations P of the three source quarks with
+         * flavour(sink quark i) == flavour(source quark P[i]) */
+        for (int p0 = 0; p0 < 3; ++p0)
+          for (int p1 = 0; p1 < 3; ++p1)
+            for (int p2 = 0; p2 < 3; ++p2) {
+              const int p[3] = {p0, p1, p2};
+              if (p0 == p1 || p0 == p2 || p1 == p2) continue;
+              int ok = 1;
+              for (int i = 0; i < 3; ++i)
+                if (fs[3 * ts + i] != fc[3 * tc + p[i]]) ok = 0;
+              if (!ok) continue;
+              const int inv = (p0 > p1) + (p0 > p2) + (p1 > p2);
+              const double coef = ws[ts] * wc[tc] * ((inv & 1) ? -1.0 : 1.0);
+              for (int ap = 0; ap < 2; ++ap)
+                for (int m = 0; m < 24; ++m) {
+                  const int* j = st[ap][m].j;
+                  const int idx = (j[p[0]] * 12 + j[p[1]]) * 12 + j[p[2]];
+                  for (int a = 0; a < 2; ++a)
+                    acc[a][ap] += coef * st[ap][m].sgn * Nsum[a * 1728 + idx];
+                }
+            }
+      }
+    }
+    for (int a = 0; a < 2; ++a)
+      for (int ap = 0; ap < 2; ++ap) C[4 * k + 2 * a + ap] = acc[a][ap];
+  }
+  free(blk);
+  return rc;
+}

@@ -61,6 +61,17 @@ int ora_correlators_at_q(const int L[3], const double* const S[3],
                          int n_ch, const int* chans, const int q[3],
                          double* out);
 
+/* Single-baryon two-point functions at zero momentum on one time slice:
+ *   C[a][a'] = sum_x sum over the operators' weighted flavour terms and the
+ *   flavour-respecting permutations P of the three source quarks, sgn(P)
+ *   times the one-baryon source tensor eps_{c1c2c3} (C g5)_{s1 s2}
+ *   delta_{s3 a'} times N_sink(x)[a][j_{P(0)}][j_{P(1)}][j_{P(2)}]
+ * (Eq. (1) with one baryon at sink and source, Eqs. (2)-(5)).
+ * pairs[2*k] = sink operator, pairs[2*k+1] = source operator; out is
+ * [n_pairs][2][2] complex (a = sink spin, a' = source spin). */
+int ora_two_point(const int L[3], const double* const S[3], int n_pairs,
+                  const int* pairs, double* out);
+
 /* Number of flavour-consistent Wick permutations summed for a channel,
  * over all weighted operator terms, and the number of such terms. */
 int ora_count_perms(const int chan[4], int* n_terms, int* n_perms);
