@@ -125,6 +125,22 @@ def cpu_baseline(L):
                       "(%d sites), %.1f s" % (L[0], L[1], L[2], V, dt)}
 
 
+def time_two_point(r, stream, reps=10):
+    """Zero-momentum two-point functions of the eight octet baryons from the
+    built blocks (a by-product of the build stage, timed apart from the
+    step): average time of one call over reps calls."""
+    import torch
+    pairs = [(b, b) for b in ("p", "n", "Lambda", "Sigma+", "Sigma0", "Sigma-", "Xi0", "Xi-")]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    r.two_point(pairs)
+    ev[0].record(stream)
+    for _ in range(reps):
+        r.two_point(pairs)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    return {"pairs": len(pairs), "ms": ev[0].elapsed_time(ev[1]) / reps}
+
+
 def bench_batch(args):
     """The batching form: one step = one launch of the captured graph over
     all 24 geometries (build, contraction in one launch, inverse transforms)."""
@@ -235,6 +251,7 @@ def bench_slab96(args):
     ms_step = wall * 1e3 / args.steps
     V = L[0] * L[1] * L[2]
     sites = V * n_slices
+    two_point = time_two_point(r, stream)
     ebb_f, meb_f = program_work(r.plan)
     contract_ms = float(stage[:, :, 1].mean())
     roof = {"bound": "alu", "achieved": (ebb_f + meb_f) * V / (contract_ms * 1e-3) / 1e12,
@@ -248,6 +265,7 @@ def bench_slab96(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "96^3 slab: slices 0-7 of T = 64, 52 channels, precision form, one slice at a time",
                    "lattice": list(L), "T": T, "slices": n_slices, "channels": len(chans), "sites_per_step": sites},
+        "two_point": two_point,
         "stage_ms_per_slice": {"build_blocks": float(stage[:, :, 0].mean()), "contract_channels": contract_ms,
                                "relative_sum": float(stage[:, :, 2].mean())},
         "roofline": roof,
@@ -315,6 +333,7 @@ def main():
     sites = V * tc
     value = sites * len(chans) / (ms_step * 1e-3)
 
+    two_point = time_two_point(r, stream)
     ebb_f, meb_f = program_work(r.plan)
     contract_ms = float(stage[:, 1].mean())
     contract_flops = (ebb_f + meb_f) * sites
@@ -340,6 +359,7 @@ def main():
         "stage_ms": {"build_blocks": float(stage[:, 0].mean()), "contract_channels": contract_ms,
                      "relative_sum": float(stage[:, 2].mean())},
         "build_hbm_gbs": build_bytes / (stage[:, 0].mean() * 1e-3) / 1e9,
+        "two_point": two_point,
         "roofline": roof,
     }
     r.close()

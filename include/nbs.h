@@ -127,6 +127,28 @@ nbs_status nbs_contract_channels(nbs_plan plan, void* stream);
  * nbs_contract_channels. */
 nbs_status nbs_relative_sum(nbs_plan plan, void* const* F_out, void* stream);
 
+/* A sink and a source operator of a single-baryon two-point function. */
+typedef struct {
+  int32_t sink, src;
+} nbs_baryon_pair;
+
+/* Zero-momentum single-baryon two-point functions, a by-product of stage 1:
+ * Eq. (1) with one baryon at the sink and one at the (wall) source,
+ *   C[a][a'](t) = sum_x sum over the source operator's flavour terms and the
+ *   flavour-respecting Wick maps of the three source quarks, sign times the
+ *   one-baryon source tensor eps (C g5) delta of Eq. (4) times the sink
+ *   operator's normal block N(x)[a][...] of Eq. (5),
+ * read from the transformed blocks at q = 0 (sum over x).  pairs: 1..8
+ * (sink, src) operator codes; the sink operator must have a block in the
+ * plan (a sink operator of one of its channels), else NBS_ERR_INVALID.
+ * C_out[g]: device pointer, complex128 [n_pairs][t_count][2][2] (sink spin
+ * a, source spin a'), owned by the caller.  Valid from nbs_build_blocks
+ * until the next build (in either order with the other stages); undoes the
+ * precision form's scale and, in the isospin-symmetric limit, reads n,
+ * Sigma-, Xi- through their aliases.  Asynchronous on stream. */
+nbs_status nbs_two_point(nbs_plan plan, const nbs_baryon_pair* pairs, int32_t n_pairs,
+                         void* const* C_out, void* stream);
+
 /* All three stages for every geometry as one captured HIP graph.  The first
  * call (and any call whose pointers differ from the captured ones) records
  * build, contract and relative sum into a graph on a plan-owned stream and

@@ -21,7 +21,7 @@ STATUS = {0: "NBS_OK", 1: "NBS_ERR_INVALID", 2: "NBS_ERR_UNSUPPORTED", 3: "NBS_E
 SYMBOLS = ("nbs_plan_create", "nbs_workspace_bytes", "nbs_build_blocks", "nbs_contract_channels",
            "nbs_relative_sum", "nbs_plan_destroy", "nbs_status_string", "nbs_last_error",
            "nbs_plan_info", "nbs_plan_diagrams", "nbs_plan_table", "nbs_plan_params", "nbs_run_graph",
-           "nbs_plan_autotune", "nbs_plan_tuning", "nbs_plan_set_tuning")
+           "nbs_plan_autotune", "nbs_plan_tuning", "nbs_plan_set_tuning", "nbs_two_point")
 
 
 class NbsError(RuntimeError):
@@ -37,6 +37,10 @@ class Geometry(ctypes.Structure):
 
 class Channel(ctypes.Structure):
     _fields_ = [("sink", ctypes.c_int32 * 2), ("src", ctypes.c_int32 * 2)]
+
+
+class BaryonPair(ctypes.Structure):
+    _fields_ = [("sink", ctypes.c_int32), ("src", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -92,6 +96,8 @@ def lib():
         L.nbs_run_graph.restype = I32
         L.nbs_plan_autotune.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), P]
         L.nbs_plan_autotune.restype = I32
+        L.nbs_two_point.argtypes = [P, ctypes.POINTER(BaryonPair), I32, ctypes.POINTER(P), P]
+        L.nbs_two_point.restype = I32
         L.nbs_plan_tuning.argtypes = [P, ctypes.POINTER(I32)]
         L.nbs_plan_tuning.restype = I32
         L.nbs_plan_set_tuning.argtypes = [P, ctypes.POINTER(I32)]
@@ -173,6 +179,15 @@ class Plan:
 
     def contract_channels(self, stream=0):
         self._check(lib().nbs_contract_channels(self._h, ctypes.c_void_p(stream)), "nbs_contract_channels")
+
+    def two_point(self, pairs, C_out, stream=0):
+        """Zero-momentum single-baryon two-point functions of (sink, source)
+        operator pairs into C_out (one device pointer per geometry)."""
+        arr = (BaryonPair * max(1, len(pairs)))()
+        for i, (a, b) in enumerate(pairs):
+            arr[i].sink, arr[i].src = _op(a), _op(b)
+        self._check(lib().nbs_two_point(self._h, arr, len(pairs), _ptrs(C_out, self.n_geom), ctypes.c_void_p(stream)),
+                    "nbs_two_point")
 
     def relative_sum(self, F_out, stream=0):
         self._check(lib().nbs_relative_sum(self._h, _ptrs(F_out, self.n_geom), ctypes.c_void_p(stream)),

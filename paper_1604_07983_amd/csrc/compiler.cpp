@@ -736,4 +736,27 @@ std::string compile_channels(const std::vector<ChannelSpec>& chans, const Compil
   return "";
 }
 
+std::vector<TwoPointTerm> two_point_terms(int sink_op, int src_op) {
+  std::vector<TwoPointTerm> out;
+  const OpExpansion src = expand_operator(src_op);
+  for (size_t k = 0; k < src.trip.size(); ++k) {
+    const int srcfl[6] = {src.trip[k].f[0], src.trip[k].f[1], src.trip[k].f[2], -1, -1, -1};
+    for (const Map& mp : effective_block(sink_op, 0x7, srcfl)) {
+      TwoPointTerm t;
+      for (int i = 0; i < 3; ++i) t.m[i] = mp.m[i];
+      t.coef = src.norm * src.wnum[k] * mp.sign;
+      out.push_back(t);
+    }
+  }
+  return out;
+}
+
+void operator_flavour_counts(int op, int nf[3]) {
+  int fl[3];
+  operator_slots(op, fl);
+  nf[0] = nf[1] = nf[2] = 0;
+  for (int i = 0; i < 3; ++i)
+    if (fl[i] >= 0 && fl[i] < 3) ++nf[fl[i]];
+}
+
 }  // namespace nbs

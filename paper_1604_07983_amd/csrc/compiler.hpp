@@ -157,4 +157,17 @@ struct Compiled {
 std::string compile_channels(const std::vector<ChannelSpec>& ch,
                              const CompileOptions& opt, Compiled* out);
 
+// Zero-momentum single-baryon two-point function of a sink-operator block
+// with a source operator: for each weighted flavour term of the source and
+// each flavour-respecting map of the block's slots onto its three quarks
+// (slot i contracted with source quark m[i]), the map and the source weight
+// times the map's sign (Eq. (1) with one baryon on each side, Eqs. (2)-(5)).
+struct TwoPointTerm {
+  int m[3];
+  double coef;
+};
+std::vector<TwoPointTerm> two_point_terms(int sink_op, int src_op);
+// Quark flavour counts (u, d, s) of an operator's block slots.
+void operator_flavour_counts(int op, int nf[3]);
+
 }  // namespace nbs

@@ -1262,8 +1262,65 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Zero-momentum single-baryon two-point functions (Eq. (1) with one baryon
+// on each side): workgroup (pair, slice), one wavefront.  Lane i takes the
+// (term, source spin, source-tensor term) items i, i + 64, ...: the source
+// tensor eps (C g5) delta of Eq. (4) for one baryon has 24 non-zero
+// (colour, spin) assignments per source spin; each item reads both sink
+// spins of the block entry the term's map selects.  FP64 accumulation,
+// fixed-order shuffle reduction.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(64) void k_two_point(TwoPointArgs a) {
+  const int k = blockIdx.x, t = blockIdx.y, lane = threadIdx.x;
+  const cx<T>* N = reinterpret_cast<const cx<T>*>(a.Nq) +
+                   (long long)(a.slot[k] * a.t_count + t) * a.V * kBlockEntries;  // q = 0
+  double acc[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) acc[i] = 0.0;
+  const int items = a.n_terms[k] * 48;
+  for (int i = lane; i < items; i += 64) {
+    const int term = i / 48, r = i - term * 48, ap = r / 24, s = r - ap * 24;
+    int j[3] = {0, 0, 0};
+    const int c = part_term(3, -1, 0, ap, s, j[0], j[1], j[2]);
+    const int mp = a.term_map[k][term];
+    const int idx = (j[mp & 3] * 12 + j[(mp >> 2) & 3]) * 12 + j[(mp >> 4) & 3];
+    const double w = a.term_coef[k][term] * c;
+#pragma unroll
+    for (int al = 0; al < 2; ++al) {
+      const cx<T> v = N[al * 1728 + idx];
+      acc[4 * al + 2 * ap] = fma(w, (double)v.re, acc[4 * al + 2 * ap]);
+      acc[4 * al + 2 * ap + 1] = fma(w, (double)v.im, acc[4 * al + 2 * ap + 1]);
+    }
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] += __shfl_xor(acc[i], d);
+  if (lane == 0) {
+    int e = 0;
+    if (a.exps)
+      for (int f = 0; f < 3; ++f) e += a.nf[k][f] * a.exps[f * a.t_count + t];
+    const double sc = ldexp(a.slot_coef[k], e);
+    cd* C = reinterpret_cast<cd*>(a.C) + ((long long)k * a.t_count + t) * 4;
+#pragma unroll
+    for (int o = 0; o < 4; ++o) C[o] = cd{acc[2 * o] * sc, acc[2 * o + 1] * sc};
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+hipError_t launch_two_point(int prec, const TwoPointArgs& a, hipStream_t st) {
+  if (a.n_pairs < 1 || a.n_pairs > kMaxTwoPointPairs || a.t_count < 1) return hipErrorInvalidValue;
+  const dim3 grid(a.n_pairs, a.t_count);
+  if (prec == 0)
+    hipLaunchKernelGGL(k_two_point<double>, grid, dim3(64), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_two_point<float>, grid, dim3(64), 0, st, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_u32(unsigned* p, unsigned v, long long n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, v, n);

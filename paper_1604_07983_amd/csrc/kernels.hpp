@@ -90,6 +90,28 @@ struct ContractArgs {
   long long block0, n_chunk;  // logical workgroups [block0, block0 + n_chunk) in this launch
 };
 
+// Zero-momentum single-baryon two-point functions of one geometry: pair k
+// reads the transformed block of operator slot slot[k] at q = 0 (times
+// slot_coef[k], the isospin alias factor), contracts it with the
+// one-baryon source tensor through term_map / term_coef (slot i with source
+// quark (map >> 2 i) & 3), undoes the precision form's scale 2^(sum_f
+// nf[k][f] exps[f][t]) when exps is given, and writes complex128
+// C[k][t][a][a'].
+constexpr int kMaxTwoPointPairs = 8, kMaxTwoPointTerms = 18;
+struct TwoPointArgs {
+  const void* Nq;
+  void* C;
+  const int* exps;
+  int V, t_count, n_pairs;
+  int slot[kMaxTwoPointPairs];
+  double slot_coef[kMaxTwoPointPairs];
+  int nf[kMaxTwoPointPairs][3];
+  int n_terms[kMaxTwoPointPairs];
+  int term_map[kMaxTwoPointPairs][kMaxTwoPointTerms];
+  double term_coef[kMaxTwoPointPairs][kMaxTwoPointTerms];
+};
+hipError_t launch_two_point(int prec, const TwoPointArgs& a, hipStream_t st);
+
 // prec: 0 = FP64 form, 1 = precision form (complex64 storage, FP32 compute).
 hipError_t launch_absmax(const void* S, unsigned* maxbits, long long per_slice, int t_count, hipStream_t st);
 hipError_t launch_fill_u32(unsigned* p, unsigned v, long long n, hipStream_t st);

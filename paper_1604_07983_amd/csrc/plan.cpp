@@ -613,6 +613,52 @@ nbs_status nbs_relative_sum(nbs_plan p, void* const* F_out, void* stream) {
   return enqueue_relsum(p, F_out, (hipStream_t)stream);
 }
 
+nbs_status nbs_two_point(nbs_plan p, const nbs_baryon_pair* pairs, int32_t n_pairs, void* const* C_out,
+                         void* stream) {
+  if (!p) return NBS_ERR_INVALID;
+  if (p->device < 0) return fail(p, NBS_ERR_STATE, "host-only plan");
+  if (p->stage < ST_BUILT) return fail(p, NBS_ERR_STATE, "nbs_build_blocks must come first");
+  if (!pairs || n_pairs < 1 || n_pairs > nbs::kMaxTwoPointPairs)
+    return fail(p, NBS_ERR_INVALID, "1 to 8 operator pairs per call");
+  if (!ptrs_ok(C_out, p->gw.size())) return fail(p, NBS_ERR_INVALID, "null output pointer");
+  const auto& P = p->comp.prog;
+  nbs::TwoPointArgs a{};
+  a.n_pairs = n_pairs;
+  for (int k = 0; k < n_pairs; ++k) {
+    const int sink = pairs[k].sink, src = pairs[k].src;
+    if (sink < 0 || sink >= NBS_NUM_OPS || src < 0 || src >= NBS_NUM_OPS)
+      return fail(p, NBS_ERR_INVALID, "unknown operator");
+    int slot = -1;
+    for (int s = 0; s < P.n_ops; ++s)
+      if (P.op_code[s] == sink) slot = s;
+    if (slot < 0) return fail(p, NBS_ERR_INVALID, "the sink operator has no block in this plan");
+    const std::vector<nbs::TwoPointTerm> terms = nbs::two_point_terms(sink, src);
+    if ((int)terms.size() > nbs::kMaxTwoPointTerms) return fail(p, NBS_ERR_UNSUPPORTED, "too many terms");
+    // in the isospin-symmetric limit only canonical blocks exist
+    a.slot[k] = p->iso ? P.op_alias[slot] : slot;
+    a.slot_coef[k] = p->iso ? P.op_alias_coef[slot] : 1.0;
+    nbs::operator_flavour_counts(sink, a.nf[k]);
+    a.n_terms[k] = (int)terms.size();
+    for (size_t i = 0; i < terms.size(); ++i) {
+      a.term_map[k][i] = terms[i].m[0] | (terms[i].m[1] << 2) | (terms[i].m[2] << 4);
+      a.term_coef[k][i] = terms[i].coef;
+    }
+  }
+  if (hipSetDevice(p->device) != hipSuccess) return fail(p, NBS_ERR_DEVICE, "hipSetDevice");
+  for (size_t g = 0; g < p->gw.size(); ++g) {
+    const GeomWork& w = p->gw[g];
+    a.Nq = w.Nq;
+    a.C = C_out[g];
+    a.exps = p->prec == NBS_FP32_MFMA ? w.exps : nullptr;
+    a.V = (int)w.V;
+    a.t_count = w.g.t_count;
+    const nbs_status s = hip_check(p, nbs::launch_two_point(p->prec == NBS_FP64 ? 0 : 1, a, (hipStream_t)stream),
+                                   "two-point");
+    if (s != NBS_OK) return s;
+  }
+  return NBS_OK;
+}
+
 nbs_status nbs_run_graph(nbs_plan p, const void* const* prop_u, const void* const* prop_d, const void* const* prop_s,
                          void* const* F_out, void* stream) {
   if (!p) return NBS_ERR_INVALID;

@@ -86,6 +86,13 @@ class Runner:
         self.relative_sum()
         return self.F
 
+    def two_point(self, pairs):
+        """C[pair, t, a, a'] (complex128, on the device) from the built blocks."""
+        torch = _torch()
+        C = torch.empty((len(pairs), self.t_count, 2, 2), dtype=torch.complex128, device="cuda")
+        self.plan.two_point(pairs, C.data_ptr(), self.stream())
+        return C
+
     def close(self):
         self.plan.close()
 
@@ -127,6 +134,14 @@ class BatchRunner:
         self.contract()
         self.relative_sum()
         return self.F
+
+    def two_point(self, pairs):
+        """Per geometry C[pair, t, a, a'] (complex128, on the device)."""
+        torch = _torch()
+        C = [torch.empty((len(pairs), self.plan.geoms[i].t_count, 2, 2), dtype=torch.complex128, device="cuda")
+             for i in range(len(self.geoms))]
+        self.plan.two_point(pairs, [c.data_ptr() for c in C], self.stream())
+        return C
 
     def run_graph(self, props):
         self.plan.run_graph(*self._split(props), [f.data_ptr() for f in self.F], self.stream())

@@ -183,6 +183,7 @@ def test_compute_calls_on_host_only_plan_are_state_errors():
     assert L.nbs_relative_sum(p.handle, z, None) == 5
     assert L.nbs_run_graph(p.handle, z, z, z, z, None) == 5
     assert L.nbs_plan_autotune(p.handle, z, z, z, None) == 5
+    assert L.nbs_two_point(p.handle, None, 0, z, None) == 5
     assert b"host-only" in L.nbs_last_error(p.handle)
     tune = p.tuning()
     assert tune["fft_line"] == 1 and tune["fft_tile"] == 1024 and tune["split"] == 1 and tune["fft_plane"] == 1
