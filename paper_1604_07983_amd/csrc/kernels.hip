@@ -203,23 +203,31 @@ __global__ __launch_bounds__(kThreads) void k_fft_pass(FftArgs a) {
 // One axis of the batched transform with the whole line in registers: thread
 // (o, i) transforms the N elements o N inner + i + k inner, k < N.  Adjacent
 // threads take adjacent i, so every load and store of a wavefront is one
-// contiguous run; arithmetic in FP64 whatever the storage type.
+// contiguous run.  Arithmetic in FP64 whatever the storage type, except the
+// precision form's forward lines longer than 48 (64, 80, 96), which keep
+// complex64 storage and FP32 arithmetic so that the line fits in registers.
+constexpr int kLineMaxFp64 = 48;
+
 template <int N, int SIGN, typename Tin, typename Tout>
 __global__ __launch_bounds__(kThreads) void k_fft_line(FftArgs a) {
+  using AT = std::conditional_t<(N > kLineMaxFp64), float, double>;
+  static_assert(N <= kLineMaxFp64 || (std::is_same<Tin, float>::value && std::is_same<Tout, float>::value),
+                "long register lines are complex64 only");
   const long long gid = a.unit0 + (long long)blockIdx.x * kThreads + threadIdx.x;
   if (gid >= a.outer * a.inner) return;
   const long long o = gid / a.inner, i = gid - o * a.inner;
   const long long base = o * N * a.inner + i;
   const cx<Tin>* in = reinterpret_cast<const cx<Tin>*>(a.in);
-  cd v[N];
+  cx<AT> v[N];
 #pragma unroll
-  for (int k = 0; k < N; ++k) v[k] = conv<double>(in[base + k * a.inner]);
+  for (int k = 0; k < N; ++k) v[k] = conv<AT>(in[base + k * a.inner]);
   fft_reg<N, SIGN>(v);
   double f = a.gscale;
   if (a.oscale) f *= a.oscale[o / a.oscale_div];
+  const AT fa = (AT)f;
   cx<Tout>* out = reinterpret_cast<cx<Tout>*>(a.out);
 #pragma unroll
-  for (int k = 0; k < N; ++k) out[base + k * a.inner] = conv<Tout>(cd{v[k].re * f, v[k].im * f});
+  for (int k = 0; k < N; ++k) out[base + k * a.inner] = conv<Tout>(cx<AT>{v[k].re * fa, v[k].im * fa});
 }
 
 // The x and y axes of a forward transform in one pass.  Workgroup (plane,
@@ -1380,11 +1388,13 @@ template <int N> hipError_t launch_line_kind(int kind, const FftArgs& a, hipStre
 
 }  // namespace
 
-bool fft_line_supported(int n) {
+bool fft_line_supported(int n, int kind) {
   switch (n) {
     case 2: case 3: case 4: case 5: case 6: case 8: case 10: case 12: case 16: case 20: case 24: case 32:
     case 40: case 48:
       return true;
+    case 64: case 80: case 96:
+      return kind == 1;
   }
   return false;
 }
@@ -1466,6 +1476,10 @@ hipError_t launch_fft_line(int kind, const FftArgs& a, hipStream_t st) {
     case 32: return launch_line_kind<32>(kind, a, st);
     case 40: return launch_line_kind<40>(kind, a, st);
     case 48: return launch_line_kind<48>(kind, a, st);
+    // long lines: the precision form's forward transform only
+    case 64: return kind == 1 ? launch_line<64, -1, float, float>(a, st) : hipErrorInvalidValue;
+    case 80: return kind == 1 ? launch_line<80, -1, float, float>(a, st) : hipErrorInvalidValue;
+    case 96: return kind == 1 ? launch_line<96, -1, float, float>(a, st) : hipErrorInvalidValue;
   }
   return hipErrorInvalidValue;
 }

@@ -123,7 +123,7 @@ hipError_t launch_nbb(int prec, const NbbArgs& a, hipStream_t st);
 hipError_t launch_fft_pass(int kind, const FftArgs& a, hipStream_t st);
 // Lengths with a register-resident kernel, and its launcher (kind as above;
 // the forward precision-form kind takes sign -1, the mixed kind sign +1).
-bool fft_line_supported(int n);
+bool fft_line_supported(int n, int kind);
 // Square planes with a fused x-y kernel (forward transforms of the blocks,
 // kinds 0 and 1); fields per workgroup for an inner extent, 0 if none fits.
 int fft_plane_fields(int n, long long inner, int kind);

@@ -204,7 +204,7 @@ nbs_status fft3d(nbs_plan p, int kind_first, int kind_rest, const void* in, void
     // one line per thread in registers where the length has a kernel and the
     // lines are wide enough apart for adjacent threads to read one run
     const int kind = ax == 0 ? kind_first : kind_rest;
-    const bool line = p->tune.fft_line && nbs::fft_line_supported(a.n) && inner >= kLineMinInner;
+    const bool line = p->tune.fft_line && nbs::fft_line_supported(a.n, kind) && inner >= kLineMinInner;
     nbs_status s = hip_check(p, line ? nbs::launch_fft_line(kind, a, st) : nbs::launch_fft_pass(kind, a, st),
                              "fft pass");
     if (s != NBS_OK) return s;
