@@ -67,6 +67,21 @@ def test_all_r52_channels_small_lattice(prec):
     assert err.max() <= TOL[prec], (err.max(), int(err.argmax()))
 
 
+@pytest.mark.parametrize("sector", [(-2, 0), (-1, -1), (-3, 1)])
+def test_generated_sector_tables(sector):
+    """Channel tables generated from quantum numbers (every ordered octet
+    pair of a strangeness and I_z sector, coupled channels included) run end
+    to end against the oracle."""
+    announce("generated sector %s" % (sector,))
+    L, T = (4, 2, 3), 2
+    props = runner.host_props(L, T, range(T), dtype=np.complex128)
+    chans = channels.coupled_channels(*sector, ordered=True)
+    Fg = run_gpu(L, T, chans, props, binding.NBS_FP64)
+    Fo = oracle_F(L, props, chans)
+    err = rel_err_per_channel(Fg, Fo)
+    assert err.max() <= TOL[binding.NBS_FP64], (err.max(), int(err.argmax()))
+
+
 @pytest.mark.parametrize("prec", [binding.NBS_FP64, binding.NBS_FP32_MFMA])
 def test_window_and_source_slice(prec):
     """A window t_begin = 3, t_count = 2 of T = 6 with the source at t0 = 2."""
