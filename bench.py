@@ -348,6 +348,18 @@ def main():
             "kernel": "k_contract (effective blocks + products)",
             "algorithmic_bytes": float(sites * n_types * 3456 * el + len(chans) * 16 * sites * el)}
     roof["frac"] = roof["achieved"] / roof["peak"]
+    # whole-step roofline: per stage the larger of its algorithmic flops at
+    # the vector peak and its algorithmic bytes at the HBM peak (propagators
+    # read, blocks written once and transformed with one read and one write,
+    # blocks read once by the contraction, F~ written, read and F written)
+    peak = PEAK["fp64"] if prec == 0 else PEAK["fp32_vector"]
+    blocks = sites * n_types * 3456 * el
+    fields = sites * len(chans) * 16
+    parts = {"build_blocks": max(sites * n_types * 3456 * (3 * 8 + 5 * np.log2(V)) / peak,
+                                 (sites * 3 * 144 * el + 3 * blocks) / PEAK["hbm"]),
+             "contract_channels": max(contract_flops / peak, (blocks + fields * el) / PEAK["hbm"]),
+             "relative_sum": max(fields * 5 * np.log2(V) / PEAK["fp64"], fields * (el + 16) / PEAK["hbm"])}
+    step_roof_ms = sum(parts.values()) * 1e3
     out = {
         "metric": "NBS site-channels/sec + GFLOP/s, FP32-MFMA batched vs FP64 plain at stated rel err",
         "value": value, "unit": "site-channels/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -361,6 +373,8 @@ def main():
         "build_hbm_gbs": build_bytes / (stage[:, 0].mean() * 1e-3) / 1e9,
         "two_point": two_point,
         "roofline": roof,
+        "step_roofline": {"ms": step_roof_ms, "frac": step_roof_ms / ms_step,
+                          "parts_ms": {k: v * 1e3 for k, v in parts.items()}},
     }
     r.close()
     if not args.no_cpu_baseline:
