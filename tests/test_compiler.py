@@ -334,3 +334,13 @@ def test_isospin_program_reproduces_oracle():
         want = oracle.correlators_at_q(L, S, chans, qv)
         err = np.linalg.norm(got - want, axis=1) / np.linalg.norm(want, axis=1)
         assert err.max() < 1e-12, (q, err.max())
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """Without the built HIP library every entry point raises (no fallback)."""
+    monkeypatch.setattr(binding, "_LIB_PATH", "/nonexistent/libnbs.so")
+    monkeypatch.setattr(binding, "_lib", None)
+    with pytest.raises(ImportError):
+        binding.lib()
+    with pytest.raises(ImportError):
+        binding.Plan((4, 4, 4), 8, [("p", "p", "p", "p")], device=-1)
