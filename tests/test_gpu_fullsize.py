@@ -112,3 +112,31 @@ def test_config5_96cubed_slice_closed_form():
         want = separable.channel(ch, C[c], phi)
         err = np.linalg.norm(got - want) / np.linalg.norm(want)
         assert err <= 1e-5, (c, ch, float(err))
+
+
+@pytest.mark.parametrize("prec", [binding.NBS_FP64, binding.NBS_FP32_MFMA])
+def test_two_point_full_slices(prec):
+    """Zero-momentum octet two-point functions at 16^3 x 32 (all 32 slices
+    from one build, as the benchmark calls it) against the oracle on three
+    slices."""
+    import torch
+    announce("two-point 16^3 x 32 prec %d" % prec)
+    L, T = (16, 16, 16), 32
+    dt = np.complex128 if prec == binding.NBS_FP64 else np.complex64
+    props = runner.host_props(L, T, range(T), decay=DECAY, dtype=dt)
+    dp = runner.device_props(props, prec)
+    r = runner.Runner(L, T, channels.r52(), prec=prec, t_count=T)
+    r.build(*dp)
+    pairs = [(b, b) for b in ("p", "n", "Lambda", "Sigma+", "Sigma0", "Sigma-", "Xi0", "Xi-")]
+    C = r.two_point(pairs).cpu().numpy()
+    torch.cuda.synchronize()
+    r.close()
+    del dp
+    assert np.isfinite(C).all()
+    tol = 1e-12 if prec == binding.NBS_FP64 else 1e-5
+    for t in (0, 13, 31):
+        want = oracle.two_point(L, flat_props(props, t), pairs)
+        got = C[:, t]
+        err = np.linalg.norm((got - want).reshape(len(pairs), -1), axis=1) / \
+            np.linalg.norm(want.reshape(len(pairs), -1), axis=1)
+        assert err.max() <= tol, (t, float(err.max()), int(err.argmax()))
