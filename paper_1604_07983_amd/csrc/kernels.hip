@@ -1148,15 +1148,62 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
       ccoef[i] = (T)A.contrib_coef[cbase + i];
     }
   };
-  const bool newB = g == gbeg || A.group_op2[g] != A.group_op2[g - 1];
-  if (newA && newB)
-    stage(std::true_type{}, std::true_type{});
-  else if (newA)
-    stage(std::true_type{}, std::false_type{});
-  else if (newB)
-    stage(std::false_type{}, std::true_type{});
-  else
-    stage(std::false_type{}, std::false_type{});
+  // FP64 (one workgroup per CU): after the first group, half of the
+  // wavefronts stage the next group's blocks while the other half forms the
+  // channel sums (below), so the HBM latency of the staging overlaps that
+  // work.  The precision form has a second workgroup on the CU to cover it.
+  // stage_blocks: the blocks of group gg whose operator changed, by the NTH
+  // threads from `first`, every global load before the first LDS store.
+  constexpr bool kOverlap = sizeof(T) == 8;
+  auto stage_blocks = [&](int gg, auto with_a, auto with_b, int first, auto nthreads) {
+    constexpr bool kA = decltype(with_a)::value, kB = decltype(with_b)::value;
+    constexpr int NTH = decltype(nthreads)::value;
+    constexpr int kP = (kBlockEntries + NTH - 1) / NTH;
+    using gptr = const __attribute__((address_space(1))) cx<T>*;
+    const gptr gA = (gptr)(Nq + ((long long)(A.group_op1[gg] * G.t_count + t) * G.V + q) * kBlockEntries);
+    const gptr gB = (gptr)(Nq + ((long long)(A.group_op2[gg] * G.t_count + t) * G.V + mq) * kBlockEntries);
+    const int lt = tid - first;
+    cx<T> va[kA ? kP : 1], vb[kB ? kP : 1];
+#pragma unroll
+    for (int k = 0; k < kP; ++k) {
+      const int i = lt + k * NTH;
+      const int ii = i < kBlockEntries ? i : kBlockEntries - 1;
+      if constexpr (kA) va[k] = cx<T>{gA[ii].re, gA[ii].im};
+      if constexpr (kB) vb[k] = cx<T>{gB[ii].re, gB[ii].im};
+    }
+#pragma unroll
+    for (int k = 0; k < kP; ++k) {
+      const int i = lt + k * NTH;
+      if (i < kBlockEntries) {
+        if constexpr (kA) slotA[lds_index(i)] = va[k];
+        if constexpr (kB) slotB[lds_index(i)] = vb[k];
+      }
+    }
+  };
+  auto stage_blocks_of = [&](int gg, int first, auto nthreads) {
+    const bool nA = gg == gbeg || A.group_op1[gg] != A.group_op1[gg - 1];
+    const bool nB = gg == gbeg || A.group_op2[gg] != A.group_op2[gg - 1];
+    if (nA && nB)
+      stage_blocks(gg, std::true_type{}, std::true_type{}, first, nthreads);
+    else if (nA)
+      stage_blocks(gg, std::true_type{}, std::false_type{}, first, nthreads);
+    else if (nB)
+      stage_blocks(gg, std::false_type{}, std::true_type{}, first, nthreads);
+  };
+  if constexpr (kOverlap) {
+    if (g == gbeg) stage_blocks_of(g, 0, std::integral_constant<int, kContractThreads>{});
+    stage(std::false_type{}, std::false_type{});  // contributions and task words
+  } else {
+    const bool newB = g == gbeg || A.group_op2[g] != A.group_op2[g - 1];
+    if (newA && newB)
+      stage(std::true_type{}, std::true_type{});
+    else if (newA)
+      stage(std::true_type{}, std::false_type{});
+    else if (newB)
+      stage(std::false_type{}, std::true_type{});
+    else
+      stage(std::false_type{}, std::false_type{});
+  }
   if (tid == 0) task_counter = 0;
   __syncthreads();
 
@@ -1228,6 +1275,10 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
   }
   __syncthreads();
 
+  const bool split = kOverlap && g + 1 < gend;
+  if (split && tid >= kContractThreads / 2) {
+    stage_blocks_of(g + 1, kContractThreads / 2, std::integral_constant<int, kContractThreads / 2>{});
+  } else {
   // channel sums: 8 lanes per output (spin s of local channel cl), each
   // summing every 8th contribution, then a fixed-order shuffle reduction.
   // The geometry is read again here rather than kept live through the
@@ -1236,7 +1287,8 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
   const long long qt2 = qtl - G2.block0;
   const int t2 = (int)(qt2 / G2.V), q2 = (int)(qt2 % G2.V);
   cx<T>* Ft = reinterpret_cast<cx<T>*>(G2.Ft);
-  for (int i0 = 0; i0 < nch * 16 * 8; i0 += kContractThreads) {
+  const int nacc = split ? kContractThreads / 2 : kContractThreads;
+  for (int i0 = 0; i0 < nch * 16 * 8; i0 += nacc) {
     const int i = i0 + tid;
     const int o = i >> 3, sub = i & 7;
     const int cl = o >> 4, s = o & 15;
@@ -1264,6 +1316,7 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
       const int ch = A.group_channels[gc0 + cl];
       Ft[(((long long)ch * G2.t_count + t2) * 16 + s) * G2.V + q2] = v;
     }
+  }
   }
   __syncthreads();  // LDS is restaged for the next group
   }
