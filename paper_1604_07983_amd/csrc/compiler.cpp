@@ -177,7 +177,34 @@ void operator_slots(int op, int fl[3]) {
   for (int i = 0; i < 3; ++i) fl[i] = e.trip.empty() ? -1 : e.trip[0].f[i];
 }
 
+bool operator_pair(int op, int* s1, int* s2) {
+  int fl[3];
+  operator_slots(op, fl);
+  for (int a = 0; a < 3; ++a)
+    for (int b = a + 1; b < 3; ++b)
+      if (fl[a] >= 0 && fl[a] == fl[b]) {
+        *s1 = a;
+        *s2 = b;
+        return true;
+      }
+  return false;
+}
+
 namespace {
+
+// Maps of an operator block onto a source set as read from the stored
+// block: for an operator with a same-flavour slot pair (s1, s2) the maps come
+// in partner pairs m, m' (m' exchanges the quarks of s1 and s2, sign(m') =
+// -sign(m)), and sign(m) N[m] + sign(m') N[m'] = sign(m) A[m] on the
+// antisymmetrised block A, so only the partner with m[s1] < m[s2] is kept.
+std::vector<Map> on_stored_block(int op, const std::vector<Map>& maps) {
+  int s1 = 0, s2 = 0;
+  if (!operator_pair(op, &s1, &s2)) return maps;
+  std::vector<Map> out;
+  for (const Map& m : maps)
+    if (m.m[s1] < m.m[s2]) out.push_back(m);
+  return out;
+}
 
 // Offset unit of source quark q in a block under map mp: the LDS stride of
 // the slot contracted with q, 0 if q is not in the block.
@@ -377,6 +404,10 @@ std::string compile_channels(const std::vector<ChannelSpec>& chans, const Compil
   for (auto& kv : op_slot) {
     kv.second = (int)P.op_code.size();
     P.op_code.push_back(kv.first);
+    {
+      int s1 = 0, s2 = 0;
+      P.op_pair.push_back(operator_pair(kv.first, &s1, &s2) ? (s1 | (s2 << 2)) : -1);
+    }
     const OpExpansion e = expand_operator(kv.first);
     int sl[3];
     operator_slots(kv.first, sl);
@@ -418,7 +449,10 @@ std::string compile_channels(const std::vector<ChannelSpec>& chans, const Compil
     for (int s = 0; s < n; ++s) {
       alias[s] = s;
       for (int s0 = 0; s0 < s; ++s0) {
-        if (alias[s0] != s0 || P.op_nterm[s0] != P.op_nterm[s]) continue;
+        // blocks are stored antisymmetrised in their same-flavour slot pair:
+        // two slots are one block only if that pair is the same (n = -p as
+        // plain blocks, but their stored forms differ in the pair)
+        if (alias[s0] != s0 || P.op_nterm[s0] != P.op_nterm[s] || P.op_pair[s0] != P.op_pair[s]) continue;
         bool same = true;
         double c = 0.0;
         for (int k = 0; k < P.op_nterm[s] && same; ++k) {
@@ -448,6 +482,7 @@ std::string compile_channels(const std::vector<ChannelSpec>& chans, const Compil
       const int s = order[i];
       Q.op_code[i] = P.op_code[s];
       Q.op_nterm[i] = P.op_nterm[s];
+      Q.op_pair[i] = P.op_pair[s];
       for (int k = 0; k < 3; ++k) {
         Q.op_term_trip[3 * i + k] = P.op_term_trip[3 * s + k];
         Q.op_term_perm[3 * i + k] = P.op_term_perm[3 * s + k];
@@ -660,9 +695,11 @@ std::string compile_channels(const std::vector<ChannelSpec>& chans, const Compil
           for (int mask = 0; mask < 64; ++mask) {
             if (popcount(mask) != 3) continue;
             const int mask2 = 0x3f & ~mask;
-            Block b1{mask, effective_block(chans[c].sink[0], mask, srcfl)};
-            Block b2{mask2, effective_block(chans[c].sink[1], mask2, srcfl)};
-            if (b1.maps.empty() || b2.maps.empty()) continue;
+            const std::vector<Map> full1 = effective_block(chans[c].sink[0], mask, srcfl);
+            const std::vector<Map> full2 = effective_block(chans[c].sink[1], mask2, srcfl);
+            if (full1.empty() || full2.empty()) continue;
+            Block b1{mask, on_stored_block(chans[c].sink[0], full1)};
+            Block b2{mask2, on_stored_block(chans[c].sink[1], full2)};
             int cross = 0;
             for (int x = 0; x < 6; ++x)
               for (int y = 0; y < 6; ++y)
@@ -689,7 +726,7 @@ std::string compile_channels(const std::vector<ChannelSpec>& chans, const Compil
             // Wick permutations covered, counted on the flavour triplets of the operators
             // every flavour triplet of an operator has the block's slot flavours, so
             // each (triplet, triplet) pair covers maps1 x maps2 permutations
-            C.n_wick += (int64_t)op[0].trip.size() * op[1].trip.size() * b1.maps.size() * b2.maps.size();
+            C.n_wick += (int64_t)op[0].trip.size() * op[1].trip.size() * full1.size() * full2.size();
           }
         }
       // new products this channel would add to the current group
@@ -741,7 +778,7 @@ std::vector<TwoPointTerm> two_point_terms(int sink_op, int src_op) {
   const OpExpansion src = expand_operator(src_op);
   for (size_t k = 0; k < src.trip.size(); ++k) {
     const int srcfl[6] = {src.trip[k].f[0], src.trip[k].f[1], src.trip[k].f[2], -1, -1, -1};
-    for (const Map& mp : effective_block(sink_op, 0x7, srcfl)) {
+    for (const Map& mp : on_stored_block(sink_op, effective_block(sink_op, 0x7, srcfl))) {
       TwoPointTerm t;
       for (int i = 0; i < 3; ++i) t.m[i] = mp.m[i];
       t.coef = src.norm * src.wnum[k] * mp.sign;

@@ -46,6 +46,17 @@ OpExpansion expand_operator(int op);
 // single-term operators, (u, d, s) for the X combinations Lambda and Sigma0.
 void operator_slots(int op, int fl[3]);
 
+// The two slots of an operator block that carry the same flavour (p: the two
+// u slots 0 and 2; n: the d slots 1 and 2; ...), or false when all three
+// differ (X_u, X_d, X_s, Lambda, Sigma0).  For such an operator every
+// flavour-respecting map of its slots onto a set of source quarks comes with
+// its partner that exchanges the quarks of the two slots, with the opposite
+// sign, so the stored block is the antisymmetrised one
+//   A[al][j0][j1][j2] = N[al][j0][j1][j2] - N[al][j0'][j1'][j2'],
+// j' = j with the indices of slots s1 and s2 exchanged, and one map of each
+// partner pair (the one with m[s1] < m[s2]) reads it.
+bool operator_pair(int op, int* s1, int* s2);
+
 struct ChannelSpec {
   int sink[2], src[2];
 };
@@ -109,6 +120,7 @@ struct Program {
   std::vector<int> op_term_trip;    // [slot * 3 + k] triplet code
   std::vector<int> op_term_perm;    // [slot * 3 + k] pi(0) | pi(1) << 2 | pi(2) << 4
   std::vector<double> op_term_w;    // [slot * 3 + k]
+  std::vector<int> op_pair;         // [slot] s1 | s2 << 2 of the antisymmetrised slot pair, or -1
   // Isospin-symmetric limit (S_d = S_u, Sec. 3(i)): slot s equals
   // op_alias_coef[s] times slot op_alias[s]; the n_canon canonical slots
   // come first and are the only ones built in that limit.

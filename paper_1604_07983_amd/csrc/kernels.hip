@@ -118,15 +118,15 @@ __global__ __launch_bounds__(kThreads) void k_nbb(NbbArgs a) {
   for (int op = 0; op < a.n_ops; ++op) {
     cx<T>* out = reinterpret_cast<cx<T>*>(a.Nq) + ((long long)(op * a.t_count + t) * a.V + site) * kBlockEntries;
     const int nt = a.op_nterm[op];
-    for (int o = threadIdx.x; o < kBlockEntries; o += kThreads) {
-      const int al = o / 1728, j0 = (o / 144) % 12, j1 = (o / 12) % 12, j2 = o % 12;
+    const int pair = a.op_pair[op];
+    // N_op[al][j0][j1][j2]
+    auto pick = [](int m, int j0, int j1, int j2) { return m == 0 ? j0 : (m == 1 ? j1 : j2); };
+    auto entry = [&](int al, int j0, int j1, int j2) {
       cx<T> v{0, 0};
       for (int k = 0; k < nt; ++k) {
         const int pm = a.op_perm[op][k];
-        const int p0 = pm & 3, p1 = (pm >> 2) & 3, p2 = (pm >> 4) & 3;
-        const int i0 = p0 == 0 ? j0 : (p0 == 1 ? j1 : j2);
-        const int i1 = p1 == 0 ? j0 : (p1 == 1 ? j1 : j2);
-        const int i2 = p2 == 0 ? j0 : (p2 == 1 ? j1 : j2);
+        const int i0 = pick(pm & 3, j0, j1, j2), i1 = pick((pm >> 2) & 3, j0, j1, j2),
+                  i2 = pick((pm >> 4) & 3, j0, j1, j2);
         const cx<T>* Dd = D[a.op_dq[op][k]];
         const cx<T>* S3 = S[a.op_f3[op][k]];
         cx<T> u{0, 0};
@@ -135,6 +135,25 @@ __global__ __launch_bounds__(kThreads) void k_nbb(NbbArgs a) {
         const T w = (T)a.op_w[op][k];
         v.re = fma(w, u.re, v.re);
         v.im = fma(w, u.im, v.im);
+      }
+      return v;
+    };
+    for (int o = threadIdx.x; o < kBlockEntries; o += kThreads) {
+      const int al = o / 1728, j0 = (o / 144) % 12, j1 = (o / 12) % 12, j2 = o % 12;
+      cx<T> v = entry(al, j0, j1, j2);
+      if (pair >= 0) {
+        // antisymmetrised in the same-flavour slot pair: N - N(s1 <-> s2)
+        const int s1 = pair & 3, s2 = (pair >> 2) & 3;
+        const int a1 = pick(s1, j0, j1, j2), a2 = pick(s2, j0, j1, j2);
+        if (a1 == a2) {
+          v = cx<T>{0, 0};
+        } else {
+          // the third slot keeps its index; the pair's indices are exchanged
+          const int k0 = s1 == 0 ? a2 : (s2 == 0 ? a1 : j0);
+          const int k1 = s1 == 1 ? a2 : (s2 == 1 ? a1 : j1);
+          const int k2 = s1 == 2 ? a2 : (s2 == 2 ? a1 : j2);
+          v = v - entry(al, k0, k1, k2);
+        }
       }
       out[o] = v;
     }

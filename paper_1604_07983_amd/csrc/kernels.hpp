@@ -19,6 +19,9 @@ struct NbbArgs {
   int op_nterm[kMaxOps];
   int op_dq[kMaxOps][3], op_f3[kMaxOps][3], op_perm[kMaxOps][3];  // perm: pi(0) | pi(1) << 2 | pi(2) << 4
   double op_w[kMaxOps][3];
+  // s1 | s2 << 2: the block is stored antisymmetrised in slots s1, s2
+  // (N - N with the two slot indices exchanged); -1: stored as is
+  int op_pair[kMaxOps];
   int flavour_used[3];
   const int* scale_exp;  // [3][t_count] power-of-two exponents (precision form) or null
 };

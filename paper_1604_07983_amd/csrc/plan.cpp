@@ -486,6 +486,7 @@ nbs_status nbs_plan_create(nbs_plan* out, const nbs_geometry* g, int32_t n_geom,
   std::map<int, int> dq;
   for (int s = 0; s < nt; ++s) {
     nb.op_nterm[s] = P.op_nterm[s];
+    nb.op_pair[s] = P.op_pair[s];
     for (int k = 0; k < P.op_nterm[s]; ++k) {
       const int code = P.op_term_trip[3 * s + k];
       const int f1 = code / 9, f2 = (code / 3) % 3, f3 = code % 3;
@@ -907,7 +908,7 @@ nbs_status nbs_plan_table(const nbs_plan p, const char* name, void* buf, int64_t
       {"group_prod", &P.group_prod}, {"group_task", &P.group_task}, {"group_ch", &P.group_ch},
       {"group_channels", &P.group_channels}, {"ch_contrib", &P.ch_contrib}, {"contrib_prod", &P.contrib_prod},
       {"prod_desc", &P.prod_desc}, {"task_lanes", &P.task_lanes}, {"op_alias", &P.op_alias},
-      {"group_op1_iso", &P.group_op1_iso}, {"group_op2_iso", &P.group_op2_iso}};
+      {"group_op1_iso", &P.group_op1_iso}, {"group_op2_iso", &P.group_op2_iso}, {"op_pair", &P.op_pair}};
   auto it = tabs.find(nm);
   if (it == tabs.end()) return NBS_ERR_INVALID;
   *n = (int64_t)it->second->size();

@@ -12,7 +12,7 @@ from __future__ import annotations
 
 import numpy as np
 
-NAMES = ("op_code", "op_nterm", "op_term_trip", "op_term_perm", "op_term_w", "group_op1", "group_op2",
+NAMES = ("op_code", "op_nterm", "op_term_trip", "op_term_perm", "op_term_w", "op_pair", "group_op1", "group_op2",
          "group_prod", "group_task", "group_ch", "group_channels", "ch_contrib", "contrib_prod",
          "contrib_coef", "prod_desc", "task_lanes")
 PROD_INTS = 48
@@ -40,6 +40,11 @@ def operator_blocks(T, triplet_blocks):
             blk = np.transpose(triplet_blocks[code], (0, 1, 2 + sigma[0], 2 + sigma[1], 2 + sigma[2]))
             term = T["op_term_w"][3 * s + k] * blk
             acc = term if acc is None else acc + term
+        pair = int(T["op_pair"][s])
+        if pair >= 0:
+            # stored antisymmetrised in the same-flavour slot pair (s1, s2)
+            s1, s2 = pair & 3, (pair >> 2) & 3
+            acc = acc - np.swapaxes(acc, 2 + s1, 2 + s2)
         out.append(acc.reshape(acc.shape[0], 3456))
     return out
 
