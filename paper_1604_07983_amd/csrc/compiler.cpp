@@ -258,6 +258,136 @@ void fill_split_offsets(const Block& b1, const Block& b2, int* d) {
   }
 }
 
+// ---- segment program of the matrix-core contraction (compiler.hpp) -----------
+
+// Row-offset generator of a block side: row r = (al n3 + a3) n4 + a4 sits at
+// (r & 1) w0 + ((r >> 1) & 1) w1 + ((r >> 2) & 1) w2.
+void row_generator(const Shape& sh, const Map& mp, int w[3]) {
+  int lw[2];
+  label_weights(sh, mp, lw);
+  const int nl = (sh.lbl3 ? 1 : 0) + (sh.lbl4 ? 1 : 0);
+  w[0] = nl == 0 ? nbs::kLdsAl : lw[0];
+  w[1] = nl == 0 ? 0 : (nl == 1 ? nbs::kLdsAl : lw[1]);
+  w[2] = nl == 2 ? nbs::kLdsAl : 0;
+}
+
+// Shape, side fields and sign of the segments of one block product (one
+// map per block: operators with a same-flavour slot pair are read
+// antisymmetrised).  Returns false for a shape the kernel lacks.
+bool segment_fields(const Block& b1, const Block& b2, int* shape, int* steps, int hdr3, int* d) {
+  const Shape s1 = shape_of(b1.mask), s2 = shape_of(b2.mask);
+  if (b1.maps.size() != 1 || b2.maps.size() != 1) return false;
+  const Map& m1 = b1.maps[0];
+  const Map& m2 = b2.maps[0];
+  int side1[6], side2[6];
+  if (s1.K() == 1) {
+    const int base1 = s1.kA == 3 ? 0 : 3, base2 = 3 - base1;
+    side1[0] = quark_unit(m1, base1 + 2); side1[1] = quark_unit(m1, base1); side1[2] = quark_unit(m1, base1 + 1);
+    side2[0] = quark_unit(m2, base2 + 2); side2[1] = quark_unit(m2, base2); side2[2] = quark_unit(m2, base2 + 1);
+    *shape = kSegC1;
+    *steps = 1;
+  } else {
+    const bool pairA = s1.kA == 2;
+    const int base1 = pairA ? 0 : 3, base2 = pairA ? 3 : 0;
+    const int lone1 = (pairA ? s1.loneA : s1.loneB) - base1;
+    const int lone2 = (pairA ? s2.loneB : s2.loneA) - base2;
+    const int p1 = base1 + (lone1 == 0 ? 1 : 0), q1 = base1 + (lone1 == 2 ? 1 : 2);
+    const int p2 = base2 + (lone2 == 0 ? 1 : 0), q2 = base2 + (lone2 == 2 ? 1 : 2);
+    const int ys = base1 + lone1, zs = base2 + lone2;
+    // block 1: pair indexed by y, single quark zs; block 2: single ys, pair by z
+    side1[0] = quark_unit(m1, zs); side1[1] = quark_unit(m1, p1); side1[2] = quark_unit(m1, q1);
+    side2[0] = quark_unit(m2, ys); side2[1] = quark_unit(m2, p2); side2[2] = quark_unit(m2, q2);
+    if (lone1 < 2 && lone2 < 2) { *shape = kSegC144; *steps = 36; }
+    else if (lone1 == 2 && lone2 == 2) { *shape = kSegC9; *steps = 3; }
+    else { *shape = kSegC36; *steps = 18; }
+  }
+  row_generator(s1, m1, side1 + 3);
+  row_generator(s2, m2, side2 + 3);
+  // the 2 x 8 products run transposed: block 2 (8 rows) is side A
+  const bool transposed = *shape == kSegC36 && s1.rows() == 2;
+  const int* sa = transposed ? side2 : side1;
+  const int* sb = transposed ? side1 : side2;
+  d[0] = *shape;
+  d[3] = hdr3 | ((m1.sign * m2.sign < 0) << 16) | (transposed << 17);
+  for (int i = 0; i < 6; ++i) {
+    d[4 + i] = sa[i];
+    d[10 + i] = sb[i];
+  }
+  return true;
+}
+
+// Cost of one step of a segment shape for one lane (block entries read) and
+// of a segment's set-up and result store, in the same units.
+double seg_step_cost(int shape) {
+  return shape == kSegC144 ? 4.0 : shape == kSegC9 ? 16.0 : shape == kSegC36 ? 10.0 : 24.0;
+}
+constexpr double kSegOverhead = 8.0;
+
+struct SegPlan {
+  std::vector<std::vector<int>> tasks;  // per task kSegTeams * kSegInts ints
+  std::vector<int> ext;                 // per product
+  int slots = 0;
+  double makespan = 0.0;
+};
+
+// Cut the products into segments (lengths l144 and l36 steps, aligned so a
+// segment starts where its lanes' pair indices start a new value), put
+// segments of one shape and one step count four to a task, and balance the
+// tasks over `waves` wavefronts longest first.
+SegPlan plan_segments(const std::vector<std::vector<int>>& base, const std::vector<int>& steps, int l144, int l36,
+                      int waves) {
+  SegPlan sp;
+  const int np = (int)base.size();
+  sp.ext.assign(np, 0);
+  int next_slot = np;
+  std::map<std::pair<int, int>, std::vector<std::vector<int>>> by_key;  // (shape, steps) -> descriptors
+  for (int p = 0; p < np; ++p) {
+    const int shape = base[p][0];
+    const int L = shape == kSegC144 ? l144 : shape == kSegC36 ? l36 : steps[p];
+    int n_extra = 0;
+    for (int s0 = 0; s0 < steps[p]; s0 += L) {
+      std::vector<int> d = base[p];
+      const int n = std::min(L, steps[p] - s0);
+      const int slot = s0 == 0 ? p : next_slot + n_extra++;
+      d[1] = s0;
+      d[2] = n;
+      d[3] = (d[3] & ~0xffff) | slot;
+      by_key[{shape, n}].push_back(d);
+    }
+    if (n_extra) sp.ext[p] = next_slot | (n_extra << 16);
+    next_slot += n_extra;
+  }
+  sp.slots = next_slot;
+  std::vector<double> cost;
+  for (auto& kv : by_key) {
+    auto& segs = kv.second;
+    for (size_t i = 0; i < segs.size(); i += kSegTeams) {
+      std::vector<int> t(kSegTeams * kSegInts, 0);
+      for (int k = 0; k < kSegTeams; ++k) {
+        int* d = t.data() + k * kSegInts;
+        if (i + k < segs.size()) {
+          std::copy(segs[i + k].begin(), segs[i + k].end(), d);
+        } else {
+          d[0] = kSegIdle;
+          d[2] = kv.first.second;
+        }
+      }
+      sp.tasks.push_back(t);
+      cost.push_back(kv.first.second * seg_step_cost(kv.first.first) + kSegOverhead);
+    }
+  }
+  std::vector<int> ord(sp.tasks.size());
+  for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int)i;
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  std::vector<double> load(std::max(1, waves), 0.0);
+  for (int i : ord) *std::min_element(load.begin(), load.end()) += cost[i];
+  sp.makespan = *std::max_element(load.begin(), load.end());
+  std::vector<std::vector<int>> sorted;
+  for (int i : ord) sorted.push_back(sp.tasks[i]);
+  sp.tasks = sorted;
+  return sp;
+}
+
 // Lane layout of one block product inside a task (see the lane word).
 struct TeamUnit {
   int p;        // product (local index)
@@ -511,6 +641,8 @@ std::string compile_channels(const std::vector<ChannelSpec>& chans, const Compil
 
   P.group_prod.push_back(0);
   P.group_task.push_back(0);
+  P.group_stask.push_back(0);
+  std::string seg_error;
   P.group_ch.push_back(0);
   P.ch_contrib.push_back(0);
   std::set<Block> all_blocks[2];
@@ -587,6 +719,38 @@ std::string compile_channels(const std::vector<ChannelSpec>& chans, const Compil
         if (s1.K() > 1) fill_split_offsets(prods[p].first, prods[p].second, d);
         P.prod_desc.insert(P.prod_desc.end(), d, d + kProdInts);
         C.product_k += s1.K();
+      }
+      // matrix-core program: segments of each product, packed into tasks
+      {
+        std::vector<std::vector<int>> base;
+        std::vector<int> nsteps;
+        bool ok = true;
+        for (int p : order_p) {
+          std::vector<int> d(kSegInts, 0);
+          int shape = 0, st = 0;
+          if (!segment_fields(prods[p].first, prods[p].second, &shape, &st, 0, d.data())) ok = false;
+          base.push_back(d);
+          nsteps.push_back(st);
+        }
+        if (!ok) seg_error = "a block product has no matrix-core shape";
+        SegPlan best;
+        bool have = false;
+        for (int l144 : {36, 18, 12, 9, 6, 3})
+          for (int l36 : {18, 12, 6}) {
+            SegPlan sp = plan_segments(base, nsteps, l144, l36, opt.seg_waves);
+            if (sp.slots > opt.max_group_slots) continue;
+            if (!have || sp.makespan < best.makespan - 1e-9 ||
+                (std::fabs(sp.makespan - best.makespan) <= 1e-9 && sp.slots < best.slots)) {
+              best = sp;
+              have = true;
+            }
+          }
+        if (!have) seg_error = "a channel group needs more result slots than the contraction holds";
+        for (const auto& t : best.tasks) P.seg_task.insert(P.seg_task.end(), t.begin(), t.end());
+        P.prod_ext.insert(P.prod_ext.end(), best.ext.begin(), best.ext.end());
+        P.group_stask.push_back((int)(P.seg_task.size() / (kSegTeams * kSegInts)));
+        P.max_group_slots = std::max(P.max_group_slots, best.slots);
+        P.max_group_stasks = std::max(P.max_group_stasks, (int)best.tasks.size());
       }
       // lanes: one team per product; the walked index may be split over
       // 2^zsl lane sets (a larger team, fewer steps per lane).  The split is
@@ -757,6 +921,8 @@ std::string compile_channels(const std::vector<ChannelSpec>& chans, const Compil
     }
     if (!gch.empty()) flush(gch);
   }
+
+  if (!seg_error.empty()) return seg_error;
 
   // ---- 3. statistics ---------------------------------------------------------
   for (int side = 0; side < 2; ++side)

@@ -111,6 +111,37 @@ constexpr int kClassIdle = 30;
 constexpr int kClassSplitAny = 31;
 int product_class(int K, int rows1, int lone1, int lone2, int nm1, int nm2);
 
+// ---- segment program of the matrix-core contraction ------------------------
+// Each block product F[r1][r2] = sum_k E1[r1][k] E2[r2][k] (Eq. (10)) is
+// cut into segments of consecutive steps; a step feeds one 4 x 4 x 4 (FP64)
+// or four 4 x 4 x 1 (FP32) matrix products of a 16-lane team, lane (h, x)
+// supplying row x of both effective blocks at shared-index slot k' = 4 s + h.
+// Shapes (the product class):
+//   kSegC144: 4 x 4 rows, both lone quarks spin-colour (K = 144); shared
+//             index k' = 12 v1 + v2, v1 = s / 3, v2 = 4 (s % 3) + h
+//   kSegC9:   4 x 4 rows, both lone quarks colour only (K = 9): k' = 3 v1 + v2
+//   kSegC36:  8 x 2 rows (the 2-term side A has 8 rows, the 8-term side B 2):
+//             side A row r = x + 4 b', k' = 2 k + b', k = 12 v2 + v1; side B
+//             feeds E_B[x & 1][k] on lanes with x >> 1 == b', zero elsewhere
+//   kSegC1:   two full projections (K = 1): the 24 source-tensor terms of
+//             each side are spread over the four h lanes and summed first
+// Side A of a product is block 1 (sink operator at +q) except for the
+// transposed 2 x 8 products, whose 8-row side is block 2.  On side A the
+// pair of source quarks is indexed by v1 and the single quark by v2; on side
+// B the pair by v2 and the single by v1.
+// Descriptor (kSegInts ints):
+//   [0] shape  [1] first step  [2] steps  [3] result slot | (sign < 0) << 16 |
+//   transposed << 17
+//   [4..9]   side A: unit of the single quark, units of the pair's two
+//            quarks, row weights w0, w1, w2 (row r at (r & 1) w0 +
+//            ((r >> 1) & 1) w1 + ((r >> 2) & 1) w2)
+//   [10..15] side B, the same fields
+// For kSegC1 the three units are those of the baryon's quarks 2, 0, 1.
+// The first segment of product p writes result slot p; further segments
+// take slots from the number of products on, and prod_ext[p] = first extra
+// slot | count << 16 lists them for the sum that precedes the channel sums.
+// (the shape codes kSegC144 .. kSegIdle are defined in kernels.hpp)
+
 struct Program {
   // operator blocks built by the NBB kernel: slot -> operator code and
   // recipe N_op = sum_k w_k N_{f1 f2 f3}[al][j_{pi(0)}][j_{pi(1)}][j_{pi(2)}]
@@ -143,6 +174,14 @@ struct Program {
   std::vector<double> contrib_coef_iso;
   std::vector<int> prod_desc;
   std::vector<int> task_lanes;
+  // matrix-core program: tasks of kSegTeams segment descriptors (wavefront-
+  // uniform shape and step count), per group a range of tasks, per product
+  // its extra result slots
+  std::vector<int> seg_task;      // [task][team][kSegInts]
+  std::vector<int> group_stask;   // n_groups + 1
+  std::vector<int> prod_ext;      // per product (global index)
+  int max_group_slots = 0;        // result slots (products + extra segments)
+  int max_group_stasks = 0;
   int max_group_products = 0;
   int max_group_channels = 0;
   int max_group_contrib = 0;
@@ -152,6 +191,8 @@ struct Program {
 struct CompileOptions {
   int max_group_products = 88;  // LDS result buffer bound per group
   int waves = 8;                // wavefronts of a contraction workgroup
+  int seg_waves = 16;           // wavefronts of a matrix-core contraction workgroup
+  int max_group_slots = 160;    // result slots of the matrix-core contraction
   bool split = true;            // may split a product's walked index over lanes
   bool mfma = false;            // 4 x 4-row split products on matrix cores (precision form)
 };

@@ -1342,6 +1342,422 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Effective blocks and their products on the matrix cores (Sec. 4(ii)-(iii),
+// Eqs. (9)-(10)).
+//
+// One workgroup per (slice, momentum q) walks the sink-operator groups as
+// the lane-team kernel above does, staging the two operator blocks in LDS.
+// The products of a group come as segments (compiler.hpp): a 16-lane team
+// takes one segment, and at every step lane (h, x) forms row x of both
+// effective blocks at shared-index slot k' = 4 s + h from the staged blocks
+// (the source-tensor sums of Eq. (9): two terms per entry where the block
+// holds a quark pair with a spin-colour lone partner, eight where the lone
+// partner is a third quark, 24 for a whole baryon), and the team's matrix
+// product accumulates E_A E_B^T: v_mfma_f64_4x4x4f64 (4 blocks of
+// 4 x 4 x 4, lanes 16 k + 4 b + i) in FP64, v_mfma_f32_4x4x1f32 (16 blocks
+// of 4 x 4 x 1, lanes 4 b + i) in the precision form, where the four quads
+// of a team hold four slots k' and are summed at the end.  Complex products
+// take three accumulators: re re, im im and the two cross terms.
+// Segments of one product write separate result slots, summed before the
+// channel sums, so the result does not depend on the order in which
+// wavefronts finish.
+// ---------------------------------------------------------------------------
+template <typename T> struct SegAcc;
+template <> struct SegAcc<double> {
+  double rr, ii, ri;
+};
+template <> struct SegAcc<float> {
+  f32x4 rr, ii, ri;
+};
+
+__device__ __forceinline__ void seg_zero(SegAcc<double>& c) { c.rr = c.ii = c.ri = 0.0; }
+__device__ __forceinline__ void seg_zero(SegAcc<float>& c) {
+  c.rr = f32x4{0.f, 0.f, 0.f, 0.f};
+  c.ii = c.rr;
+  c.ri = c.rr;
+}
+__device__ __forceinline__ void seg_mma(SegAcc<double>& c, cd a, cd b) {
+  c.rr = __builtin_amdgcn_mfma_f64_4x4x4f64(a.re, b.re, c.rr, 0, 0, 0);
+  c.ii = __builtin_amdgcn_mfma_f64_4x4x4f64(a.im, b.im, c.ii, 0, 0, 0);
+  c.ri = __builtin_amdgcn_mfma_f64_4x4x4f64(a.re, b.im, c.ri, 0, 0, 0);
+  c.ri = __builtin_amdgcn_mfma_f64_4x4x4f64(a.im, b.re, c.ri, 0, 0, 0);
+}
+__device__ __forceinline__ void seg_mma(SegAcc<float>& c, cf a, cf b) {
+  c.rr = __builtin_amdgcn_mfma_f32_4x4x1f32(a.re, b.re, c.rr, 0, 0, 0);
+  c.ii = __builtin_amdgcn_mfma_f32_4x4x1f32(a.im, b.im, c.ii, 0, 0, 0);
+  c.ri = __builtin_amdgcn_mfma_f32_4x4x1f32(a.re, b.im, c.ri, 0, 0, 0);
+  c.ri = __builtin_amdgcn_mfma_f32_4x4x1f32(a.im, b.re, c.ri, 0, 0, 0);
+}
+
+// Lane roles: team tm (0..3) of the wavefront, shared-index slot h (0..3),
+// row x (0..3).  FP64: lane 16 h + 4 tm + x (the 4 x 4 x 4 block layout);
+// FP32: lane 16 tm + 4 h + x (quad 4 tm + h of the 4 x 4 x 1 layout).
+template <typename T> __device__ __forceinline__ void seg_roles(int lane, int& tm, int& h, int& x) {
+  x = lane & 3;
+  if constexpr (sizeof(T) == 8) {
+    h = lane >> 4;
+    tm = (lane >> 2) & 3;
+  } else {
+    tm = lane >> 4;
+    h = (lane >> 2) & 3;
+  }
+}
+
+// Sum over the four slots h of a team (the lanes that differ in h only).
+template <typename T> __device__ __forceinline__ T seg_hsum(T v) {
+  constexpr int s0 = sizeof(T) == 8 ? 16 : 4, s1 = sizeof(T) == 8 ? 32 : 8;
+  v += __shfl_xor(v, s0);
+  v += __shfl_xor(v, s1);
+  return v;
+}
+
+__device__ __forceinline__ int seg_row(int r, const int* w) {
+  return (r & 1) * w[0] + ((r >> 1) & 1) * w[1] + ((r >> 2) & 1) * w[2];
+}
+
+// Pair of a source baryon whose lone quark (quark 0 or 1, shared index
+// v = 3 s + c) sits in the other block: two terms, the pair's quark p at
+// 3 (s ^ 1) + (c + 1 + t) % 3 and its third quark q (spin: a label) at colour
+// (c + 2 - t) % 3, coefficient (t ? -1 : 1) (s odd ? -1 : 1).  Returns the
+// two offsets and the sign of term 0.
+__device__ __forceinline__ int seg_pair2(int v, int up, int uq, int& o0, int& o1) {
+  const int sp = v / 3, c = v - 3 * sp;
+  const int c1 = c == 2 ? 0 : c + 1, c2 = c == 0 ? 2 : c - 1;
+  const int jp = 3 * (sp ^ 1);
+  o0 = (jp + c1) * up + c2 * uq;
+  o1 = (jp + c2) * up + c1 * uq;
+  return (sp & 1) ? -1 : 1;
+}
+
+// Pair of a source baryon whose lone quark is its third quark (shared index
+// v = its colour c): terms (cc, sp) with quark p at 3 sp + (c + 1 + cc) % 3,
+// quark q at 3 (sp ^ 1) + (c + 2 - cc) % 3, coefficient (cc ? -1 : 1)
+// (sp odd ? -1 : 1).  Colour parts of the two colour orders.
+__device__ __forceinline__ void seg_pair8(int c, int up, int uq, int& o0, int& o1) {
+  const int c1 = c == 2 ? 0 : c + 1, c2 = c == 0 ? 2 : c - 1;
+  o0 = c1 * up + c2 * uq;
+  o1 = c2 * up + c1 * uq;
+}
+
+// Entry of a side with an eight-term pair: sum over the spin sp of the
+// pair's first quark (spin offsets so[sp]) and the two colour orders.
+template <typename T>
+__device__ __forceinline__ cx<T> seg_entry8(const cx<T>* S, int base, const int so[4], int o0, int o1) {
+  cx<T> e{0, 0};
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp) {
+    const cx<T> u = S[base + so[sp] + o0], w = S[base + so[sp] + o1];
+    if (sp & 1) {
+      e.re += w.re - u.re;
+      e.im += w.im - u.im;
+    } else {
+      e.re += u.re - w.re;
+      e.im += u.im - w.im;
+    }
+  }
+  return e;
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> seg_entry2(const cx<T>* S, int base, int o0, int o1, int sg) {
+  const cx<T> u = S[base + o0], w = S[base + o1];
+  return sg > 0 ? cx<T>{u.re - w.re, u.im - w.im} : cx<T>{w.re - u.re, w.im - u.im};
+}
+
+// One segment of a team.  d: the team's descriptor; SA, SB: the staged
+// blocks of sides A and B; R: result slots (16 complex each).
+template <typename T>
+__device__ __forceinline__ void seg_run(const int* d, const cx<T>* S1, const cx<T>* S2, cx<T>* R, int shape,
+                                        int nsteps, int lane) {
+  int tm, h, x;
+  seg_roles<T>(lane, tm, h, x);
+  (void)tm;
+  const bool live = d[0] != kSegIdle;
+  const int s0 = d[1], hdr = d[3];
+  const bool transposed = (hdr >> 17) & 1;
+  const cx<T>* SA = transposed ? S2 : S1;
+  const cx<T>* SB = transposed ? S1 : S2;
+  int wa[3] = {d[7], d[8], d[9]}, wb[3] = {d[13], d[14], d[15]};
+  const int uAs = d[4], uAp = d[5], uAq = d[6];
+  const int uBs = d[10], uBp = d[11], uBq = d[12];
+  SegAcc<T> acc;
+  seg_zero(acc);
+  const cx<T> zero{0, 0};
+  if (shape == kSegC144) {
+    // v1 = s / 3 (side A's pair, side B's single quark), v2 = 4 (s % 3) + h
+    const int roA = seg_row(x, wa), roB = seg_row(x, wb);
+    int oB0[3], oB1[3], gB[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) gB[m] = seg_pair2(4 * m + h, uBp, uBq, oB0[m], oB1[m]);
+    // nsteps is wavefront-uniform: the loop runs the same count on every lane
+    for (int it = 0; it < nsteps / 3; ++it) {
+      const int v1 = s0 / 3 + it;
+      int oA0, oA1;
+      const int gA = seg_pair2(v1, uAp, uAq, oA0, oA1);
+      const int bB = roB + v1 * uBs;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        cx<T> a = zero, b = zero;
+        if (live) {
+          const int bA = roA + (4 * m + h) * uAs;
+          a = seg_entry2<T>(SA, bA, oA0, oA1, gA);
+          b = seg_entry2<T>(SB, bB, oB0[m], oB1[m], gB[m]);
+        }
+        seg_mma(acc, a, b);
+      }
+    }
+  } else if (shape == kSegC36) {
+    // k = 2 s + (h >> 1), b' = h & 1: side A row x + 4 b' at (v1, v2) =
+    // (k % 12, k / 12); side B row x & 1 on lanes with x >> 1 == b'
+    const int bp = h & 1;
+    const int roA = seg_row(x + 4 * bp, wa), roB = seg_row(x & 1, wb);
+    const bool bl = live && (x >> 1) == bp;
+    int so[4];
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp) so[sp] = 3 * sp * uBp + 3 * (sp ^ 1) * uBq;
+    for (int it = 0; it < nsteps; ++it) {
+      const int k = 2 * (s0 + it) + (h >> 1);
+      const int v2 = k / 12, v1 = k - 12 * v2;
+      cx<T> a = zero, b = zero;
+      if (live) {
+        int oA0, oA1;
+        const int gA = seg_pair2(v1, uAp, uAq, oA0, oA1);
+        a = seg_entry2<T>(SA, roA + v2 * uAs, oA0, oA1, gA);
+      }
+      if (bl) {
+        int o0, o1;
+        seg_pair8(v2, uBp, uBq, o0, o1);
+        b = seg_entry8<T>(SB, roB + v1 * uBs, so, o0, o1);
+      }
+      seg_mma(acc, a, b);
+    }
+  } else if (shape == kSegC9) {
+    // k' = 4 s + h = 3 v1 + v2 < 9
+    const int roA = seg_row(x, wa), roB = seg_row(x, wb);
+    int soA[4], soB[4];
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp) {
+      soA[sp] = 3 * sp * uAp + 3 * (sp ^ 1) * uAq;
+      soB[sp] = 3 * sp * uBp + 3 * (sp ^ 1) * uBq;
+    }
+    for (int it = 0; it < nsteps; ++it) {
+      const int kk = 4 * (s0 + it) + h;
+      const int v1 = kk / 3, v2 = kk - 3 * v1;
+      cx<T> a = zero, b = zero;
+      if (live && kk < 9) {
+        int o0, o1;
+        seg_pair8(v1, uAp, uAq, o0, o1);
+        a = seg_entry8<T>(SA, roA + v2 * uAs, soA, o0, o1);
+        seg_pair8(v2, uBp, uBq, o0, o1);
+        b = seg_entry8<T>(SB, roB + v1 * uBs, soB, o0, o1);
+      }
+      seg_mma(acc, a, b);
+    }
+  } else {
+    // two whole baryons: lane h takes the terms with the first quark's spin
+    // h, (C g5)_{h, h ^ 1} = (h odd ? -1 : 1), and the six colour orders
+    const int roA = seg_row(x, wa), roB = seg_row(x, wb);
+    auto whole = [&](const cx<T>* S, int ro, int u2, int u0, int u1) {
+      const int b = ro + 3 * h * u0 + 3 * (h ^ 1) * u1;
+      cx<T> e{0, 0};
+#pragma unroll
+      for (int cp = 0; cp < 6; ++cp) {
+        const int c0 = cp < 3 ? cp : cp - 3;
+        const int c1 = cp < 3 ? (c0 + 1) % 3 : (c0 + 2) % 3;
+        const int c2 = cp < 3 ? (c0 + 2) % 3 : (c0 + 1) % 3;
+        const cx<T> v = S[b + c0 * u0 + c1 * u1 + c2 * u2];
+        if (cp < 3) {
+          e.re += v.re;
+          e.im += v.im;
+        } else {
+          e.re -= v.re;
+          e.im -= v.im;
+        }
+      }
+      if (h & 1) e = cx<T>{-e.re, -e.im};
+      return e;
+    };
+    cx<T> a = zero, b = zero;
+    if (live) {
+      a = whole(SA, roA, uAs, uAp, uAq);
+      b = whole(SB, roB, uBs, uBp, uBq);
+    }
+    a.re = seg_hsum(a.re);
+    a.im = seg_hsum(a.im);
+    b.re = seg_hsum(b.re);
+    b.im = seg_hsum(b.im);
+    if (h != 0) a = b = zero;
+    seg_mma(acc, a, b);
+  }
+  // results: D[i][j] = sum_k E_A[i][k] E_B[j][k]; canonical slot entry
+  // r1 * rows2 + r2 with (r1, r2) the rows of blocks 1 and 2
+  const T sgn = ((hdr >> 16) & 1) ? (T)-1 : (T)1;
+  const int slot = hdr & 0xffff;
+  auto put = [&](int i, int j, T re, T im) {
+    int idx;
+    if (shape == kSegC36) {
+      const int ra = i + 4 * (j >> 1), rb = j & 1;
+      idx = transposed ? rb * 8 + ra : ra * 2 + rb;
+    } else {
+      idx = i * 4 + j;
+    }
+    R[slot * 16 + idx] = cx<T>{sgn * re, sgn * im};
+  };
+  if constexpr (sizeof(T) == 8) {
+    if (live) put(h, x, acc.rr - acc.ii, acc.ri);
+  } else {
+    // the four quads of the team hold partial sums over their slots h
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      acc.rr[i] = seg_hsum(acc.rr[i]);
+      acc.ii[i] = seg_hsum(acc.ii[i]);
+      acc.ri[i] = seg_hsum(acc.ri[i]);
+    }
+    if (live && h == 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) put(i, x, acc.rr[i] - acc.ii[i], acc.ri[i]);
+    }
+  }
+}
+
+size_t contract_seg_lds_bytes(int prec, int max_gslots, int max_gcontrib, int max_gch) {
+  const size_t el = prec == 0 ? sizeof(cd) : sizeof(cf);
+  const size_t real = prec == 0 ? sizeof(double) : sizeof(float);
+  return el * (2 * (size_t)kLdsBlock + (size_t)max_gslots * 16) + real * max_gcontrib +
+         sizeof(int) * (max_gcontrib + max_gch + 1 + 1);
+}
+
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_contract_seg(ContractArgs a) {
+  extern __shared__ __align__(16) char smem_raw[];
+  const long long nb8 = (a.n_chunk + 7) / 8 * 8;
+  const long long b = blockIdx.x;
+  const long long local = (b % 8) * (nb8 / 8) + b / 8;
+  if (local >= a.n_chunk) return;
+  const long long logical = a.block0 + local;
+  const long long qtl = logical / a.n_gchunk;
+  const int chunk = (int)(logical - qtl * a.n_gchunk);
+  const ContractGeom G = find_geometry(a.geo, a.n_geom, qtl);
+  const long long qt = qtl - G.block0;
+  const int t = (int)(qt / G.V), q = (int)(qt % G.V);
+  const int qx = q % G.Lx, qy = (q / G.Lx) % G.Ly, qz = q / (G.Lx * G.Ly);
+  const int mq = (G.Lx - qx) % G.Lx + G.Lx * ((G.Ly - qy) % G.Ly + G.Ly * ((G.Lz - qz) % G.Lz));
+  cx<T>* const slotA = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* const slotB = slotA + kLdsBlock;
+  cx<T>* const R = slotB + kLdsBlock;
+  T* const ccoef = reinterpret_cast<T*>(R + a.max_gslots * 16);
+  int* const cword = reinterpret_cast<int*>(ccoef + a.max_gcontrib);
+  int* const coff = cword + a.max_gcontrib;
+  int* const counter = coff + a.max_gch + 1;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const cx<T>* Nq = reinterpret_cast<const cx<T>*>(G.Nq);
+  const int gbeg = a.gchunk[chunk], gend = a.gchunk[chunk + 1];
+  for (int g = gbeg; g < gend; ++g) {
+    // stage the blocks whose operator changed (every global load before the
+    // first LDS store) and the group's channel contributions
+    const bool newA = g == gbeg || a.group_op1[g] != a.group_op1[g - 1];
+    const bool newB = g == gbeg || a.group_op2[g] != a.group_op2[g - 1];
+    using gptr = const __attribute__((address_space(1))) cx<T>*;
+    const gptr gA = (gptr)(Nq + ((long long)(a.group_op1[g] * G.t_count + t) * G.V + q) * kBlockEntries);
+    const gptr gB = (gptr)(Nq + ((long long)(a.group_op2[g] * G.t_count + t) * G.V + mq) * kBlockEntries);
+    constexpr int kPer = (kBlockEntries + NT - 1) / NT;
+    cx<T> va[kPer], vb[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int i = tid + k * NT;
+      const int ii = i < kBlockEntries ? i : kBlockEntries - 1;
+      if (newA) va[k] = cx<T>{gA[ii].re, gA[ii].im};
+      if (newB) vb[k] = cx<T>{gB[ii].re, gB[ii].im};
+    }
+    const int gc0 = a.group_ch[g], nch = a.group_ch[g + 1] - gc0;
+    const int cbase = a.ch_contrib[gc0], ncon = a.ch_contrib[gc0 + nch] - cbase;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int i = tid + k * NT;
+      if (i < kBlockEntries) {
+        if (newA) slotA[lds_index(i)] = va[k];
+        if (newB) slotB[lds_index(i)] = vb[k];
+      }
+    }
+    for (int i = tid; i < ncon; i += NT) {
+      cword[i] = a.contrib_prod[cbase + i];
+      ccoef[i] = (T)a.contrib_coef[cbase + i];
+    }
+    if (tid <= nch) coff[tid] = a.ch_contrib[gc0 + tid] - cbase;
+    if (tid == 0) *counter = 0;
+    __syncthreads();
+
+    // products: wavefronts claim tasks (longest first) from the counter
+    const int tb = a.group_stask[g], ntask = a.group_stask[g + 1] - tb;
+    for (;;) {
+      int claim = 0;
+      if (lane == 0) claim = atomicAdd(counter, 1);
+      const int tix = __builtin_amdgcn_readfirstlane(__shfl(claim, 0));
+      if (tix >= ntask) break;
+      int tm, h, x;
+      seg_roles<T>(lane, tm, h, x);
+      (void)h;
+      (void)x;
+      const int* dt = a.seg_task + (long long)(tb + tix) * (kSegTeams * kSegInts);
+      const int shape = __builtin_amdgcn_readfirstlane(dt[0]);
+      const int nsteps = __builtin_amdgcn_readfirstlane(dt[2]);
+      int d[kSegInts];
+#pragma unroll
+      for (int k = 0; k < kSegInts; ++k) d[k] = dt[tm * kSegInts + k];
+      seg_run<T>(d, slotA, slotB, R, shape, nsteps, lane);
+    }
+    __syncthreads();
+
+    // segments of one product: sum into the product's first slot
+    const int pbase = a.group_prod[g], nprod = a.group_prod[g + 1] - pbase;
+    for (int i = tid; i < nprod * 16; i += NT) {
+      const int p = i >> 4, o = i & 15;
+      const int ext = a.prod_ext[pbase + p];
+      const int ne = ext >> 16, e0 = ext & 0xffff;
+      if (ne > 0) {
+        cx<T> v = R[p * 16 + o];
+        for (int e = 0; e < ne; ++e) v += R[(e0 + e) * 16 + o];
+        R[p * 16 + o] = v;
+      }
+    }
+    __syncthreads();
+
+    // channel sums: 8 lanes per output (spin s of local channel cl)
+    cx<T>* Ft = reinterpret_cast<cx<T>*>(G.Ft);
+    for (int i0 = 0; i0 < nch * 16 * 8; i0 += NT) {
+      const int i = i0 + tid;
+      const int o = i >> 3, sub = i & 7;
+      const int cl = o >> 4, s = o & 15;
+      cx<T> v{0, 0};
+      if (cl < nch) {
+        const int a1 = (s >> 3) & 1, a2 = (s >> 2) & 1, a3 = (s >> 1) & 1, a4 = s & 1;
+        for (int c = coff[cl] + sub; c < coff[cl + 1]; c += 8) {
+          const int w = cword[c];
+          const int p = w & 0xffff, rows2 = 16 / ((w >> 16) & 15);
+          const bool l3 = (w >> 20) & 1, l4 = (w >> 21) & 1;
+          const int r1 = (a1 * (l3 ? 2 : 1) + (l3 ? a3 : 0)) * (l4 ? 2 : 1) + (l4 ? a4 : 0);
+          const int r2 = (a2 * (l3 ? 1 : 2) + (l3 ? 0 : a3)) * (l4 ? 1 : 2) + (l4 ? 0 : a4);
+          const T cf = ccoef[c];
+          const cx<T> xv = R[p * 16 + r1 * rows2 + r2];
+          v.re = fma(cf, xv.re, v.re);
+          v.im = fma(cf, xv.im, v.im);
+        }
+      }
+#pragma unroll
+      for (int dd = 1; dd < 8; dd <<= 1) {
+        v.re += __shfl_xor(v.re, dd);
+        v.im += __shfl_xor(v.im, dd);
+      }
+      if (cl < nch && sub == 0) {
+        const int ch = a.group_channels[gc0 + cl];
+        Ft[(((long long)ch * G.t_count + t) * 16 + s) * G.V + q] = v;
+      }
+    }
+    __syncthreads();  // LDS is restaged for the next group
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Zero-momentum single-baryon two-point functions (Eq. (1) with one baryon
 // on each side): workgroup (pair, slice), one wavefront.  Lane i takes the
 // (term, source spin, source-tensor term) items i, i + 64, ...: the source
@@ -1578,7 +1994,7 @@ hipError_t launch_fft_pass(int kind, const FftArgs& a, hipStream_t st) {
 
 int contract_waves(int prec) { return prec == 0 ? 8 : 4; }
 
-hipError_t prepare_kernels(int prec, int waves, size_t contract_lds) {
+hipError_t prepare_kernels(int prec, int waves, size_t contract_lds, int engine) {
   const int mx = 160 * 1024;
   hipError_t e = hipSuccess;
   auto set = [&](const void* f, int bytes) {
@@ -1597,17 +2013,25 @@ hipError_t prepare_kernels(int prec, int waves, size_t contract_lds) {
   set((const void*)k_fft_plane<24, plane_ib<float>(24), float>, 128 * 1024);
   set((const void*)k_fft_plane<32, plane_ib<float>(32), float>, 128 * 1024);
   set((const void*)k_fft_plane<40, plane_ib<float>(40), float>, 128 * 1024);
-  if (prec == 0)
+  if (engine == 1) {
+    if (prec == 0)
+      set(waves == 16 ? (const void*)k_contract_seg<double, 1024> : (const void*)k_contract_seg<double, 512>,
+          (int)contract_lds);
+    else
+      set(waves == 16 ? (const void*)k_contract_seg<float, 1024> : (const void*)k_contract_seg<float, 512>,
+          (int)contract_lds);
+  } else if (prec == 0) {
     set((const void*)k_contract<double, 512>, (int)contract_lds);
-  else if (waves == 8)
+  } else if (waves == 8) {
     set((const void*)k_contract<float, 512>, (int)contract_lds);
-  else
+  } else {
     set((const void*)k_contract<float, 256>, (int)contract_lds);
+  }
   return e;
 }
 
 namespace {
-template <typename T, int NT> hipError_t launch_contract_t(const ContractArgs& a, size_t lds, hipStream_t st) {
+template <typename T, int NT, bool SEG> hipError_t launch_contract_t(const ContractArgs& a, size_t lds, hipStream_t st) {
   hipError_t e = hipSuccess;
   const long long chunk = kMaxLaunchItems / NT / 8 * 8;
   for (long long b0 = 0; b0 < a.n_blocks; b0 += chunk) {
@@ -1615,7 +2039,10 @@ template <typename T, int NT> hipError_t launch_contract_t(const ContractArgs& a
     c.block0 = b0;
     c.n_chunk = a.n_blocks - b0 < chunk ? a.n_blocks - b0 : chunk;
     const long long nb8 = (c.n_chunk + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_contract<T, NT>), dim3((unsigned)nb8), dim3(NT), lds, st, c);
+    if constexpr (SEG)
+      hipLaunchKernelGGL((k_contract_seg<T, NT>), dim3((unsigned)nb8), dim3(NT), lds, st, c);
+    else
+      hipLaunchKernelGGL((k_contract<T, NT>), dim3((unsigned)nb8), dim3(NT), lds, st, c);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
@@ -1623,10 +2050,19 @@ template <typename T, int NT> hipError_t launch_contract_t(const ContractArgs& a
 }  // namespace
 
 hipError_t launch_contract(int prec, const ContractArgs& a, hipStream_t st) {
+  if (a.engine == 1) {
+    const size_t lds = contract_seg_lds_bytes(prec, a.max_gslots, a.max_gcontrib, a.max_gch);
+    if (a.waves != 8 && a.waves != 16) return hipErrorInvalidValue;
+    if (prec == 0)
+      return a.waves == 16 ? launch_contract_t<double, 1024, true>(a, lds, st)
+                           : launch_contract_t<double, 512, true>(a, lds, st);
+    return a.waves == 16 ? launch_contract_t<float, 1024, true>(a, lds, st)
+                         : launch_contract_t<float, 512, true>(a, lds, st);
+  }
   const size_t lds = contract_lds_bytes(prec, a.max_gprod, a.max_gcontrib, a.max_gch, a.max_gtask);
-  if (prec == 0) return a.waves == 8 ? launch_contract_t<double, 512>(a, lds, st) : hipErrorInvalidValue;
-  if (a.waves == 4) return launch_contract_t<float, 256>(a, lds, st);
-  if (a.waves == 8) return launch_contract_t<float, 512>(a, lds, st);
+  if (prec == 0) return a.waves == 8 ? launch_contract_t<double, 512, false>(a, lds, st) : hipErrorInvalidValue;
+  if (a.waves == 4) return launch_contract_t<float, 256, false>(a, lds, st);
+  if (a.waves == 8) return launch_contract_t<float, 512, false>(a, lds, st);
   return hipErrorInvalidValue;
 }
 

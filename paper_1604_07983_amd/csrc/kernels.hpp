@@ -63,6 +63,10 @@ constexpr long long kMaxLaunchItems = 1LL << 31;
 constexpr int kLdsJ0 = 157, kLdsJ1 = 13, kLdsAl = 1888, kLdsBlock = 2 * kLdsAl;
 // Integers per block-product descriptor (layout documented in compiler.hpp).
 constexpr int kProdInts = 48;
+// Segment descriptors of the matrix-core contraction: integers per
+// descriptor, teams (one descriptor each) per wavefront task.
+constexpr int kSegInts = 16, kSegTeams = 4;
+constexpr int kSegC144 = 0, kSegC9 = 1, kSegC36 = 2, kSegC1 = 3, kSegIdle = 15;
 
 // One geometry of a contraction launch: its blocks, its F~ output and its
 // first (slice, momentum) pair: geometry i owns the pairs [block0, block0 +
@@ -90,6 +94,11 @@ struct ContractArgs {
   const double* contrib_coef;
   int max_gprod, max_gcontrib, max_gch, max_gtask;
   int waves;  // wavefronts the compiled tasks are balanced over
+  // matrix-core contraction (engine 1): segment tasks per group, extra
+  // result slots per product, result slots per group
+  int engine;
+  const int *seg_task, *group_stask, *prod_ext;
+  int max_gslots;
   long long block0, n_chunk;  // logical workgroups [block0, block0 + n_chunk) in this launch
 };
 
@@ -133,6 +142,7 @@ int fft_plane_fields(int n, long long inner, int kind);
 hipError_t launch_fft_plane(int kind, int n, const FftPlaneArgs& a, hipStream_t st);
 hipError_t launch_fft_line(int kind, const FftArgs& a, hipStream_t st);
 size_t contract_lds_bytes(int prec, int max_gprod, int max_gcontrib, int max_gch, int max_gtask);
+size_t contract_seg_lds_bytes(int prec, int max_gslots, int max_gcontrib, int max_gch);
 // Wavefronts per contraction workgroup for a precision (the channel compiler
 // balances each group's tasks over this many).
 int contract_waves(int prec);
@@ -140,6 +150,6 @@ hipError_t launch_contract(int prec, const ContractArgs& a, hipStream_t st);
 // Sets the dynamic-LDS limits of the kernels that need more than the
 // default; called once per plan before any launch (and so outside any
 // stream capture).
-hipError_t prepare_kernels(int prec, int waves, size_t contract_lds);
+hipError_t prepare_kernels(int prec, int waves, size_t contract_lds, int engine);
 
 }  // namespace nbs

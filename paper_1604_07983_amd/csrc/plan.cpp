@@ -49,6 +49,10 @@ struct Tuning {
   // sink-operator group, 1 one per run of groups in which one operator
   // block stays, 2 one per group
   int gchunk = 0;
+  // contraction engine: 0 lane teams on the vector units, 1 segments on the
+  // matrix cores; wavefronts per workgroup of the matrix-core engine
+  int engine = 1;
+  int seg_waves = 16;
 };
 
 }  // namespace
@@ -82,6 +86,11 @@ struct nbs_plan_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<const void*> graph_key;
+  // plans without device allocation: every buffer is carved from a caller
+  // workspace (arena), tables are uploaded on `upload` and waited for
+  char* arena = nullptr;
+  size_t arena_size = 0, arena_used = 0;
+  hipStream_t upload = nullptr;
 };
 
 namespace {
@@ -106,6 +115,17 @@ int alloc_fail_countdown() {
 nbs_status dev_alloc(nbs_plan p, size_t bytes, void** out, int* countdown) {
   *out = nullptr;
   if (bytes == 0) bytes = 256;
+  if (p->arena) {
+    const size_t at = (p->arena_used + 255) & ~(size_t)255;
+    if (at + bytes > p->arena_size)
+      return fail(p, NBS_ERR_UNSUPPORTED,
+                  "the problem needs more device memory than the " + std::to_string(p->arena_size >> 20) +
+                      " MiB static workspace holds");
+    *out = p->arena + at;
+    p->arena_used = at + bytes;
+    p->dev_bytes = p->arena_used;
+    return NBS_OK;
+  }
   if (*countdown > 0 && --*countdown == 0)
     return fail(p, NBS_ERR_NOMEM, "injected allocation failure (NBS_TEST_FAIL_ALLOC)");
   hipError_t e = hipMalloc(out, bytes);
@@ -120,6 +140,7 @@ nbs_status dev_alloc(nbs_plan p, size_t bytes, void** out, int* countdown) {
 }
 
 void dev_free(nbs_plan p, void* ptr) {
+  if (p->arena) return;  // the caller's workspace is not freed piecewise
   for (size_t i = 0; i < p->bufs.size(); ++i)
     if (p->bufs[i].p == ptr) {
       (void)hipFree(ptr);
@@ -138,6 +159,10 @@ void drop_graph(nbs_plan p) {
 }
 
 void free_all(nbs_plan p) {
+  if (p->arena) {
+    p->bufs.clear();
+    return;
+  }
   if (p->device >= 0) {
     (void)hipSetDevice(p->device);
     drop_graph(p);
@@ -146,6 +171,16 @@ void free_all(nbs_plan p) {
     for (auto& b : p->bufs) (void)hipFree(b.p);
   }
   p->bufs.clear();
+}
+
+// Host-to-device copy of a table: synchronous for allocating plans; for
+// workspace plans ordered on their stream and waited for (the host buffer
+// is freed after the call).
+hipError_t upload(nbs_plan p, void* dst, const void* src, size_t bytes) {
+  if (!p->arena) return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, p->upload);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->upload);
+  return e;
 }
 
 nbs_status hip_check(nbs_plan p, hipError_t e, const char* what) {
@@ -231,6 +266,8 @@ nbs_status compile_and_upload(nbs_plan p) {
   p->opt.waves = p->tune.waves;
   p->opt.split = p->tune.split != 0;
   p->opt.mfma = p->prec == NBS_FP32_MFMA && p->tune.mfma != 0;
+  p->opt.seg_waves = p->tune.seg_waves;
+  p->opt.max_group_slots = 128;
   Compiled comp;
   std::string msg = nbs::compile_channels(p->specs, p->opt, &comp);
   if (!msg.empty()) return fail(p, NBS_ERR_INVALID, msg);
@@ -249,6 +286,7 @@ nbs_status compile_and_upload(nbs_plan p) {
   put("ch_contrib", P.ch_contrib); put("contrib_prod", P.contrib_prod); put("prod_desc", P.prod_desc);
   put("task_lanes", P.task_lanes);
   put("group_op1_iso", P.group_op1_iso); put("group_op2_iso", P.group_op2_iso);
+  put("seg_task", P.seg_task); put("group_stask", P.group_stask); put("prod_ext", P.prod_ext);
   const std::vector<int> gchunk = group_chunks(P.group_op1, P.group_op2, p->tune.gchunk);
   put("gchunk", gchunk);
   int countdown = 0;
@@ -266,11 +304,10 @@ nbs_status compile_and_upload(nbs_plan p) {
     dev_free(p, coef);
     return s;
   }
-  hipError_t e = hipMemcpy(prog, flat.data(), flat.size() * 4, hipMemcpyHostToDevice);
-  if (e == hipSuccess && !P.contrib_coef.empty())
-    e = hipMemcpy(coef, P.contrib_coef.data(), P.contrib_coef.size() * 8, hipMemcpyHostToDevice);
+  hipError_t e = upload(p, prog, flat.data(), flat.size() * 4);
+  if (e == hipSuccess && !P.contrib_coef.empty()) e = upload(p, coef, P.contrib_coef.data(), P.contrib_coef.size() * 8);
   if (e == hipSuccess && !P.contrib_coef_iso.empty())
-    e = hipMemcpy(coef_iso, P.contrib_coef_iso.data(), P.contrib_coef_iso.size() * 8, hipMemcpyHostToDevice);
+    e = upload(p, coef_iso, P.contrib_coef_iso.data(), P.contrib_coef_iso.size() * 8);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     dev_free(p, prog);
@@ -301,10 +338,17 @@ nbs_status compile_and_upload(nbs_plan p) {
   c.max_gcontrib = std::max(1, P.max_group_contrib);
   c.max_gch = std::max(1, P.max_group_channels);
   c.max_gtask = std::max(1, P.max_group_tasks);
-  c.waves = p->tune.waves;
-  const size_t lds = nbs::contract_lds_bytes(p->prec, c.max_gprod, c.max_gcontrib, c.max_gch, c.max_gtask);
+  c.engine = p->tune.engine;
+  c.seg_task = T("seg_task");
+  c.group_stask = T("group_stask");
+  c.prod_ext = T("prod_ext");
+  c.max_gslots = std::max(1, P.max_group_slots);
+  c.waves = c.engine == 1 ? p->tune.seg_waves : p->tune.waves;
+  const size_t lds = c.engine == 1
+                         ? nbs::contract_seg_lds_bytes(p->prec, c.max_gslots, c.max_gcontrib, c.max_gch)
+                         : nbs::contract_lds_bytes(p->prec, c.max_gprod, c.max_gcontrib, c.max_gch, c.max_gtask);
   if (lds > 160 * 1024) return fail(p, NBS_ERR_UNSUPPORTED, "a channel group needs more LDS than a CU has");
-  return hip_check(p, nbs::prepare_kernels(p->prec, c.waves, lds), "kernel attributes");
+  return hip_check(p, nbs::prepare_kernels(p->prec, c.waves, lds, c.engine), "kernel attributes");
 }
 
 // ---- the three stages, enqueued on a stream --------------------------------
@@ -412,8 +456,19 @@ const char* nbs_status_string(nbs_status s) {
 
 const char* nbs_last_error(const nbs_plan plan) { return plan ? plan->err.c_str() : "null plan"; }
 
-nbs_status nbs_plan_create(nbs_plan* out, const nbs_geometry* g, int32_t n_geom, const nbs_channel* ch,
-                           int32_t n_ch, nbs_precision prec, int32_t device) {
+}  // extern "C"
+
+namespace nbs {
+
+namespace {
+thread_local std::string t_create_err;  // why the last create_plan of this thread failed
+}
+
+const char* create_error() { return t_create_err.c_str(); }
+
+nbs_status create_plan(nbs_plan* out, const nbs_geometry* g, int32_t n_geom, const nbs_channel* ch, int32_t n_ch,
+                       nbs_precision prec, int32_t device, void* arena, size_t arena_size, hipStream_t upload_stream) {
+  t_create_err.clear();
   if (!out) return NBS_ERR_INVALID;
   *out = nullptr;
   if (!g || !ch || n_ch <= 0 || n_geom <= 0) return NBS_ERR_INVALID;
@@ -431,6 +486,15 @@ nbs_status nbs_plan_create(nbs_plan* out, const nbs_geometry* g, int32_t n_geom,
 
   nbs_plan p = new (std::nothrow) nbs_plan_s;
   if (!p) return NBS_ERR_NOMEM;
+  if (arena) {
+    if (device < 0) {
+      delete p;
+      return NBS_ERR_INVALID;
+    }
+    p->arena = (char*)arena;
+    p->arena_size = arena_size;
+    p->upload = upload_stream;
+  }
   p->n_ch = n_ch;
   p->prec = prec;
   p->device = device;
@@ -471,7 +535,11 @@ nbs_status nbs_plan_create(nbs_plan* out, const nbs_geometry* g, int32_t n_geom,
     p->device = -1;
     const nbs_status s = compile_and_upload(p);
     p->device = dev;
-    if (s != NBS_OK) { delete p; return s; }
+    if (s != NBS_OK) {
+      t_create_err = p->err;
+      delete p;
+      return s;
+    }
   }
   if (device < 0) {
     *out = p;
@@ -516,16 +584,19 @@ nbs_status nbs_plan_create(nbs_plan* out, const nbs_geometry* g, int32_t n_geom,
     need += (size_t)w.g.t_count * nt * w.V * nbs::kBlockEntries * el + (size_t)n_ch * w.g.t_count * 16 * w.V * el;
     n_qt += w.V * w.g.t_count;
   }
-  size_t free_b = 0, total_b = 0;
-  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) { (void)hipGetLastError(); free_b = (size_t)-1; }
-  if (need > free_b) {
-    delete p;
-    return NBS_ERR_NOMEM;
+  if (!p->arena) {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) { (void)hipGetLastError(); free_b = (size_t)-1; }
+    if (need > free_b) {
+      delete p;
+      return NBS_ERR_NOMEM;
+    }
   }
-  int countdown = alloc_fail_countdown();
+  int countdown = p->arena ? 0 : alloc_fail_countdown();
   nbs_status s = NBS_OK;
   void* tmp = nullptr;
   auto bail = [&](nbs_status st) {
+    t_create_err = p->err;
     free_all(p);
     delete p;
     return st;
@@ -560,8 +631,8 @@ nbs_status nbs_plan_create(nbs_plan* out, const nbs_geometry* g, int32_t n_geom,
     geo[i].block0 = b0;
     b0 += w.V * w.g.t_count;
   }
-  hipError_t e = hipMemcpy(p->chan_nf, nf.data(), nf.size() * 4, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(p->geo, geo.data(), sizeof(nbs::ContractGeom) * n_geom, hipMemcpyHostToDevice);
+  hipError_t e = upload(p, p->chan_nf, nf.data(), nf.size() * 4);
+  if (e == hipSuccess) e = upload(p, p->geo, geo.data(), sizeof(nbs::ContractGeom) * n_geom);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return bail(NBS_ERR_DEVICE);
@@ -572,6 +643,25 @@ nbs_status nbs_plan_create(nbs_plan* out, const nbs_geometry* g, int32_t n_geom,
   p->con.n_geom = n_geom;
   *out = p;
   return NBS_OK;
+}
+
+nbs_status run_plan(nbs_plan p, const void* const* pu, const void* const* pd, const void* const* ps,
+                    void* const* F_out, hipStream_t st) {
+  nbs_status s = enqueue_build(p, pu, pd, ps, st);
+  if (s == NBS_OK) s = enqueue_contract(p, st);
+  if (s == NBS_OK) s = enqueue_relsum(p, F_out, st);
+  return s;
+}
+
+const char* plan_error(const nbs_plan p) { return p ? p->err.c_str() : ""; }
+
+}  // namespace nbs
+
+extern "C" {
+
+nbs_status nbs_plan_create(nbs_plan* out, const nbs_geometry* g, int32_t n_geom, const nbs_channel* ch,
+                           int32_t n_ch, nbs_precision prec, int32_t device) {
+  return nbs::create_plan(out, g, n_geom, ch, n_ch, prec, device, nullptr, 0, nullptr);
 }
 
 nbs_status nbs_workspace_bytes(const nbs_plan plan, size_t* bytes) {
@@ -766,14 +856,24 @@ nbs_status nbs_plan_autotune(nbs_plan p, const void* const* prop_u, const void* 
   p->tune.fft_tile = best_fft.tile;
   // 2. contraction: workgroup size (precision form) and index splitting
   if ((s = enqueue_build(p, prop_u, prop_d, prop_s, st)) != NBS_OK) return finish(s);
-  struct ConChoice { int waves, split, mfma; };
-  std::vector<ConChoice> con_cands = {{8, 1, 0}, {8, 0, 0}};
+  // engine 1: matrix-core segments with 16 or 8 wavefronts per workgroup;
+  // engine 0: lane teams with their own shapes
+  struct ConChoice { int engine, waves, split, mfma; };
+  std::vector<ConChoice> con_cands = {{1, 16, 1, 0}, {1, 8, 1, 0}, {0, 8, 1, 0}, {0, 8, 0, 0}};
   if (p->prec == NBS_FP32_MFMA)
-    con_cands = {{4, 1, 1}, {4, 0, 1}, {8, 1, 1}, {4, 1, 0}, {4, 0, 0}, {8, 1, 0}, {8, 0, 0}};
+    con_cands = {{1, 16, 1, 0}, {1, 8, 1, 0}, {0, 4, 1, 1}, {0, 4, 0, 1}, {0, 8, 1, 1},
+                 {0, 4, 1, 0}, {0, 4, 0, 0}, {0, 8, 1, 0}, {0, 8, 0, 0}};
   ConChoice best_con = con_cands[0];
   first = true;
+  const Tuning before = p->tune;
   for (const auto& c : con_cands) {
-    p->tune.waves = c.waves;
+    p->tune.engine = c.engine;
+    if (c.engine == 1) {
+      p->tune.seg_waves = c.waves;
+      p->tune.waves = before.waves;
+    } else {
+      p->tune.waves = c.waves;
+    }
     p->tune.split = c.split;
     p->tune.mfma = c.mfma;
     if ((s = compile_and_upload(p)) != NBS_OK) return finish(s);
@@ -781,7 +881,13 @@ nbs_status nbs_plan_autotune(nbs_plan p, const void* const* prop_u, const void* 
     if ((s = timed([&]() { return enqueue_contract(p, st); }, &ms)) != NBS_OK) return finish(s);
     if (first || ms < best_ms) { best_ms = ms; best_con = c; first = false; }
   }
-  p->tune.waves = best_con.waves;
+  p->tune.engine = best_con.engine;
+  if (best_con.engine == 1) {
+    p->tune.seg_waves = best_con.waves;
+    p->tune.waves = before.waves;
+  } else {
+    p->tune.waves = best_con.waves;
+  }
   p->tune.split = best_con.split;
   p->tune.mfma = best_con.mfma;
   // 3. with those: the ranges of groups a workgroup walks
@@ -808,8 +914,8 @@ nbs_status nbs_plan_tuning(const nbs_plan p, int32_t out[4]) {
   if (!p || !out) return NBS_ERR_INVALID;
   out[0] = p->tune.fft_line | (p->tune.fft_plane << 1);
   out[1] = p->tune.fft_tile;
-  out[2] = p->tune.waves;
-  out[3] = p->tune.split | (p->tune.mfma << 1) | (p->tune.gchunk << 2);
+  out[2] = p->tune.engine == 1 ? p->tune.seg_waves : p->tune.waves;
+  out[3] = p->tune.split | (p->tune.mfma << 1) | (p->tune.gchunk << 2) | (p->tune.engine << 4);
   return NBS_OK;
 }
 
@@ -818,19 +924,25 @@ nbs_status nbs_plan_set_tuning(nbs_plan p, const int32_t in[4]) {
   const int tile = in[1];
   if (tile != 512 && tile != 1024 && tile != 2048 && tile != 4096) return fail(p, NBS_ERR_INVALID, "fft tile");
   const int waves = in[2];
-  if (p->prec == NBS_FP64 ? waves != 8 : (waves != 4 && waves != 8)) return fail(p, NBS_ERR_INVALID, "waves");
+  const int engine = (in[3] >> 4) & 1;
+  if (in[3] < 0 || (in[3] >> 5) != 0) return fail(p, NBS_ERR_INVALID, "unknown tuning bits");
+  if (engine == 1 ? (waves != 8 && waves != 16)
+                  : (p->prec == NBS_FP64 ? waves != 8 : (waves != 4 && waves != 8)))
+    return fail(p, NBS_ERR_INVALID, "waves");
   if ((in[3] >> 1) & 1 && p->prec != NBS_FP32_MFMA) return fail(p, NBS_ERR_INVALID, "matrix cores need the precision form");
-  if (in[3] < 0 || (in[3] >> 2) > 2) return fail(p, NBS_ERR_INVALID, "group ranges");
+  if (((in[3] >> 2) & 3) > 2) return fail(p, NBS_ERR_INVALID, "group ranges");
   if (p->device >= 0 && hipSetDevice(p->device) != hipSuccess) return fail(p, NBS_ERR_DEVICE, "hipSetDevice");
   if (p->device >= 0 && hipDeviceSynchronize() != hipSuccess) return fail(p, NBS_ERR_DEVICE, "synchronize");
   const Tuning old = p->tune;
   p->tune.fft_line = in[0] & 1;
   p->tune.fft_plane = (in[0] >> 1) & 1;
   p->tune.fft_tile = tile;
-  p->tune.waves = waves;
+  p->tune.engine = engine;
+  if (engine == 1) p->tune.seg_waves = waves;
+  else p->tune.waves = waves;
   p->tune.split = in[3] & 1;
   p->tune.mfma = (in[3] >> 1) & 1;
-  p->tune.gchunk = in[3] >> 2;
+  p->tune.gchunk = (in[3] >> 2) & 3;
   drop_graph(p);
   const nbs_status s = compile_and_upload(p);
   if (s != NBS_OK) {
@@ -843,7 +955,7 @@ nbs_status nbs_plan_set_tuning(nbs_plan p, const int32_t in[4]) {
 
 nbs_status nbs_plan_destroy(nbs_plan p) {
   if (!p) return NBS_OK;
-  if (p->device >= 0) {
+  if (p->device >= 0 && !p->arena) {
     (void)hipSetDevice(p->device);
     (void)hipDeviceSynchronize();
   }
@@ -908,7 +1020,8 @@ nbs_status nbs_plan_table(const nbs_plan p, const char* name, void* buf, int64_t
       {"group_prod", &P.group_prod}, {"group_task", &P.group_task}, {"group_ch", &P.group_ch},
       {"group_channels", &P.group_channels}, {"ch_contrib", &P.ch_contrib}, {"contrib_prod", &P.contrib_prod},
       {"prod_desc", &P.prod_desc}, {"task_lanes", &P.task_lanes}, {"op_alias", &P.op_alias},
-      {"group_op1_iso", &P.group_op1_iso}, {"group_op2_iso", &P.group_op2_iso}, {"op_pair", &P.op_pair}};
+      {"group_op1_iso", &P.group_op1_iso}, {"group_op2_iso", &P.group_op2_iso}, {"op_pair", &P.op_pair},
+      {"seg_task", &P.seg_task}, {"group_stask", &P.group_stask}, {"prod_ext", &P.prod_ext}};
   auto it = tabs.find(nm);
   if (it == tabs.end()) return NBS_ERR_INVALID;
   *n = (int64_t)it->second->size();

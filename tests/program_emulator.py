@@ -318,3 +318,160 @@ def quad_team_reduce(vals, lg):
             for i in range(4):
                 out[(l, i * 4 + (l & 3))] = cur[l][i]
     return out
+
+
+# ---- the matrix-core contraction's segment program ---------------------------
+SEG_NAMES = ("seg_task", "group_stask", "prod_ext")
+SEG_INTS, SEG_TEAMS = 16, 4
+SEG_C144, SEG_C9, SEG_C36, SEG_C1, SEG_IDLE = 0, 1, 2, 3, 15
+LDS_AL, LDS_BLOCK = 1888, 2 * 1888
+
+
+def lds_image(block):
+    """A staged operator block in the kernel's LDS layout; padding is NaN so
+    that a read outside the block's entries shows in the result."""
+    out = np.full(LDS_BLOCK, np.nan + 0j, dtype=np.complex128)
+    i = np.arange(3456)
+    al, j0, j1, j2 = i // 1728, (i // 144) % 12, (i // 12) % 12, i % 12
+    out[al * LDS_AL + j0 * LDS_J0 + j1 * LDS_J1 + j2] = block
+    return out
+
+
+def _seg_row(r, w):
+    return (r & 1) * w[0] + ((r >> 1) & 1) * w[1] + ((r >> 2) & 1) * w[2]
+
+
+def _pair2(v, up, uq):
+    sp, c = divmod(v, 3)
+    c1, c2 = (c + 1) % 3, (c + 2) % 3
+    jp = 3 * (sp ^ 1)
+    return (jp + c1) * up + c2 * uq, (jp + c2) * up + c1 * uq, (-1 if sp & 1 else 1)
+
+
+def _entry2(S, base, o0, o1, g):
+    return g * (S[base + o0] - S[base + o1])
+
+
+def _entry8(S, base, up, uq, c):
+    c1, c2 = (c + 1) % 3, (c + 2) % 3
+    o0, o1 = c1 * up + c2 * uq, c2 * up + c1 * uq
+    e = 0j
+    for sp in range(4):
+        so = 3 * sp * up + 3 * (sp ^ 1) * uq
+        e += (-1 if sp & 1 else 1) * (S[base + so + o0] - S[base + so + o1])
+    return e
+
+
+def seg_run(d, S1, S2, shape, nsteps):
+    """The 4 x 4 result D[i][j] of one team's segment (None for an idle team),
+    computed lane by lane as the kernel does: lane (h, x) supplies row x of
+    both sides at slot k' = 4 s + h, D = sum over steps and h of A B^T."""
+    if d[0] == SEG_IDLE:
+        return None
+    s0, hdr = int(d[1]), int(d[3])
+    transposed = (hdr >> 17) & 1
+    SA, SB = (S2, S1) if transposed else (S1, S2)
+    uAs, uAp, uAq, wa = int(d[4]), int(d[5]), int(d[6]), [int(v) for v in d[7:10]]
+    uBs, uBp, uBq, wb = int(d[10]), int(d[11]), int(d[12]), [int(v) for v in d[13:16]]
+    D = np.zeros((4, 4), dtype=np.complex128)
+    for s in range(s0, s0 + nsteps):
+        A = np.zeros((4, 4), dtype=np.complex128)  # [row x][slot h]
+        B = np.zeros((4, 4), dtype=np.complex128)
+        for h in range(4):
+            for x in range(4):
+                if shape == SEG_C144:
+                    v1, v2 = s // 3, 4 * (s % 3) + h
+                    o0, o1, g = _pair2(v1, uAp, uAq)
+                    A[x, h] = _entry2(SA, _seg_row(x, wa) + v2 * uAs, o0, o1, g)
+                    o0, o1, g = _pair2(v2, uBp, uBq)
+                    B[x, h] = _entry2(SB, _seg_row(x, wb) + v1 * uBs, o0, o1, g)
+                elif shape == SEG_C36:
+                    bp = h & 1
+                    k = 2 * s + (h >> 1)
+                    v2, v1 = divmod(k, 12)
+                    o0, o1, g = _pair2(v1, uAp, uAq)
+                    A[x, h] = _entry2(SA, _seg_row(x + 4 * bp, wa) + v2 * uAs, o0, o1, g)
+                    if (x >> 1) == bp:
+                        B[x, h] = _entry8(SB, _seg_row(x & 1, wb) + v1 * uBs, uBp, uBq, v2)
+                elif shape == SEG_C9:
+                    kk = 4 * s + h
+                    if kk < 9:
+                        v1, v2 = divmod(kk, 3)
+                        A[x, h] = _entry8(SA, _seg_row(x, wa) + v2 * uAs, uAp, uAq, v1)
+                        B[x, h] = _entry8(SB, _seg_row(x, wb) + v1 * uBs, uBp, uBq, v2)
+                else:
+                    for side, (S, ro, u2, u0, u1) in enumerate(((SA, _seg_row(x, wa), uAs, uAp, uAq),
+                                                                (SB, _seg_row(x, wb), uBs, uBp, uBq))):
+                        b = ro + 3 * h * u0 + 3 * (h ^ 1) * u1
+                        e = 0j
+                        for cp in range(6):
+                            c0 = cp if cp < 3 else cp - 3
+                            c1 = (c0 + 1) % 3 if cp < 3 else (c0 + 2) % 3
+                            c2 = (c0 + 2) % 3 if cp < 3 else (c0 + 1) % 3
+                            e += (1 if cp < 3 else -1) * S[b + c0 * u0 + c1 * u1 + c2 * u2]
+                        e *= -1 if h & 1 else 1
+                        (A if side == 0 else B)[x, h] = e
+        if shape == SEG_C1:  # summed over the four h lanes, fed on h = 0
+            A = np.concatenate([A.sum(axis=1, keepdims=True), np.zeros((4, 3))], axis=1)
+            B = np.concatenate([B.sum(axis=1, keepdims=True), np.zeros((4, 3))], axis=1)
+        D += A @ B.T
+    sgn = -1 if (hdr >> 16) & 1 else 1
+    R = np.zeros(16, dtype=np.complex128)
+    for i in range(4):
+        for j in range(4):
+            if shape == SEG_C36:
+                ra, rb = i + 4 * (j >> 1), j & 1
+                idx = rb * 8 + ra if transposed else ra * 2 + rb
+            else:
+                idx = i * 4 + j
+            R[idx] = sgn * D[i, j]
+    return R
+
+
+def emulate_q_seg(T, Nq_plus, Nq_minus, n_ch, check_slots=True):
+    """F~(q) [n_ch, 16] from the segment program of the matrix-core
+    contraction, following its kernel: segments into result slots, extra
+    slots summed into the product's first, channel sums."""
+    out = np.zeros((n_ch, 16), dtype=np.complex128)
+    tasks = T["seg_task"].reshape(-1, SEG_TEAMS, SEG_INTS)
+    n_groups = len(T["group_prod"]) - 1
+    for g in range(n_groups):
+        S1 = lds_image(Nq_plus[T["group_op1"][g]])
+        S2 = lds_image(Nq_minus[T["group_op2"][g]])
+        pb, pe = int(T["group_prod"][g]), int(T["group_prod"][g + 1])
+        R = {}
+        for task in tasks[T["group_stask"][g]:T["group_stask"][g + 1]]:
+            shape, nsteps = int(task[0][0]), int(task[0][2])
+            assert shape != SEG_IDLE, "a task led by an idle team"
+            for d in task:
+                assert d[0] in (shape, SEG_IDLE) and d[2] == nsteps, "a task mixes shapes or step counts"
+                r = seg_run(d, S1, S2, shape, nsteps)
+                if r is None:
+                    continue
+                slot = int(d[3]) & 0xFFFF
+                assert slot not in R, "result slot written twice"
+                R[slot] = r
+        np_ = pe - pb
+        for p in range(np_):
+            ext = int(T["prod_ext"][pb + p])
+            for e in range(ext >> 16):
+                R[p] = R[p] + R.pop((ext & 0xFFFF) + e)
+        if check_slots:
+            assert sorted(R) == list(range(np_)), "result slots do not match the products"
+        c0 = T["group_ch"][g]
+        for cl in range(T["group_ch"][g + 1] - c0):
+            ch = T["group_channels"][c0 + cl]
+            for s in range(16):
+                a1, a2, a3, a4 = (s >> 3) & 1, (s >> 2) & 1, (s >> 1) & 1, s & 1
+                v = 0j
+                for c in range(T["ch_contrib"][c0 + cl], T["ch_contrib"][c0 + cl + 1]):
+                    w = int(T["contrib_prod"][c])
+                    p = w & 0xFFFF
+                    rows1, lbl = (w >> 16) & 15, (w >> 20) & 3
+                    l3, l4 = bool(lbl & 1), bool(lbl & 2)
+                    rows2 = 16 // rows1
+                    r1 = (a1 * (2 if l3 else 1) + (a3 if l3 else 0)) * (2 if l4 else 1) + (a4 if l4 else 0)
+                    r2 = (a2 * (1 if l3 else 2) + (0 if l3 else a3)) * (1 if l4 else 2) + (0 if l4 else a4)
+                    v += T["contrib_coef"][c] * R[p][r1 * rows2 + r2]
+                out[ch, s] = v
+    return out

@@ -126,6 +126,67 @@ def test_compiled_program_reproduces_oracle(chans, L, qs, prec, mfma=False):
         assert err.max() < 1e-12, (q, err.max(), int(err.argmax()))
 
 
+@pytest.mark.parametrize("chans,L,qs", [
+    ([channels.WORKED_EXAMPLE, ("p", "p", "p", "p")], (2, 2, 2), None),
+    ([("Lambda", "Lambda", "Sigma+", "Sigma-"), ("Xi0", "Sigma0", "Xi-", "Sigma+"),
+      ("n", "Xi0", "Lambda", "Lambda")], (2, 2, 2), [0, 3, 5]),
+    (channels.r52(), (2, 3, 2), [0, 7]),
+])
+def test_segment_program_reproduces_oracle(chans, L, qs):
+    """The matrix-core contraction's segment program, run lane by lane by the
+    CPU emulator (block padding read as NaN, every result slot written once),
+    gives the oracle's F~(q)."""
+    rng = np.random.default_rng(103)
+    S = ref.random_props(rng, L)
+    p = host_plan(chans, L=L, T=4)
+    T = emu.tables(p)
+    T.update({n: p.table(n) for n in emu.SEG_NAMES})
+    Nt = _momentum_operator_blocks(L, S, T)
+    V = int(np.prod(L))
+    for q in (qs if qs is not None else range(V)):
+        mq = _neg(L, q)
+        got = emu.emulate_q_seg(T, [n[q] for n in Nt], [n[mq] for n in Nt], len(chans))
+        qv = (q % L[0], (q // L[0]) % L[1], q // (L[0] * L[1]))
+        want = oracle.correlators_at_q(L, S, chans, qv)
+        err = np.linalg.norm(got - want, axis=1) / np.linalg.norm(want, axis=1)
+        assert err.max() < 1e-12, (q, err.max(), int(err.argmax()))
+
+
+def test_segment_program_shapes_and_balance():
+    """Every R52 product has a matrix-core shape; tasks hold four segments of
+    one shape and step count; segments of a product cover its steps once."""
+    p = host_plan(channels.r52())
+    tasks = p.table("seg_task").reshape(-1, emu.SEG_TEAMS, emu.SEG_INTS)
+    gs, gp, ext = p.table("group_stask"), p.table("group_prod"), p.table("prod_ext")
+    full = {emu.SEG_C144: 36, emu.SEG_C9: 3, emu.SEG_C36: 18, emu.SEG_C1: 1}
+    for g in range(len(gp) - 1):
+        np_ = gp[g + 1] - gp[g]
+        steps = {}
+        for t in tasks[gs[g]:gs[g + 1]]:
+            for d in t:
+                if d[0] == emu.SEG_IDLE:
+                    continue
+                slot = int(d[3]) & 0xFFFF
+                steps.setdefault(int(d[0]), []).append((slot, int(d[1]), int(d[2])))
+        # map extra slots back to their products and check coverage
+        owner = {p_: p_ for p_ in range(np_)}
+        for p_ in range(np_):
+            e = int(ext[gp[g] + p_])
+            for k in range(e >> 16):
+                owner[(e & 0xFFFF) + k] = p_
+        cover = {}
+        for shape, segs in steps.items():
+            for slot, s0, n in segs:
+                cover.setdefault(owner[slot], []).append((s0, n, shape))
+        assert sorted(cover) == list(range(np_))
+        for p_, segs in cover.items():
+            shapes = {sh for _, _, sh in segs}
+            assert len(shapes) == 1
+            sh = shapes.pop()
+            got = sorted(s for s0, n, _ in segs for s in range(s0, s0 + n))
+            assert got == list(range(full[sh])), (g, p_)
+
+
 # ---- ABI argument checking (host only) -------------------------------------
 
 def _create(L=(4, 4, 4), T=8, chans=(("p", "p", "p", "p"),), prec=0, device=-1, n_geom=1, **kw):
@@ -269,10 +330,13 @@ def test_matrix_core_program_reproduces_oracle():
 
 def test_set_tuning_rejects_bad_shapes():
     p = host_plan([("p", "p", "p", "p")])
-    for kw in (dict(fft_tile=300), dict(waves=4), dict(mfma=1), dict(gchunk=3)):
+    for kw in (dict(fft_tile=300), dict(waves=4), dict(mfma=1), dict(gchunk=3), dict(engine=0, waves=16)):
         with pytest.raises(binding.NbsError):
             p.set_tuning(**kw)
-    assert p.tuning()["waves"] == 8
+    # the matrix-core engine with 16-wavefront workgroups by default
+    assert p.tuning()["waves"] == 16 and p.tuning()["engine"] == 1
+    p.set_tuning(engine=0, waves=8)
+    assert p.tuning()["waves"] == 8 and p.tuning()["engine"] == 0
 
 
 def test_group_range_modes():

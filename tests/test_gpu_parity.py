@@ -138,12 +138,15 @@ def test_square_plane_lattice(prec):
     assert err.max() <= TOL[prec], (err.max(), int(err.argmax()))
 
 
-@pytest.mark.parametrize("tuning", [dict(mfma=1), dict(mfma=1, waves=8), dict(split=0, fft_line=0, fft_tile=2048),
-                                    dict(fft_plane=1), dict(gchunk=1), dict(gchunk=2, waves=8)])
+@pytest.mark.parametrize("tuning", [dict(engine=0, waves=4), dict(engine=0, mfma=1, waves=4),
+                                    dict(engine=0, mfma=1, waves=8),
+                                    dict(engine=0, waves=4, split=0, fft_line=0, fft_tile=2048), dict(fft_plane=1),
+                                    dict(gchunk=1), dict(gchunk=2, waves=8), dict(waves=8)])
 def test_precision_form_launch_shapes(tuning):
-    """The precision form under other launch shapes (matrix-core products,
-    512-thread workgroups, no index splitting, LDS-tile transforms, the
-    fused x-y pass) on every R52 channel."""
+    """The precision form under other launch shapes (the lane-team engine
+    with and without its matrix-core quads, 256- and 512-thread workgroups,
+    no index splitting, LDS-tile transforms, the fused x-y pass, group
+    ranges, 512-thread matrix-core workgroups) on every R52 channel."""
     announce("precision form shapes %s" % tuning)
     L, T = (8, 8, 3), 2
     props = runner.host_props(L, T, range(T), dtype=np.complex64)
@@ -168,16 +171,18 @@ def test_precision_form_long_register_lines(L):
     assert err.max() <= 1e-5, (err.max(), int(err.argmax()))
 
 
-@pytest.mark.parametrize("gchunk", [1, 2])
-def test_fp64_group_ranges(gchunk):
+@pytest.mark.parametrize("tuning", [dict(gchunk=1), dict(gchunk=2), dict(engine=0, waves=8),
+                                    dict(engine=0, waves=8, gchunk=2), dict(waves=8)])
+def test_fp64_launch_shapes(tuning):
     """Double precision with workgroups that walk one run of sink-operator
-    groups in which one operator block stays, or a single group, on every
+    groups in which one operator block stays, or a single group, with the
+    lane-team engine, and with 512-thread matrix-core workgroups, on every
     R52 channel."""
-    announce("fp64 group ranges %d" % gchunk)
+    announce("fp64 launch shapes %s" % tuning)
     L, T = (6, 4, 5), 2
     props = runner.host_props(L, T, range(T), dtype=np.complex128)
     chans = channels.r52()
-    Fg = run_gpu(L, T, chans, props, binding.NBS_FP64, tuning=dict(gchunk=gchunk))
+    Fg = run_gpu(L, T, chans, props, binding.NBS_FP64, tuning=tuning)
     Fo = oracle_F(L, props, chans)
     err = rel_err_per_channel(Fg, Fo)
     assert err.max() <= 1e-12, (err.max(), int(err.argmax()))
@@ -185,9 +190,9 @@ def test_fp64_group_ranges(gchunk):
 
 @pytest.mark.parametrize("prec", [binding.NBS_FP64, binding.NBS_FP32_MFMA])
 def test_isospin_limit_builds_canonical_blocks_only(prec):
-    """u and d given as the same memory: only p, Lambda, Sigma+, Sigma0, Xi0
-    blocks are built (Sec. 3(i)); every R52 channel against the oracle with
-    S_d = S_u, and against the same propagators passed as two copies."""
+    """u and d given as the same memory: only p, n, Lambda, Sigma+, Sigma0,
+    Xi0 blocks are built (Sec. 4(i)); every R52 channel against the oracle
+    with S_d = S_u, and against the same propagators passed as two copies."""
     announce("isospin limit prec=%d" % prec)
     L, T = (4, 3, 2), 2
     dt = np.complex128 if prec == binding.NBS_FP64 else np.complex64
