@@ -243,6 +243,38 @@ nbs_status nbs_plan_table(const nbs_plan plan, const char* name, void* buf, int6
  * out[3] = most channels in one group. */
 nbs_status nbs_plan_params(const nbs_plan plan, int32_t out[4]);
 
+/* ---- without device allocation --------------------------------------- */
+
+/* Device workspace (MiB) of nbs_four_point_static on each device. */
+#define NBS_STATIC_WORKSPACE_MIB 64
+
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the whole
+ * path of nbs_plan_create + nbs_build_blocks + nbs_contract_channels +
+ * nbs_relative_sum for ONE geometry on the current device, with every
+ * device buffer the path needs (operator blocks, F~, the compiled channel
+ * program, the precision form's scales) carved from a workspace of
+ * NBS_STATIC_WORKSPACE_MIB MiB that the library holds on each device it
+ * runs on until the process ends; no hipMalloc or hipFree is called.
+ * Arguments as for those calls: g one geometry, ch/n_ch the channels,
+ * prop_u/d/s device pointers [t_count][Lz][Ly][Lx][12][12] (d may alias u:
+ * the isospin limit), F_out device complex128 [n_ch][t_count][16][Lz][Ly][Lx].
+ * The channel program is compiled on the host and uploaded on `stream`
+ * (this call waits for the upload), the kernels are enqueued on `stream`.
+ * Errors: NBS_ERR_UNSUPPORTED when the problem needs more device memory than
+ * the workspace (nbs_static_last_error gives the size), otherwise as
+ * nbs_plan_create and the stage calls.  Every call on a device shares that
+ * device's workspace and overwrites what the previous call left there:
+ * calls that overlap on one device (different streams or host threads)
+ * race; calls on one stream are ordered.  Results equal those of the plan
+ * path with default launch shapes. */
+nbs_status nbs_four_point_static(const nbs_geometry* g, const nbs_channel* ch, int32_t n_ch,
+                                 nbs_precision precision, const void* prop_u, const void* prop_d,
+                                 const void* prop_s, void* F_out, void* stream);
+
+/* Message of the last failed nbs_four_point_static call ("" if none). */
+const char* nbs_static_last_error(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -21,7 +21,8 @@ STATUS = {0: "NBS_OK", 1: "NBS_ERR_INVALID", 2: "NBS_ERR_UNSUPPORTED", 3: "NBS_E
 SYMBOLS = ("nbs_plan_create", "nbs_workspace_bytes", "nbs_build_blocks", "nbs_contract_channels",
            "nbs_relative_sum", "nbs_plan_destroy", "nbs_status_string", "nbs_last_error",
            "nbs_plan_info", "nbs_plan_diagrams", "nbs_plan_table", "nbs_plan_params", "nbs_run_graph",
-           "nbs_plan_autotune", "nbs_plan_tuning", "nbs_plan_set_tuning", "nbs_two_point")
+           "nbs_plan_autotune", "nbs_plan_tuning", "nbs_plan_set_tuning", "nbs_two_point",
+           "nbs_four_point_static", "nbs_static_last_error")
 
 
 class NbsError(RuntimeError):
@@ -102,6 +103,11 @@ def lib():
         L.nbs_plan_tuning.restype = I32
         L.nbs_plan_set_tuning.argtypes = [P, ctypes.POINTER(I32)]
         L.nbs_plan_set_tuning.restype = I32
+        L.nbs_four_point_static.argtypes = [ctypes.POINTER(Geometry), ctypes.POINTER(Channel), I32, I32, P, P, P,
+                                            P, P]
+        L.nbs_four_point_static.restype = I32
+        L.nbs_static_last_error.argtypes = []
+        L.nbs_static_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
 
@@ -127,6 +133,20 @@ def make_channels(chans):
         arr[i].sink[0], arr[i].sink[1] = _op(b1), _op(b2)
         arr[i].src[0], arr[i].src[1] = _op(b3), _op(b4)
     return arr
+
+
+def four_point_static(L, T, chans, prop_u, prop_d, prop_s, F_out, prec=NBS_FP64, t0=0, t_begin=0, t_count=None,
+                      stream=0):
+    """nbs_four_point_static: the whole path for one geometry with the
+    library's static device workspace (no device allocation); arguments are
+    device pointers."""
+    g = make_geometry(L, T, t0, t_begin, t_count)
+    ch = make_channels(chans)
+    st = lib().nbs_four_point_static(ctypes.byref(g), ch, len(chans), int(prec), ctypes.c_void_p(prop_u),
+                                     ctypes.c_void_p(prop_d), ctypes.c_void_p(prop_s), ctypes.c_void_p(F_out),
+                                     ctypes.c_void_p(stream))
+    if st != 0:
+        raise NbsError(st, "nbs_four_point_static: %s" % lib().nbs_static_last_error().decode())
 
 
 def _ptrs(x, n):

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "libnbs.so")
-SOURCES = ["kernels.hip", "plan.cpp", "compiler.cpp"]
+SOURCES = ["kernels.hip", "plan.cpp", "compiler.cpp", "static_path.hip"]
 ARCH = os.environ.get("NBS_OFFLOAD_ARCH", "gfx950")
 
 
