@@ -330,8 +330,8 @@ struct SegPlan {
   double makespan = 0.0;
 };
 
-// Cut the products into segments (lengths l144 and l36 steps, aligned so a
-// segment starts where its lanes' pair indices start a new value), put
+// Cut the products into segments (lengths l144 and l36 steps; a multiple
+// of three steps, where the 4 x 4 shape's lanes start a new v1), put
 // segments of one shape and one step count four to a task, and balance the
 // tasks over `waves` wavefronts longest first.
 SegPlan plan_segments(const std::vector<std::vector<int>>& base, const std::vector<int>& steps, int l144, int l36,
@@ -736,7 +736,7 @@ std::string compile_channels(const std::vector<ChannelSpec>& chans, const Compil
         SegPlan best;
         bool have = false;
         for (int l144 : {36, 18, 12, 9, 6, 3})
-          for (int l36 : {18, 12, 6}) {
+          for (int l36 : {18, 12, 9, 6, 3}) {
             SegPlan sp = plan_segments(base, nsteps, l144, l36, opt.seg_waves);
             if (sp.slots > opt.max_group_slots) continue;
             if (!have || sp.makespan < best.makespan - 1e-9 ||

@@ -123,6 +123,7 @@ int product_class(int K, int rows1, int lone1, int lone2, int nm1, int nm2);
 //   kSegC36:  8 x 2 rows (the 2-term side A has 8 rows, the 8-term side B 2):
 //             side A row r = x + 4 b', k' = 2 k + b', k = 12 v2 + v1; side B
 //             feeds E_B[x & 1][k] on lanes with x >> 1 == b', zero elsewhere
+// Segments start and end on multiples of three steps.
 //   kSegC1:   two full projections (K = 1): the 24 source-tensor terms of
 //             each side are spread over the four h lanes and summed first
 // Side A of a product is block 1 (sink operator at +q) except for the

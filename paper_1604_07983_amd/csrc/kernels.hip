@@ -902,6 +902,7 @@ __device__ __forceinline__ ContractGeom find_geometry(const ContractGeom* geo, i
   G.t_count = uni(geo[gi].t_count);
   G.pad = 0;
   G.block0 = uni64(geo[gi].block0);
+  G.qorder = (const int*)uni64((long long)geo[gi].qorder);
   return G;
 }
 
@@ -936,6 +937,7 @@ __device__ __forceinline__ void rs_step(const cx<T>* in, cx<T>* out, bool upper)
 }
 
 constexpr int kDppRowMirror = 0x140, kDppRowHalfMirror = 0x141, kDppQuadMirror = 0x1B, kDppQuadSwap = 0xB1;
+constexpr int kDppQuadSwap2 = 0x4E;  // quad_perm [2, 3, 0, 1]: partner lane ^ 2
 
 template <typename T>
 __device__ __forceinline__ void team_reduce_store(const cx<T> acc[16], int lg, int lane, int p, cx<T>* R) {
@@ -1418,15 +1420,15 @@ __device__ __forceinline__ int seg_row(int r, const int* w) {
 // Pair of a source baryon whose lone quark (quark 0 or 1, shared index
 // v = 3 s + c) sits in the other block: two terms, the pair's quark p at
 // 3 (s ^ 1) + (c + 1 + t) % 3 and its third quark q (spin: a label) at colour
-// (c + 2 - t) % 3, coefficient (t ? -1 : 1) (s odd ? -1 : 1).  Returns the
-// two offsets and the sign of term 0.
-__device__ __forceinline__ int seg_pair2(int v, int up, int uq, int& o0, int& o1) {
+// (c + 2 - t) % 3, coefficient (t ? -1 : 1) (s odd ? -1 : 1).  The entry is
+// S[o0] - S[o1]: the offsets come in the order that absorbs the sign.
+__device__ __forceinline__ void seg_pair2(int v, int up, int uq, int& o0, int& o1) {
   const int sp = v / 3, c = v - 3 * sp;
   const int c1 = c == 2 ? 0 : c + 1, c2 = c == 0 ? 2 : c - 1;
   const int jp = 3 * (sp ^ 1);
-  o0 = (jp + c1) * up + c2 * uq;
-  o1 = (jp + c2) * up + c1 * uq;
-  return (sp & 1) ? -1 : 1;
+  const int a = (jp + c1) * up + c2 * uq, b = (jp + c2) * up + c1 * uq;
+  o0 = (sp & 1) ? b : a;
+  o1 = (sp & 1) ? a : b;
 }
 
 // Pair of a source baryon whose lone quark is its third quark (shared index
@@ -1458,11 +1460,7 @@ __device__ __forceinline__ cx<T> seg_entry8(const cx<T>* S, int base, const int 
   return e;
 }
 
-template <typename T>
-__device__ __forceinline__ cx<T> seg_entry2(const cx<T>* S, int base, int o0, int o1, int sg) {
-  const cx<T> u = S[base + o0], w = S[base + o1];
-  return sg > 0 ? cx<T>{u.re - w.re, u.im - w.im} : cx<T>{w.re - u.re, w.im - u.im};
-}
+template <typename T> __device__ __forceinline__ cx<T> cdiff(cx<T> u, cx<T> w) { return cx<T>{u.re - w.re, u.im - w.im}; }
 
 // One segment of a team.  d: the team's descriptor; SA, SB: the staged
 // blocks of sides A and B; R: result slots (16 complex each).
@@ -1484,52 +1482,60 @@ __device__ __forceinline__ void seg_run(const int* d, const cx<T>* S1, const cx<
   seg_zero(acc);
   const cx<T> zero{0, 0};
   if (shape == kSegC144) {
-    // v1 = s / 3 (side A's pair, side B's single quark), v2 = 4 (s % 3) + h
-    const int roA = seg_row(x, wa), roB = seg_row(x, wb);
-    int oB0[3], oB1[3], gB[3];
+    // v1 = s / 3 (side A's pair, side B's single quark), v2 = 4 (s % 3) + h.
+    // Teams without a segment compute from in-range offsets (their
+    // descriptor is zero) and store nothing; the matrix blocks of the
+    // other teams do not see their values.  Per value of v1 all twelve
+    // block reads are issued before any is used.
+    const int roA = seg_row(x, wa) + h * uAs, roB = seg_row(x, wb);
+    const int stepA = 4 * uAs;
+    int oB[3][2];
 #pragma unroll
-    for (int m = 0; m < 3; ++m) gB[m] = seg_pair2(4 * m + h, uBp, uBq, oB0[m], oB1[m]);
-    // nsteps is wavefront-uniform: the loop runs the same count on every lane
+    for (int m = 0; m < 3; ++m) seg_pair2(4 * m + h, uBp, uBq, oB[m][0], oB[m][1]);
     for (int it = 0; it < nsteps / 3; ++it) {
       const int v1 = s0 / 3 + it;
       int oA0, oA1;
-      const int gA = seg_pair2(v1, uAp, uAq, oA0, oA1);
-      const int bB = roB + v1 * uBs;
+      seg_pair2(v1, uAp, uAq, oA0, oA1);
+      const int bA0 = roA + oA0, bA1 = roA + oA1, bB = roB + v1 * uBs;
+      cx<T> ua[3], wa_[3], ub[3], wb_[3];
 #pragma unroll
       for (int m = 0; m < 3; ++m) {
-        cx<T> a = zero, b = zero;
-        if (live) {
-          const int bA = roA + (4 * m + h) * uAs;
-          a = seg_entry2<T>(SA, bA, oA0, oA1, gA);
-          b = seg_entry2<T>(SB, bB, oB0[m], oB1[m], gB[m]);
-        }
-        seg_mma(acc, a, b);
+        ua[m] = SA[bA0 + m * stepA];
+        wa_[m] = SA[bA1 + m * stepA];
+        ub[m] = SB[bB + oB[m][0]];
+        wb_[m] = SB[bB + oB[m][1]];
       }
+#pragma unroll
+      for (int m = 0; m < 3; ++m) seg_mma(acc, cdiff(ua[m], wa_[m]), cdiff(ub[m], wb_[m]));
     }
   } else if (shape == kSegC36) {
     // k = 2 s + (h >> 1), b' = h & 1: side A row x + 4 b' at (v1, v2) =
-    // (k % 12, k / 12); side B row x & 1 on lanes with x >> 1 == b'
-    const int bp = h & 1;
-    const int roA = seg_row(x + 4 * bp, wa), roB = seg_row(x & 1, wb);
-    const bool bl = live && (x >> 1) == bp;
+    // (k % 12, k / 12); side B row x & 1 on lanes with x >> 1 == b'.
+    // Step s has v2 = s / 6 and v1 = 2 j + (h >> 1), j = s % 6.
+    const int bp = h & 1, hh = h >> 1;
+    const int roA = seg_row(x + 4 * bp, wa), roB = seg_row(x & 1, wb) + hh * uBs;
+    const bool bl = (x >> 1) == bp;
     int so[4];
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp) so[sp] = 3 * sp * uBp + 3 * (sp ^ 1) * uBq;
+    int v2 = s0 / 6, j = s0 - 6 * (s0 / 6);
+    int o0, o1;
+    seg_pair8(v2, uBp, uBq, o0, o1);
+    int bA = roA + v2 * uAs;
+#pragma unroll 1
     for (int it = 0; it < nsteps; ++it) {
-      const int k = 2 * (s0 + it) + (h >> 1);
-      const int v2 = k / 12, v1 = k - 12 * v2;
-      cx<T> a = zero, b = zero;
-      if (live) {
-        int oA0, oA1;
-        const int gA = seg_pair2(v1, uAp, uAq, oA0, oA1);
-        a = seg_entry2<T>(SA, roA + v2 * uAs, oA0, oA1, gA);
-      }
-      if (bl) {
-        int o0, o1;
-        seg_pair8(v2, uBp, uBq, o0, o1);
-        b = seg_entry8<T>(SB, roB + v1 * uBs, so, o0, o1);
-      }
+      int a0, a1;
+      seg_pair2(2 * j + hh, uAp, uAq, a0, a1);
+      const cx<T> a = cdiff(SA[bA + a0], SA[bA + a1]);
+      cx<T> b = zero;
+      if (bl) b = seg_entry8<T>(SB, roB + 2 * j * uBs, so, o0, o1);
       seg_mma(acc, a, b);
+      if (++j == 6) {
+        j = 0;
+        ++v2;
+        seg_pair8(v2, uBp, uBq, o0, o1);
+        bA = roA + v2 * uAs;
+      }
     }
   } else if (shape == kSegC9) {
     // k' = 4 s + h = 3 v1 + v2 < 9
@@ -1544,7 +1550,7 @@ __device__ __forceinline__ void seg_run(const int* d, const cx<T>* S1, const cx<
       const int kk = 4 * (s0 + it) + h;
       const int v1 = kk / 3, v2 = kk - 3 * v1;
       cx<T> a = zero, b = zero;
-      if (live && kk < 9) {
+      if (kk < 9) {
         int o0, o1;
         seg_pair8(v1, uAp, uAq, o0, o1);
         a = seg_entry8<T>(SA, roA + v2 * uAs, soA, o0, o1);
@@ -1577,11 +1583,7 @@ __device__ __forceinline__ void seg_run(const int* d, const cx<T>* S1, const cx<
       if (h & 1) e = cx<T>{-e.re, -e.im};
       return e;
     };
-    cx<T> a = zero, b = zero;
-    if (live) {
-      a = whole(SA, roA, uAs, uAp, uAq);
-      b = whole(SB, roB, uBs, uBp, uBq);
-    }
+    cx<T> a = whole(SA, roA, uAs, uAp, uAq), b = whole(SB, roB, uBs, uBp, uBq);
     a.re = seg_hsum(a.re);
     a.im = seg_hsum(a.im);
     b.re = seg_hsum(b.re);
@@ -1620,12 +1622,51 @@ __device__ __forceinline__ void seg_run(const int* d, const cx<T>* S1, const cx<
   }
 }
 
-size_t contract_seg_lds_bytes(int prec, int max_gslots, int max_gcontrib, int max_gch) {
+size_t contract_seg_lds_bytes(int prec, int max_gslots, int max_gcontrib, int max_gch, int max_gstask) {
   const size_t el = prec == 0 ? sizeof(cd) : sizeof(cf);
   const size_t real = prec == 0 ? sizeof(double) : sizeof(float);
   return el * (2 * (size_t)kLdsBlock + (size_t)max_gslots * 16) + real * max_gcontrib +
-         sizeof(int) * (max_gcontrib + max_gch + 1 + 1);
+         sizeof(int) * ((size_t)max_gstask * kSegTeams * kSegInts + max_gcontrib + max_gch + 1 + 1);
 }
+
+// One operator block moved from HBM to LDS in chunks of four consecutive
+// entries (one run of the last slot index), kChunks per thread: the loads
+// can be issued early and the registers written to LDS later.
+constexpr int kBlockChunks = kBlockEntries / 4;
+
+__device__ __forceinline__ int chunk_lds_base(int c) {
+  const int r = c / 3, j2 = 4 * (c - 3 * r);
+  const int al = r / 144, rr = r - 144 * al;
+  const int j0 = rr / 12, j1 = rr - 12 * j0;
+  return al * kLdsAl + j0 * kLdsJ0 + j1 * kLdsJ1 + j2;
+}
+
+template <typename T, int NT> struct BlockRegs {
+  static constexpr int kCh = (kBlockChunks + NT - 1) / NT;
+  cx<T> v[kCh][4];
+  __device__ __forceinline__ void load(const cx<T>* src, int tid) {
+    using gptr = const __attribute__((address_space(1))) cx<T>*;
+    const gptr g = (gptr)src;
+#pragma unroll
+    for (int k = 0; k < kCh; ++k) {
+      const int c = tid + k * NT;
+      const int cc = c < kBlockChunks ? c : kBlockChunks - 1;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[k][e] = cx<T>{g[4 * cc + e].re, g[4 * cc + e].im};
+    }
+  }
+  __device__ __forceinline__ void store(cx<T>* slot, int tid) const {
+#pragma unroll
+    for (int k = 0; k < kCh; ++k) {
+      const int c = tid + k * NT;
+      if (c < kBlockChunks) {
+        const int b = chunk_lds_base(c);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) slot[b + e] = v[k][e];
+      }
+    }
+  }
+};
 
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_contract_seg(ContractArgs a) {
@@ -1639,66 +1680,72 @@ __global__ __launch_bounds__(NT) void k_contract_seg(ContractArgs a) {
   const int chunk = (int)(logical - qtl * a.n_gchunk);
   const ContractGeom G = find_geometry(a.geo, a.n_geom, qtl);
   const long long qt = qtl - G.block0;
-  const int t = (int)(qt / G.V), q = (int)(qt % G.V);
+  const int t = (int)(qt / G.V), q = uni(G.qorder[qt % G.V]);
   const int qx = q % G.Lx, qy = (q / G.Lx) % G.Ly, qz = q / (G.Lx * G.Ly);
   const int mq = (G.Lx - qx) % G.Lx + G.Lx * ((G.Ly - qy) % G.Ly + G.Ly * ((G.Lz - qz) % G.Lz));
   cx<T>* const slotA = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* const slotB = slotA + kLdsBlock;
   cx<T>* const R = slotB + kLdsBlock;
   T* const ccoef = reinterpret_cast<T*>(R + a.max_gslots * 16);
-  int* const cword = reinterpret_cast<int*>(ccoef + a.max_gcontrib);
+  int* const tdesc = reinterpret_cast<int*>(ccoef + a.max_gcontrib);
+  int* const cword = tdesc + a.max_gstask * (kSegTeams * kSegInts);
   int* const coff = cword + a.max_gcontrib;
   int* const counter = coff + a.max_gch + 1;
   const int tid = threadIdx.x, lane = tid & 63;
   const cx<T>* Nq = reinterpret_cast<const cx<T>*>(G.Nq);
   const int gbeg = a.gchunk[chunk], gend = a.gchunk[chunk + 1];
+  auto block_src = [&](int op, int qq) {
+    return Nq + ((long long)(op * G.t_count + t) * G.V + qq) * kBlockEntries;
+  };
+  // the first group's two blocks
+  {
+    BlockRegs<T, NT> ra, rb;
+    ra.load(block_src(a.group_op1[gbeg], q), tid);
+    rb.load(block_src(a.group_op2[gbeg], mq), tid);
+    ra.store(slotA, tid);
+    rb.store(slotB, tid);
+  }
   for (int g = gbeg; g < gend; ++g) {
-    // stage the blocks whose operator changed (every global load before the
-    // first LDS store) and the group's channel contributions
-    const bool newA = g == gbeg || a.group_op1[g] != a.group_op1[g - 1];
-    const bool newB = g == gbeg || a.group_op2[g] != a.group_op2[g - 1];
-    using gptr = const __attribute__((address_space(1))) cx<T>*;
-    const gptr gA = (gptr)(Nq + ((long long)(a.group_op1[g] * G.t_count + t) * G.V + q) * kBlockEntries);
-    const gptr gB = (gptr)(Nq + ((long long)(a.group_op2[g] * G.t_count + t) * G.V + mq) * kBlockEntries);
-    constexpr int kPer = (kBlockEntries + NT - 1) / NT;
-    cx<T> va[kPer], vb[kPer];
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      const int i = tid + k * NT;
-      const int ii = i < kBlockEntries ? i : kBlockEntries - 1;
-      if (newA) va[k] = cx<T>{gA[ii].re, gA[ii].im};
-      if (newB) vb[k] = cx<T>{gB[ii].re, gB[ii].im};
-    }
+    // the group's channel contributions
     const int gc0 = a.group_ch[g], nch = a.group_ch[g + 1] - gc0;
     const int cbase = a.ch_contrib[gc0], ncon = a.ch_contrib[gc0 + nch] - cbase;
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      const int i = tid + k * NT;
-      if (i < kBlockEntries) {
-        if (newA) slotA[lds_index(i)] = va[k];
-        if (newB) slotB[lds_index(i)] = vb[k];
-      }
-    }
     for (int i = tid; i < ncon; i += NT) {
       cword[i] = a.contrib_prod[cbase + i];
       ccoef[i] = (T)a.contrib_coef[cbase + i];
     }
     if (tid <= nch) coff[tid] = a.ch_contrib[gc0 + tid] - cbase;
     if (tid == 0) *counter = 0;
+    // the group's task descriptors: read from LDS during the products, so
+    // that no global load there waits behind the prefetch below
+    const int tb = a.group_stask[g], ntask = a.group_stask[g + 1] - tb;
+    for (int i = tid; i < ntask * (kSegTeams * kSegInts); i += NT)
+      tdesc[i] = a.seg_task[(long long)tb * (kSegTeams * kSegInts) + i];
     __syncthreads();
 
+    // the next group's changed block (the walk changes one operator at a
+    // time where it can) is loaded into registers now and written to LDS
+    // after this group's last LDS read, so its HBM latency overlaps the
+    // products
+    const bool more = g + 1 < gend;
+    const bool nA = more && a.group_op1[g + 1] != a.group_op1[g];
+    const bool nB = more && a.group_op2[g + 1] != a.group_op2[g];
+    BlockRegs<T, NT> pf;
+    if (nA)
+      pf.load(block_src(a.group_op1[g + 1], q), tid);
+    else if (nB)
+      pf.load(block_src(a.group_op2[g + 1], mq), tid);
+
     // products: wavefronts claim tasks (longest first) from the counter
-    const int tb = a.group_stask[g], ntask = a.group_stask[g + 1] - tb;
     for (;;) {
       int claim = 0;
       if (lane == 0) claim = atomicAdd(counter, 1);
-      const int tix = __builtin_amdgcn_readfirstlane(__shfl(claim, 0));
+      const int tix = __builtin_amdgcn_readfirstlane(claim);
       if (tix >= ntask) break;
       int tm, h, x;
       seg_roles<T>(lane, tm, h, x);
       (void)h;
       (void)x;
-      const int* dt = a.seg_task + (long long)(tb + tix) * (kSegTeams * kSegInts);
+      const int* dt = tdesc + tix * (kSegTeams * kSegInts);
       const int shape = __builtin_amdgcn_readfirstlane(dt[0]);
       const int nsteps = __builtin_amdgcn_readfirstlane(dt[2]);
       int d[kSegInts];
@@ -1743,17 +1790,30 @@ __global__ __launch_bounds__(NT) void k_contract_seg(ContractArgs a) {
           v.im = fma(cf, xv.im, v.im);
         }
       }
-#pragma unroll
-      for (int dd = 1; dd < 8; dd <<= 1) {
-        v.re += __shfl_xor(v.re, dd);
-        v.im += __shfl_xor(v.im, dd);
-      }
+      // sum of the 8 lanes of the output: DPP moves within each 8-lane
+      // half row (partners lane ^ 1, lane ^ 2, then the mirrored quad)
+      v.re += dpp_move<kDppQuadSwap>(v.re);
+      v.im += dpp_move<kDppQuadSwap>(v.im);
+      v.re += dpp_move<kDppQuadSwap2>(v.re);
+      v.im += dpp_move<kDppQuadSwap2>(v.im);
+      v.re += dpp_move<kDppRowHalfMirror>(v.re);
+      v.im += dpp_move<kDppRowHalfMirror>(v.im);
       if (cl < nch && sub == 0) {
         const int ch = a.group_channels[gc0 + cl];
         Ft[(((long long)ch * G.t_count + t) * 16 + s) * G.V + q] = v;
       }
     }
-    __syncthreads();  // LDS is restaged for the next group
+    __syncthreads();  // every LDS read of this group is done
+    if (nA) {
+      pf.store(slotA, tid);
+      if (nB) {
+        BlockRegs<T, NT> rb;
+        rb.load(block_src(a.group_op2[g + 1], mq), tid);
+        rb.store(slotB, tid);
+      }
+    } else if (nB) {
+      pf.store(slotB, tid);
+    }
   }
 }
 
@@ -2051,7 +2111,7 @@ template <typename T, int NT, bool SEG> hipError_t launch_contract_t(const Contr
 
 hipError_t launch_contract(int prec, const ContractArgs& a, hipStream_t st) {
   if (a.engine == 1) {
-    const size_t lds = contract_seg_lds_bytes(prec, a.max_gslots, a.max_gcontrib, a.max_gch);
+    const size_t lds = contract_seg_lds_bytes(prec, a.max_gslots, a.max_gcontrib, a.max_gch, a.max_gstask);
     if (a.waves != 8 && a.waves != 16) return hipErrorInvalidValue;
     if (prec == 0)
       return a.waves == 16 ? launch_contract_t<double, 1024, true>(a, lds, st)

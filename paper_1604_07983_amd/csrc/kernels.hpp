@@ -60,7 +60,9 @@ constexpr long long kMaxLaunchItems = 1LL << 31;
 // lanes of a team (which differ in those indices) spread over the LDS banks
 // (144 and 12 complex entries are multiples of the bank cycle).  The channel
 // compiler precomputes per-product offsets in these units.
-constexpr int kLdsJ0 = 157, kLdsJ1 = 13, kLdsAl = 1888, kLdsBlock = 2 * kLdsAl;
+// The spin stride is 8 modulo 16 (complex entries) so that the rows of an
+// effective block, which differ by it, fall in different LDS banks.
+constexpr int kLdsJ0 = 157, kLdsJ1 = 13, kLdsAl = 1896, kLdsBlock = 2 * kLdsAl;
 // Integers per block-product descriptor (layout documented in compiler.hpp).
 constexpr int kProdInts = 48;
 // Segment descriptors of the matrix-core contraction: integers per
@@ -76,6 +78,10 @@ struct ContractGeom {
   void* Ft;        // [n_ch][t_count][16][V]
   int V, Lx, Ly, Lz, t_count, pad;
   long long block0;
+  // momentum of the i-th workgroup of a slice: q and -q are consecutive, so
+  // the two workgroups that read the same pair of blocks run together and
+  // the second finds them in the cache
+  const int* qorder;
 };
 constexpr int kMaxGeom = 32;
 
@@ -98,7 +104,7 @@ struct ContractArgs {
   // result slots per product, result slots per group
   int engine;
   const int *seg_task, *group_stask, *prod_ext;
-  int max_gslots;
+  int max_gslots, max_gstask;
   long long block0, n_chunk;  // logical workgroups [block0, block0 + n_chunk) in this launch
 };
 
@@ -142,7 +148,7 @@ int fft_plane_fields(int n, long long inner, int kind);
 hipError_t launch_fft_plane(int kind, int n, const FftPlaneArgs& a, hipStream_t st);
 hipError_t launch_fft_line(int kind, const FftArgs& a, hipStream_t st);
 size_t contract_lds_bytes(int prec, int max_gprod, int max_gcontrib, int max_gch, int max_gtask);
-size_t contract_seg_lds_bytes(int prec, int max_gslots, int max_gcontrib, int max_gch);
+size_t contract_seg_lds_bytes(int prec, int max_gslots, int max_gcontrib, int max_gch, int max_gstask);
 // Wavefronts per contraction workgroup for a precision (the channel compiler
 // balances each group's tasks over this many).
 int contract_waves(int prec);

@@ -343,9 +343,10 @@ nbs_status compile_and_upload(nbs_plan p) {
   c.group_stask = T("group_stask");
   c.prod_ext = T("prod_ext");
   c.max_gslots = std::max(1, P.max_group_slots);
+  c.max_gstask = std::max(1, P.max_group_stasks);
   c.waves = c.engine == 1 ? p->tune.seg_waves : p->tune.waves;
   const size_t lds = c.engine == 1
-                         ? nbs::contract_seg_lds_bytes(p->prec, c.max_gslots, c.max_gcontrib, c.max_gch)
+                         ? nbs::contract_seg_lds_bytes(p->prec, c.max_gslots, c.max_gcontrib, c.max_gch, c.max_gstask)
                          : nbs::contract_lds_bytes(p->prec, c.max_gprod, c.max_gcontrib, c.max_gch, c.max_gtask);
   if (lds > 160 * 1024) return fail(p, NBS_ERR_UNSUPPORTED, "a channel group needs more LDS than a CU has");
   return hip_check(p, nbs::prepare_kernels(p->prec, c.waves, lds, c.engine), "kernel attributes");
@@ -510,6 +511,10 @@ nbs_status create_plan(nbs_plan* out, const nbs_geometry* g, int32_t n_geom, con
       p->specs[c].src[k] = ch[c].src[k];
     }
   p->tune.waves = nbs::contract_waves(prec == NBS_FP64 ? 0 : 1);
+  // matrix-core engine: 1024-thread workgroups in FP64 (the two blocks fill
+  // the LDS, one workgroup per CU); 512 threads in the precision form, so
+  // that two workgroups share a CU and one stages while the other computes
+  p->tune.seg_waves = prec == NBS_FP64 ? 16 : 8;
   // the fused x-y pass pays off for FP64 storage (128-byte runs in 64 KB
   // tiles at 16^3); for complex64 the separate passes measured faster
   p->tune.fft_plane = prec == NBS_FP64 ? 1 : 0;
@@ -618,6 +623,12 @@ nbs_status create_plan(nbs_plan* out, const nbs_geometry* g, int32_t n_geom, con
   p->chan_nf = (int*)tmp;
   if ((s = dev_alloc(p, sizeof(nbs::ContractGeom) * n_geom, &tmp, &countdown)) != NBS_OK) return bail(s);
   p->geo = (nbs::ContractGeom*)tmp;
+  // per geometry: momenta in the order q, -q, q', -q', ...
+  std::vector<int*> qorder(n_geom, nullptr);
+  for (int i = 0; i < n_geom; ++i) {
+    if ((s = dev_alloc(p, p->gw[i].V * 4, &tmp, &countdown)) != NBS_OK) return bail(s);
+    qorder[i] = (int*)tmp;
+  }
   std::vector<nbs::ContractGeom> geo(n_geom);
   long long b0 = 0;
   for (int i = 0; i < n_geom; ++i) {
@@ -629,10 +640,29 @@ nbs_status create_plan(nbs_plan* out, const nbs_geometry* g, int32_t n_geom, con
     geo[i].t_count = w.g.t_count;
     geo[i].pad = 0;
     geo[i].block0 = b0;
+    geo[i].qorder = qorder[i];
     b0 += w.V * w.g.t_count;
   }
   hipError_t e = upload(p, p->chan_nf, nf.data(), nf.size() * 4);
   if (e == hipSuccess) e = upload(p, p->geo, geo.data(), sizeof(nbs::ContractGeom) * n_geom);
+  for (int i = 0; i < n_geom && e == hipSuccess; ++i) {
+    const int* L = p->gw[i].g.L;
+    const int V = (int)p->gw[i].V;
+    std::vector<int> order;
+    std::vector<char> placed(V, 0);
+    for (int q = 0; q < V; ++q) {
+      if (placed[q]) continue;
+      const int x = q % L[0], y = (q / L[0]) % L[1], z = q / (L[0] * L[1]);
+      const int mq = (L[0] - x) % L[0] + L[0] * ((L[1] - y) % L[1] + L[1] * ((L[2] - z) % L[2]));
+      order.push_back(q);
+      placed[q] = 1;
+      if (!placed[mq]) {
+        order.push_back(mq);
+        placed[mq] = 1;
+      }
+    }
+    e = upload(p, qorder[i], order.data(), (size_t)V * 4);
+  }
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return bail(NBS_ERR_DEVICE);

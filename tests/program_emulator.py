@@ -324,7 +324,7 @@ def quad_team_reduce(vals, lg):
 SEG_NAMES = ("seg_task", "group_stask", "prod_ext")
 SEG_INTS, SEG_TEAMS = 16, 4
 SEG_C144, SEG_C9, SEG_C36, SEG_C1, SEG_IDLE = 0, 1, 2, 3, 15
-LDS_AL, LDS_BLOCK = 1888, 2 * 1888
+LDS_AL, LDS_BLOCK = 1896, 2 * 1896
 
 
 def lds_image(block):

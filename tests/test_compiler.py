@@ -175,8 +175,12 @@ def test_segment_program_shapes_and_balance():
             for k in range(e >> 16):
                 owner[(e & 0xFFFF) + k] = p_
         cover = {}
+        align = {emu.SEG_C144: 3, emu.SEG_C36: 3, emu.SEG_C9: 3, emu.SEG_C1: 1}
         for shape, segs in steps.items():
             for slot, s0, n in segs:
+                # segments start and end where the kernel's per-lane pair
+                # indices start a new value
+                assert s0 % align[shape] == 0 and n % align[shape] == 0, (shape, s0, n)
                 cover.setdefault(owner[slot], []).append((s0, n, shape))
         assert sorted(cover) == list(range(np_))
         for p_, segs in cover.items():
