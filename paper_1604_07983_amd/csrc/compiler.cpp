@@ -299,7 +299,7 @@ bool segment_fields(const Block& b1, const Block& b2, int* shape, int* steps, in
     side2[0] = quark_unit(m2, ys); side2[1] = quark_unit(m2, p2); side2[2] = quark_unit(m2, q2);
     if (lone1 < 2 && lone2 < 2) { *shape = kSegC144; *steps = 36; }
     else if (lone1 == 2 && lone2 == 2) { *shape = kSegC9; *steps = 3; }
-    else { *shape = kSegC36; *steps = 18; }
+    else { *shape = kSegC36; *steps = 9; }
   }
   row_generator(s1, m1, side1 + 3);
   row_generator(s2, m2, side2 + 3);
@@ -319,7 +319,7 @@ bool segment_fields(const Block& b1, const Block& b2, int* shape, int* steps, in
 // Cost of one step of a segment shape for one lane (block entries read) and
 // of a segment's set-up and result store, in the same units.
 double seg_step_cost(int shape) {
-  return shape == kSegC144 ? 4.0 : shape == kSegC9 ? 16.0 : shape == kSegC36 ? 10.0 : 24.0;
+  return shape == kSegC144 ? 4.0 : shape == kSegC9 ? 16.0 : shape == kSegC36 ? 12.0 : 24.0;
 }
 constexpr double kSegOverhead = 8.0;
 
@@ -736,7 +736,7 @@ std::string compile_channels(const std::vector<ChannelSpec>& chans, const Compil
         SegPlan best;
         bool have = false;
         for (int l144 : {36, 18, 12, 9, 6, 3})
-          for (int l36 : {18, 12, 9, 6, 3}) {
+          for (int l36 : {9, 6, 3}) {
             SegPlan sp = plan_segments(base, nsteps, l144, l36, opt.seg_waves);
             if (sp.slots > opt.max_group_slots) continue;
             if (!have || sp.makespan < best.makespan - 1e-9 ||

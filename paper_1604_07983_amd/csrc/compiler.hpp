@@ -121,8 +121,9 @@ int product_class(int K, int rows1, int lone1, int lone2, int nm1, int nm2);
 //             index k' = 12 v1 + v2, v1 = s / 3, v2 = 4 (s % 3) + h
 //   kSegC9:   4 x 4 rows, both lone quarks colour only (K = 9): k' = 3 v1 + v2
 //   kSegC36:  8 x 2 rows (the 2-term side A has 8 rows, the 8-term side B 2):
-//             side A row r = x + 4 b', k' = 2 k + b', k = 12 v2 + v1; side B
-//             feeds E_B[x & 1][k] on lanes with x >> 1 == b', zero elsewhere
+//             two accumulators for side A's rows x and x + 4, side B fed on
+//             lanes x < 2 (zero elsewhere); k' = 12 v2 + v1, v2 = s / 3,
+//             v1 = 4 (s % 3) + h
 // Segments start and end on multiples of three steps.
 //   kSegC1:   two full projections (K = 1): the 24 source-tensor terms of
 //             each side are spread over the four h lanes and summed first

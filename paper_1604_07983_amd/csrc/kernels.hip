@@ -1413,6 +1413,14 @@ template <typename T> __device__ __forceinline__ T seg_hsum(T v) {
   return v;
 }
 
+// FP32 lanes 16 tm + 4 h + x: sum over h into the lanes with h = 3 (DPP row
+// shifts by 4 and 8 lanes within the 16-lane row, Hillis-Steele).
+__device__ __forceinline__ float seg_hsum_last(float v) {
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x114, 0xF, 0xF, true));
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x118, 0xF, 0xF, true));
+  return v;
+}
+
 __device__ __forceinline__ int seg_row(int r, const int* w) {
   return (r & 1) * w[0] + ((r >> 1) & 1) * w[1] + ((r >> 2) & 1) * w[2];
 }
@@ -1478,8 +1486,9 @@ __device__ __forceinline__ void seg_run(const int* d, const cx<T>* S1, const cx<
   int wa[3] = {d[7], d[8], d[9]}, wb[3] = {d[13], d[14], d[15]};
   const int uAs = d[4], uAp = d[5], uAq = d[6];
   const int uBs = d[10], uBp = d[11], uBq = d[12];
-  SegAcc<T> acc;
+  SegAcc<T> acc, acc2;
   seg_zero(acc);
+  seg_zero(acc2);
   const cx<T> zero{0, 0};
   if (shape == kSegC144) {
     // v1 = s / 3 (side A's pair, side B's single quark), v2 = 4 (s % 3) + h.
@@ -1509,32 +1518,31 @@ __device__ __forceinline__ void seg_run(const int* d, const cx<T>* S1, const cx<
       for (int m = 0; m < 3; ++m) seg_mma(acc, cdiff(ua[m], wa_[m]), cdiff(ub[m], wb_[m]));
     }
   } else if (shape == kSegC36) {
-    // k = 2 s + (h >> 1), b' = h & 1: side A row x + 4 b' at (v1, v2) =
-    // (k % 12, k / 12); side B row x & 1 on lanes with x >> 1 == b'.
-    // Step s has v2 = s / 6 and v1 = 2 j + (h >> 1), j = s % 6.
-    const int bp = h & 1, hh = h >> 1;
-    const int roA = seg_row(x + 4 * bp, wa), roB = seg_row(x & 1, wb) + hh * uBs;
-    const bool bl = (x >> 1) == bp;
+    // side A has 8 rows: two accumulators, rows x (acc) and x + 4 (acc2);
+    // side B has 2 rows, fed on lanes x < 2 (zero on the others).  Step s
+    // covers k = 4 s + h = 12 v2 + v1: v2 = s / 3 (side A's single quark,
+    // side B's pair), v1 = 4 (s % 3) + h (side A's pair, side B's single).
+    const int roA0 = seg_row(x, wa), roA1 = seg_row(x + 4, wa);
+    const int roB = seg_row(x & 1, wb) + h * uBs;
+    const bool bl = x < 2;
     int so[4];
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp) so[sp] = 3 * sp * uBp + 3 * (sp ^ 1) * uBq;
-    int v2 = s0 / 6, j = s0 - 6 * (s0 / 6);
-    int o0, o1;
-    seg_pair8(v2, uBp, uBq, o0, o1);
-    int bA = roA + v2 * uAs;
+    for (int it = 0; it < nsteps / 3; ++it) {
+      const int v2 = s0 / 3 + it;
+      int o0, o1;
+      seg_pair8(v2, uBp, uBq, o0, o1);
+      const int bA0 = roA0 + v2 * uAs, bA1 = roA1 + v2 * uAs;
 #pragma unroll 1
-    for (int it = 0; it < nsteps; ++it) {
-      int a0, a1;
-      seg_pair2(2 * j + hh, uAp, uAq, a0, a1);
-      const cx<T> a = cdiff(SA[bA + a0], SA[bA + a1]);
-      cx<T> b = zero;
-      if (bl) b = seg_entry8<T>(SB, roB + 2 * j * uBs, so, o0, o1);
-      seg_mma(acc, a, b);
-      if (++j == 6) {
-        j = 0;
-        ++v2;
-        seg_pair8(v2, uBp, uBq, o0, o1);
-        bA = roA + v2 * uAs;
+      for (int m = 0; m < 3; ++m) {
+        int p0, p1;
+        seg_pair2(4 * m + h, uAp, uAq, p0, p1);
+        const cx<T> a0 = cdiff(SA[bA0 + p0], SA[bA0 + p1]);
+        const cx<T> a1 = cdiff(SA[bA1 + p0], SA[bA1 + p1]);
+        cx<T> b = zero;
+        if (bl) b = seg_entry8<T>(SB, roB + 4 * m * uBs, so, o0, o1);
+        seg_mma(acc, a0, b);
+        seg_mma(acc2, a1, b);
       }
     }
   } else if (shape == kSegC9) {
@@ -1591,33 +1599,62 @@ __device__ __forceinline__ void seg_run(const int* d, const cx<T>* S1, const cx<
     if (h != 0) a = b = zero;
     seg_mma(acc, a, b);
   }
-  // results: D[i][j] = sum_k E_A[i][k] E_B[j][k]; canonical slot entry
-  // r1 * rows2 + r2 with (r1, r2) the rows of blocks 1 and 2
+  // results: D[i][j] = sum_k E_A[i][k] E_B[j][k] (for the 8 x 2 shape D
+  // of acc2 holds side A's rows i + 4); canonical slot entry r1 * rows2 + r2
+  // with (r1, r2) the rows of blocks 1 and 2
   const T sgn = ((hdr >> 16) & 1) ? (T)-1 : (T)1;
   const int slot = hdr & 0xffff;
-  auto put = [&](int i, int j, T re, T im) {
+  auto put = [&](int i, int j, int b, T re, T im) {
     int idx;
     if (shape == kSegC36) {
-      const int ra = i + 4 * (j >> 1), rb = j & 1;
-      idx = transposed ? rb * 8 + ra : ra * 2 + rb;
+      const int ra = i + 4 * b;
+      idx = transposed ? j * 8 + ra : ra * 2 + j;
     } else {
       idx = i * 4 + j;
     }
     R[slot * 16 + idx] = cx<T>{sgn * re, sgn * im};
   };
   if constexpr (sizeof(T) == 8) {
-    if (live) put(h, x, acc.rr - acc.ii, acc.ri);
+    if (live) {
+      if (shape == kSegC36) {
+        if (x < 2) {
+          put(h, x, 0, acc.rr - acc.ii, acc.ri);
+          put(h, x, 1, acc2.rr - acc2.ii, acc2.ri);
+        }
+      } else {
+        put(h, x, 0, acc.rr - acc.ii, acc.ri);
+      }
+    }
   } else {
-    // the four quads of the team hold partial sums over their slots h
+    // the four quads of the team hold partial sums over their slots h:
+    // summed into the quad h = 3
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      acc.rr[i] = seg_hsum(acc.rr[i]);
-      acc.ii[i] = seg_hsum(acc.ii[i]);
-      acc.ri[i] = seg_hsum(acc.ri[i]);
+      acc.rr[i] = seg_hsum_last(acc.rr[i]);
+      acc.ii[i] = seg_hsum_last(acc.ii[i]);
+      acc.ri[i] = seg_hsum_last(acc.ri[i]);
     }
-    if (live && h == 0) {
+    if (shape == kSegC36) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) put(i, x, acc.rr[i] - acc.ii[i], acc.ri[i]);
+      for (int i = 0; i < 4; ++i) {
+        acc2.rr[i] = seg_hsum_last(acc2.rr[i]);
+        acc2.ii[i] = seg_hsum_last(acc2.ii[i]);
+        acc2.ri[i] = seg_hsum_last(acc2.ri[i]);
+      }
+    }
+    if (live && h == 3) {
+      if (shape == kSegC36) {
+        if (x < 2) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            put(i, x, 0, acc.rr[i] - acc.ii[i], acc.ri[i]);
+            put(i, x, 1, acc2.rr[i] - acc2.ii[i], acc2.ri[i]);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) put(i, x, 0, acc.rr[i] - acc.ii[i], acc.ri[i]);
+      }
     }
   }
 }
@@ -1668,8 +1705,7 @@ template <typename T, int NT> struct BlockRegs {
   }
 };
 
-template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_contract_seg(ContractArgs a) {
+template <typename T, int NT> __device__ __forceinline__ void contract_seg_body(const ContractArgs& a) {
   extern __shared__ __align__(16) char smem_raw[];
   const long long nb8 = (a.n_chunk + 7) / 8 * 8;
   const long long b = blockIdx.x;
@@ -1815,6 +1851,15 @@ __global__ __launch_bounds__(NT) void k_contract_seg(ContractArgs a) {
       pf.store(slotB, tid);
     }
   }
+}
+
+template <typename T, int NT> __global__ __launch_bounds__(NT) void k_contract_seg(ContractArgs a) {
+  contract_seg_body<T, NT>(a);
+}
+// Precision form, 512 threads: four wavefronts per SIMD (registers for two
+// workgroups per CU), so that one stages blocks while the other computes.
+template <> __global__ __launch_bounds__(512, 4) void k_contract_seg<float, 512>(ContractArgs a) {
+  contract_seg_body<float, 512>(a);
 }
 
 // ---------------------------------------------------------------------------

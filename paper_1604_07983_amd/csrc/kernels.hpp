@@ -60,9 +60,10 @@ constexpr long long kMaxLaunchItems = 1LL << 31;
 // lanes of a team (which differ in those indices) spread over the LDS banks
 // (144 and 12 complex entries are multiples of the bank cycle).  The channel
 // compiler precomputes per-product offsets in these units.
-// The spin stride is 8 modulo 16 (complex entries) so that the rows of an
-// effective block, which differ by it, fall in different LDS banks.
-constexpr int kLdsJ0 = 157, kLdsJ1 = 13, kLdsAl = 1896, kLdsBlock = 2 * kLdsAl;
+// The spin stride is 4 modulo 8 (complex entries) so that the rows of an
+// effective block, which differ by it and by a label weight, fall in
+// different LDS banks.
+constexpr int kLdsJ0 = 157, kLdsJ1 = 13, kLdsAl = 1892, kLdsBlock = 2 * kLdsAl;
 // Integers per block-product descriptor (layout documented in compiler.hpp).
 constexpr int kProdInts = 48;
 // Segment descriptors of the matrix-core contraction: integers per

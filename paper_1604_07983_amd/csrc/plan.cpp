@@ -511,10 +511,9 @@ nbs_status create_plan(nbs_plan* out, const nbs_geometry* g, int32_t n_geom, con
       p->specs[c].src[k] = ch[c].src[k];
     }
   p->tune.waves = nbs::contract_waves(prec == NBS_FP64 ? 0 : 1);
-  // matrix-core engine: 1024-thread workgroups in FP64 (the two blocks fill
-  // the LDS, one workgroup per CU); 512 threads in the precision form, so
-  // that two workgroups share a CU and one stages while the other computes
-  p->tune.seg_waves = prec == NBS_FP64 ? 16 : 8;
+  // matrix-core engine: 512-thread workgroups (measured faster than 1024 in
+  // both forms; in the precision form two of them share a CU)
+  p->tune.seg_waves = 8;
   // the fused x-y pass pays off for FP64 storage (128-byte runs in 64 KB
   // tiles at 16^3); for complex64 the separate passes measured faster
   p->tune.fft_plane = prec == NBS_FP64 ? 1 : 0;

@@ -324,7 +324,7 @@ def quad_team_reduce(vals, lg):
 SEG_NAMES = ("seg_task", "group_stask", "prod_ext")
 SEG_INTS, SEG_TEAMS = 16, 4
 SEG_C144, SEG_C9, SEG_C36, SEG_C1, SEG_IDLE = 0, 1, 2, 3, 15
-LDS_AL, LDS_BLOCK = 1896, 2 * 1896
+LDS_AL, LDS_BLOCK = 1892, 2 * 1892
 
 
 def lds_image(block):
@@ -374,8 +374,10 @@ def seg_run(d, S1, S2, shape, nsteps):
     uAs, uAp, uAq, wa = int(d[4]), int(d[5]), int(d[6]), [int(v) for v in d[7:10]]
     uBs, uBp, uBq, wb = int(d[10]), int(d[11]), int(d[12]), [int(v) for v in d[13:16]]
     D = np.zeros((4, 4), dtype=np.complex128)
+    D2 = np.zeros((4, 4), dtype=np.complex128)
     for s in range(s0, s0 + nsteps):
         A = np.zeros((4, 4), dtype=np.complex128)  # [row x][slot h]
+        A2 = np.zeros((4, 4), dtype=np.complex128)  # rows x + 4 of the 8 x 2 shape
         B = np.zeros((4, 4), dtype=np.complex128)
         for h in range(4):
             for x in range(4):
@@ -386,13 +388,12 @@ def seg_run(d, S1, S2, shape, nsteps):
                     o0, o1, g = _pair2(v2, uBp, uBq)
                     B[x, h] = _entry2(SB, _seg_row(x, wb) + v1 * uBs, o0, o1, g)
                 elif shape == SEG_C36:
-                    bp = h & 1
-                    k = 2 * s + (h >> 1)
-                    v2, v1 = divmod(k, 12)
+                    v2, v1 = s // 3, 4 * (s % 3) + h
                     o0, o1, g = _pair2(v1, uAp, uAq)
-                    A[x, h] = _entry2(SA, _seg_row(x + 4 * bp, wa) + v2 * uAs, o0, o1, g)
-                    if (x >> 1) == bp:
-                        B[x, h] = _entry8(SB, _seg_row(x & 1, wb) + v1 * uBs, uBp, uBq, v2)
+                    A[x, h] = _entry2(SA, _seg_row(x, wa) + v2 * uAs, o0, o1, g)
+                    A2[x, h] = _entry2(SA, _seg_row(x + 4, wa) + v2 * uAs, o0, o1, g)
+                    if x < 2:
+                        B[x, h] = _entry8(SB, _seg_row(x, wb) + v1 * uBs, uBp, uBq, v2)
                 elif shape == SEG_C9:
                     kk = 4 * s + h
                     if kk < 9:
@@ -415,16 +416,20 @@ def seg_run(d, S1, S2, shape, nsteps):
             A = np.concatenate([A.sum(axis=1, keepdims=True), np.zeros((4, 3))], axis=1)
             B = np.concatenate([B.sum(axis=1, keepdims=True), np.zeros((4, 3))], axis=1)
         D += A @ B.T
+        D2 += A2 @ B.T
     sgn = -1 if (hdr >> 16) & 1 else 1
     R = np.zeros(16, dtype=np.complex128)
     for i in range(4):
         for j in range(4):
             if shape == SEG_C36:
-                ra, rb = i + 4 * (j >> 1), j & 1
-                idx = rb * 8 + ra if transposed else ra * 2 + rb
+                if j >= 2:
+                    assert D[i, j] == 0 and D2[i, j] == 0
+                    continue
+                for b, Db in ((0, D), (1, D2)):
+                    ra = i + 4 * b
+                    R[j * 8 + ra if transposed else ra * 2 + j] = sgn * Db[i, j]
             else:
-                idx = i * 4 + j
-            R[idx] = sgn * D[i, j]
+                R[i * 4 + j] = sgn * D[i, j]
     return R
 
 

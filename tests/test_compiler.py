@@ -158,7 +158,7 @@ def test_segment_program_shapes_and_balance():
     p = host_plan(channels.r52())
     tasks = p.table("seg_task").reshape(-1, emu.SEG_TEAMS, emu.SEG_INTS)
     gs, gp, ext = p.table("group_stask"), p.table("group_prod"), p.table("prod_ext")
-    full = {emu.SEG_C144: 36, emu.SEG_C9: 3, emu.SEG_C36: 18, emu.SEG_C1: 1}
+    full = {emu.SEG_C144: 36, emu.SEG_C9: 3, emu.SEG_C36: 9, emu.SEG_C1: 1}
     for g in range(len(gp) - 1):
         np_ = gp[g + 1] - gp[g]
         steps = {}
@@ -337,8 +337,8 @@ def test_set_tuning_rejects_bad_shapes():
     for kw in (dict(fft_tile=300), dict(waves=4), dict(mfma=1), dict(gchunk=3), dict(engine=0, waves=16)):
         with pytest.raises(binding.NbsError):
             p.set_tuning(**kw)
-    # the matrix-core engine with 16-wavefront workgroups by default
-    assert p.tuning()["waves"] == 16 and p.tuning()["engine"] == 1
+    # the matrix-core engine with 8-wavefront workgroups by default
+    assert p.tuning()["waves"] == 8 and p.tuning()["engine"] == 1
     p.set_tuning(engine=0, waves=8)
     assert p.tuning()["waves"] == 8 and p.tuning()["engine"] == 0
 

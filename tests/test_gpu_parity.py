@@ -141,12 +141,12 @@ def test_square_plane_lattice(prec):
 @pytest.mark.parametrize("tuning", [dict(engine=0, waves=4), dict(engine=0, mfma=1, waves=4),
                                     dict(engine=0, mfma=1, waves=8),
                                     dict(engine=0, waves=4, split=0, fft_line=0, fft_tile=2048), dict(fft_plane=1),
-                                    dict(gchunk=1), dict(gchunk=2, waves=8), dict(waves=8)])
+                                    dict(gchunk=1), dict(gchunk=2, waves=8), dict(waves=16)])
 def test_precision_form_launch_shapes(tuning):
     """The precision form under other launch shapes (the lane-team engine
     with and without its matrix-core quads, 256- and 512-thread workgroups,
     no index splitting, LDS-tile transforms, the fused x-y pass, group
-    ranges, 512-thread matrix-core workgroups) on every R52 channel."""
+    ranges, 1024-thread matrix-core workgroups) on every R52 channel."""
     announce("precision form shapes %s" % tuning)
     L, T = (8, 8, 3), 2
     props = runner.host_props(L, T, range(T), dtype=np.complex64)
@@ -172,11 +172,11 @@ def test_precision_form_long_register_lines(L):
 
 
 @pytest.mark.parametrize("tuning", [dict(gchunk=1), dict(gchunk=2), dict(engine=0, waves=8),
-                                    dict(engine=0, waves=8, gchunk=2), dict(waves=8)])
+                                    dict(engine=0, waves=8, gchunk=2), dict(waves=16)])
 def test_fp64_launch_shapes(tuning):
     """Double precision with workgroups that walk one run of sink-operator
     groups in which one operator block stays, or a single group, with the
-    lane-team engine, and with 512-thread matrix-core workgroups, on every
+    lane-team engine, and with 1024-thread matrix-core workgroups, on every
     R52 channel."""
     announce("fp64 launch shapes %s" % tuning)
     L, T = (6, 4, 5), 2
