@@ -888,10 +888,8 @@ nbs_status nbs_plan_autotune(nbs_plan p, const void* const* prop_u, const void* 
   // engine 1: matrix-core segments with 16 or 8 wavefronts per workgroup;
   // engine 0: lane teams with their own shapes
   struct ConChoice { int engine, waves, split, mfma; };
-  std::vector<ConChoice> con_cands = {{1, 16, 1, 0}, {1, 8, 1, 0}, {0, 8, 1, 0}, {0, 8, 0, 0}};
-  if (p->prec == NBS_FP32_MFMA)
-    con_cands = {{1, 16, 1, 0}, {1, 8, 1, 0}, {0, 4, 1, 1}, {0, 4, 0, 1}, {0, 8, 1, 1},
-                 {0, 4, 1, 0}, {0, 4, 0, 0}, {0, 8, 1, 0}, {0, 8, 0, 0}};
+  std::vector<ConChoice> con_cands = {{1, 8, 1, 0}, {1, 16, 1, 0}, {0, 8, 1, 0}};
+  if (p->prec == NBS_FP32_MFMA) con_cands = {{1, 8, 1, 0}, {1, 16, 1, 0}, {0, 4, 1, 0}};
   ConChoice best_con = con_cands[0];
   first = true;
   const Tuning before = p->tune;

@@ -5,6 +5,10 @@ happens inside libnbs's HIP kernels.
 """
 from __future__ import annotations
 
+import hashlib
+import json
+import os
+
 import numpy as np
 
 from . import binding, synth
@@ -53,6 +57,45 @@ def host_props_many(geoms, decay=DECAY, dtype=np.complex128, workers=8):
     import multiprocessing as mp
     with cf.ProcessPoolExecutor(max_workers=min(workers, len(jobs)), mp_context=mp.get_context("spawn")) as ex:
         return list(ex.map(_props_job, jobs))
+
+
+def tune_cache_path():
+    """File of autotuned launch shapes: $NBS_TUNE_CACHE, else
+    ~/.cache/nbs/tuning.json."""
+    return os.environ.get("NBS_TUNE_CACHE") or os.path.join(os.path.expanduser("~"), ".cache", "nbs", "tuning.json")
+
+
+def _tune_key(plan, geoms):
+    torch = _torch()
+    arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
+    g = ";".join("%s/%d/%d/%d/%d" % ("x".join(map(str, x["L"])), x["T"], x.get("t0", 0), x.get("t_begin", 0),
+                                        x.get("t_count", 1)) for x in geoms)
+    codes = [[binding.OPS[b] if isinstance(b, str) else int(b) for b in c] for c in plan.chans]
+    ch = hashlib.sha256(np.asarray(codes, dtype=np.int32).tobytes()).hexdigest()[:16]
+    return "%s|prec%d|%s|%s" % (arch, plan.prec, g, ch)
+
+
+def _tune_cache_load():
+    try:
+        with open(tune_cache_path()) as f:
+            d = json.load(f)
+        return d if isinstance(d, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def _tune_cache_store(key, tune):
+    path = tune_cache_path()
+    d = _tune_cache_load()
+    d[key] = {k: int(v) for k, v in tune.items()}
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as f:
+            json.dump(d, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass
 
 
 class Runner:
@@ -147,9 +190,24 @@ class BatchRunner:
         self.plan.run_graph(*self._split(props), [f.data_ptr() for f in self.F], self.stream())
         return self.F
 
-    def autotune(self, props):
+    def autotune(self, props, cache=False):
+        """nbs_plan_autotune with the caller's propagators; with cache=True
+        the chosen shapes are kept in a JSON file keyed by (GPU architecture,
+        precision, geometries, channels) and reused instead of measuring
+        again."""
+        key = _tune_key(self.plan, self.geoms) if cache else None
+        if key is not None:
+            hit = _tune_cache_load().get(key)
+            if hit is not None:
+                self.plan.set_tuning(**hit)
+                # leave the plan built, as nbs_plan_autotune does
+                self.build(props)
+                return self.plan.tuning()
         self.plan.autotune(*self._split(props), self.stream())
-        return self.plan.tuning()
+        tune = self.plan.tuning()
+        if key is not None:
+            _tune_cache_store(key, tune)
+        return tune
 
     def close(self):
         self.plan.close()
