@@ -19,6 +19,17 @@
 
 namespace nbs {
 
+// Lane moves within rows of 16 lanes (DPP), for floats and doubles.
+template <int CTRL> __device__ __forceinline__ float dpp_move(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL> __device__ __forceinline__ double dpp_move(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // ---------------------------------------------------------------------------
 // per-slice scale (precision form): max |Re|,|Im| of each flavour on each
 // slice, kept as float bits (monotone for non-negative floats, so the
@@ -222,16 +233,11 @@ __global__ __launch_bounds__(kThreads) void k_fft_pass(FftArgs a) {
 // One axis of the batched transform with the whole line in registers: thread
 // (o, i) transforms the N elements o N inner + i + k inner, k < N.  Adjacent
 // threads take adjacent i, so every load and store of a wavefront is one
-// contiguous run.  Arithmetic in FP64 whatever the storage type, except the
-// precision form's forward lines longer than 48 (64, 80, 96), which keep
-// complex64 storage and FP32 arithmetic so that the line fits in registers.
-constexpr int kLineMaxFp64 = 48;
-
+// contiguous run.  Arithmetic in FP64 whatever the storage type.  Lines up
+// to 48 points; 64, 80 and 96 take two threads per line (k_fft_line2).
 template <int N, int SIGN, typename Tin, typename Tout>
 __global__ __launch_bounds__(kThreads) void k_fft_line(FftArgs a) {
-  using AT = std::conditional_t<(N > kLineMaxFp64), float, double>;
-  static_assert(N <= kLineMaxFp64 || (std::is_same<Tin, float>::value && std::is_same<Tout, float>::value),
-                "long register lines are complex64 only");
+  using AT = double;
   const long long gid = a.unit0 + (long long)blockIdx.x * kThreads + threadIdx.x;
   if (gid >= a.outer * a.inner) return;
   const long long o = gid / a.inner, i = gid - o * a.inner;
@@ -247,6 +253,42 @@ __global__ __launch_bounds__(kThreads) void k_fft_line(FftArgs a) {
   cx<Tout>* out = reinterpret_cast<cx<Tout>*>(a.out);
 #pragma unroll
   for (int k = 0; k < N; ++k) out[base + k * a.inner] = conv<Tout>(cx<AT>{v[k].re * fa, v[k].im * fa});
+}
+
+// Lines of N = 2 M points (64, 80, 96) with FP64 arithmetic, two threads
+// per line: thread r (r = 0, 1; adjacent lanes) loads the points 2 m + r,
+// transforms them (length M, registers), and the pair combines the halves
+// by decimation in time, X[k] = E[k] + w^k O[k], X[k + M] = E[k] - w^k O[k]
+// with w = exp(SIGN 2 pi i / N), exchanging one half through a DPP lane
+// swap; thread r writes X[r M .. r M + M).
+template <int N, int SIGN, typename Tin, typename Tout>
+__global__ __launch_bounds__(kThreads) void k_fft_line2(FftArgs a) {
+  constexpr int M = N / 2;
+  const long long gid = 2 * a.unit0 + (long long)blockIdx.x * kThreads + threadIdx.x;
+  const long long line = gid >> 1;
+  const int r = (int)(gid & 1);
+  // both threads of a pair are in range together (the grid covers 2 x lines)
+  if (line >= a.outer * a.inner) return;
+  const long long o = line / a.inner, i = line - o * a.inner;
+  const long long base = o * N * a.inner + i;
+  const cx<Tin>* in = reinterpret_cast<const cx<Tin>*>(a.in);
+  cd v[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) v[m] = conv<double>(in[base + (2 * m + r) * a.inner]);
+  fft_reg<M, SIGN>(v);
+  constexpr ct::Twiddles<N> tw = ct::make_twiddles<N>();
+  double f = a.gscale;
+  if (a.oscale) f *= a.oscale[o / a.oscale_div];
+  cx<Tout>* out = reinterpret_cast<cx<Tout>*>(a.out);
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    // the partner's value of this k (lane ^ 1)
+    const cd w{dpp_move<0xB1>(v[k].re), dpp_move<0xB1>(v[k].im)};
+    const cd E = r ? w : v[k], O = r ? v[k] : w;
+    const cd t = O * cd{tw.c[k], SIGN * tw.s[k]};
+    const cd x = r ? E - t : E + t;
+    out[base + (k + r * M) * a.inner] = conv<Tout>(cd{x.re * f, x.im * f});
+  }
 }
 
 // The x and y axes of a forward transform in one pass.  Workgroup (plane,
@@ -916,16 +958,6 @@ __device__ __forceinline__ ContractGeom find_geometry(const ContractGeom* geo, i
 // 1..0 and 2..0 and keep 4 and 2 outputs per lane); rows of 32- and 64-lane
 // teams are added with cross-row shuffles.  About 15 complex
 // moves per lane instead of 16 per butterfly step, and a fixed order.
-template <int CTRL> __device__ __forceinline__ float dpp_move(float x) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, true));
-}
-template <int CTRL> __device__ __forceinline__ double dpp_move(double x) {
-  const long long b = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, true);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
 template <int CTRL, int NV, typename T>
 __device__ __forceinline__ void rs_step(const cx<T>* in, cx<T>* out, bool upper) {
 #pragma unroll
@@ -1979,6 +2011,28 @@ template <int N> hipError_t launch_line_kind(int kind, const FftArgs& a, hipStre
   return launch_line<N, 1, float, double>(a, st);                  // first inverse pass of the precision form
 }
 
+// Long lines, two threads per line.
+template <int N, int SIGN, typename Tin, typename Tout> hipError_t launch_line2(const FftArgs& a, hipStream_t st) {
+  const long long lines = a.outer * a.inner;
+  const long long per = kMaxLaunchItems / 2;
+  for (long long l0 = 0; l0 < lines; l0 += per) {
+    FftArgs c = a;
+    c.unit0 = l0;
+    const long long n = lines - l0 < per ? lines - l0 : per;
+    hipLaunchKernelGGL((k_fft_line2<N, SIGN, Tin, Tout>), dim3((unsigned)((2 * n + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, st, c);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <int N> hipError_t launch_line2_kind(int kind, const FftArgs& a, hipStream_t st) {
+  if (kind == 0) return a.sign < 0 ? launch_line2<N, -1, double, double>(a, st) : launch_line2<N, 1, double, double>(a, st);
+  if (kind == 1) return launch_line2<N, -1, float, float>(a, st);
+  return launch_line2<N, 1, float, double>(a, st);
+}
+
 }  // namespace
 
 bool fft_line_supported(int n, int kind) {
@@ -1987,7 +2041,7 @@ bool fft_line_supported(int n, int kind) {
     case 40: case 48:
       return true;
     case 64: case 80: case 96:
-      return kind == 1;
+      return true;
   }
   return false;
 }
@@ -2069,10 +2123,10 @@ hipError_t launch_fft_line(int kind, const FftArgs& a, hipStream_t st) {
     case 32: return launch_line_kind<32>(kind, a, st);
     case 40: return launch_line_kind<40>(kind, a, st);
     case 48: return launch_line_kind<48>(kind, a, st);
-    // long lines: the precision form's forward transform only
-    case 64: return kind == 1 ? launch_line<64, -1, float, float>(a, st) : hipErrorInvalidValue;
-    case 80: return kind == 1 ? launch_line<80, -1, float, float>(a, st) : hipErrorInvalidValue;
-    case 96: return kind == 1 ? launch_line<96, -1, float, float>(a, st) : hipErrorInvalidValue;
+    // long lines: two threads per line
+    case 64: return launch_line2_kind<64>(kind, a, st);
+    case 80: return launch_line2_kind<80>(kind, a, st);
+    case 96: return launch_line2_kind<96>(kind, a, st);
   }
   return hipErrorInvalidValue;
 }

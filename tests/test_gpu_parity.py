@@ -157,18 +157,20 @@ def test_precision_form_launch_shapes(tuning):
     assert err.max() <= 1e-5, (err.max(), int(err.argmax()))
 
 
+@pytest.mark.parametrize("prec", [binding.NBS_FP64, binding.NBS_FP32_MFMA])
 @pytest.mark.parametrize("L", [(64, 2, 3), (80, 2, 2), (96, 2, 2)])
-def test_precision_form_long_register_lines(L):
-    """Lines of 64, 80 and 96 points: the precision form's forward transform
-    holds them in registers with FP32 arithmetic; channels of every
+def test_long_register_lines(L, prec):
+    """Lines of 64, 80 and 96 points, two threads per line with FP64
+    arithmetic, forward and inverse, in both forms; channels of every
     strangeness sector against the oracle."""
-    announce("precision form long lines %s" % (L,))
+    announce("long lines %s prec=%d" % (L, prec))
     chans = [channels.r52()[c] for c in (0, 1, 2, 12, 22, 30, 51)]
-    props = runner.host_props(L, 2, range(1), dtype=np.complex64)
-    Fg = run_gpu(L, 2, chans, props, binding.NBS_FP32_MFMA, t_count=1)
+    dt = np.complex128 if prec == binding.NBS_FP64 else np.complex64
+    props = runner.host_props(L, 2, range(1), dtype=dt)
+    Fg = run_gpu(L, 2, chans, props, prec, t_count=1)
     Fo = oracle_F(L, props, chans)
     err = rel_err_per_channel(Fg, Fo)
-    assert err.max() <= 1e-5, (err.max(), int(err.argmax()))
+    assert err.max() <= TOL[prec], (err.max(), int(err.argmax()))
 
 
 @pytest.mark.parametrize("tuning", [dict(gchunk=1), dict(gchunk=2), dict(engine=0, waves=8),
