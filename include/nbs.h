@@ -189,6 +189,15 @@ nbs_status nbs_plan_tuning(const nbs_plan plan, int32_t out[4]);
  * modes above 2. */
 nbs_status nbs_plan_set_tuning(nbs_plan plan, const int32_t in[4]);
 
+/* Whether the propagators of the plan's last nbs_build_blocks (or
+ * nbs_run_graph) held a NaN or an infinite entry: *found = 1 if so, else 0.
+ * The block kernel checks every entry it reads; such entries are not
+ * replaced, so the outputs of that build are not finite either, and in the
+ * precision form an infinite maximum leaves the slice's scale at 1.  Waits
+ * for all work on the plan's device.  NBS_ERR_STATE before the first build or
+ * on a host-only plan. */
+nbs_status nbs_plan_nonfinite(nbs_plan plan, int32_t* found);
+
 /* Release everything the plan owns (waits for its device work). NULL is ok. */
 nbs_status nbs_plan_destroy(nbs_plan plan);
 

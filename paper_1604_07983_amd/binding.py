@@ -22,7 +22,7 @@ SYMBOLS = ("nbs_plan_create", "nbs_workspace_bytes", "nbs_build_blocks", "nbs_co
            "nbs_relative_sum", "nbs_plan_destroy", "nbs_status_string", "nbs_last_error",
            "nbs_plan_info", "nbs_plan_diagrams", "nbs_plan_table", "nbs_plan_params", "nbs_run_graph",
            "nbs_plan_autotune", "nbs_plan_tuning", "nbs_plan_set_tuning", "nbs_two_point",
-           "nbs_four_point_static", "nbs_static_last_error")
+           "nbs_four_point_static", "nbs_static_last_error", "nbs_plan_nonfinite")
 
 
 class NbsError(RuntimeError):
@@ -103,6 +103,8 @@ def lib():
         L.nbs_plan_tuning.restype = I32
         L.nbs_plan_set_tuning.argtypes = [P, ctypes.POINTER(I32)]
         L.nbs_plan_set_tuning.restype = I32
+        L.nbs_plan_nonfinite.argtypes = [P, ctypes.POINTER(I32)]
+        L.nbs_plan_nonfinite.restype = I32
         L.nbs_four_point_static.argtypes = [ctypes.POINTER(Geometry), ctypes.POINTER(Channel), I32, I32, P, P, P,
                                             P, P]
         L.nbs_four_point_static.restype = I32
@@ -222,6 +224,12 @@ class Plan:
         n = self.n_geom
         self._check(lib().nbs_plan_autotune(self._h, _ptrs(prop_u, n), _ptrs(prop_d, n), _ptrs(prop_s, n),
                                             ctypes.c_void_p(stream)), "nbs_plan_autotune")
+
+    def nonfinite(self):
+        """True if the last build's propagators held a NaN or infinite entry."""
+        f = ctypes.c_int32(0)
+        self._check(lib().nbs_plan_nonfinite(self._h, ctypes.byref(f)), "nbs_plan_nonfinite")
+        return bool(f.value)
 
     def tuning(self):
         out = (ctypes.c_int32 * 4)()

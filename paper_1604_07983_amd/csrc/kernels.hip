@@ -10,6 +10,8 @@
 //               scale of the precision form and its exact undo
 #include <hip/hip_runtime.h>
 
+#include <cfloat>
+#include <limits>
 #include <type_traits>
 
 #include "cx.hpp"
@@ -64,7 +66,9 @@ __global__ void k_scale_exps(const unsigned* maxbits, int* exps, int n) {
   if (i >= n) return;
   const float m = __uint_as_float(maxbits[i]);
   int e = 0;
-  if (m > 0.f) frexpf(m, &e);  // m = f 2^e, f in [0.5, 1): S 2^-e has max in [0.5, 1)
+  // m = f 2^e, f in [0.5, 1): S 2^-e has max in [0.5, 1); an infinite
+  // maximum (non-finite input, reported by the block kernel) keeps scale 1
+  if (m > 0.f && m <= FLT_MAX) frexpf(m, &e);
   exps[i] = e;
 }
 
@@ -97,6 +101,9 @@ __global__ __launch_bounds__(kThreads) void k_nbb(NbbArgs a) {
     const int f = i / 144, e = i % 144;
     if (!a.flavour_used[f]) continue;
     const cx<Tin> v = reinterpret_cast<const cx<Tin>*>(a.S[f])[sbase + e];
+    // NaN fails every comparison; infinities exceed the largest finite value
+    constexpr Tin kMax = std::numeric_limits<Tin>::max();
+    if (!(fabs(v.re) <= kMax && fabs(v.im) <= kMax)) atomicOr(a.nonfinite, 1u);
     T sc = (T)1;
     if (a.scale_exp) sc = (T)ldexp(1.0, -a.scale_exp[f * a.t_count + t]);
     S[f][e] = cx<T>{(T)v.re * sc, (T)v.im * sc};

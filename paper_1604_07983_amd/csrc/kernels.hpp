@@ -24,6 +24,7 @@ struct NbbArgs {
   int op_pair[kMaxOps];
   int flavour_used[3];
   const int* scale_exp;  // [3][t_count] power-of-two exponents (precision form) or null
+  unsigned* nonfinite;   // set to 1 when a propagator entry read is NaN or infinite
 };
 
 // One axis of a batched 3-D transform on an array viewed as

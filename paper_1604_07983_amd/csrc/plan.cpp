@@ -76,6 +76,7 @@ struct nbs_plan_s {
   bool iso = false;            // last build used the isospin-symmetric limit (prop_d == prop_u)
   int* chan_nf = nullptr;  // [n_ch][3] quark counts
   nbs::ContractGeom* geo = nullptr;
+  unsigned* nonfinite = nullptr;  // set by the block kernel on NaN / infinite propagator entries
   long long n_qt = 0;  // (slice, momentum) pairs over all geometries
   size_t dev_bytes = 0;
   std::map<std::string, size_t> prog_off;  // table name -> offset (ints) into prog
@@ -370,6 +371,9 @@ nbs_status enqueue_build(nbs_plan p, const void* const* pu, const void* const* p
   // first n_canon slots) are built and transformed (Sec. 3(i))
   p->iso = isospin_limit(p, pu, pd);
   const int n_build = p->iso ? p->comp.prog.n_canon : p->comp.prog.n_ops;
+  // the non-finite input flag of this build (a fill kernel, not a memset,
+  // so that the sequence can be captured into a graph)
+  if ((s = hip_check(p, nbs::launch_fill_u32(p->nonfinite, 0u, 1, st), "fill")) != NBS_OK) return s;
   for (size_t i = 0; i < p->gw.size(); ++i) {
     GeomWork& w = p->gw[i];
     const nbs_geometry& g = w.g;
@@ -381,6 +385,7 @@ nbs_status enqueue_build(nbs_plan p, const void* const* pu, const void* const* p
     a.t_count = g.t_count;
     a.n_ops = n_build;
     a.scale_exp = nullptr;
+    a.nonfinite = p->nonfinite;
     if (p->prec == NBS_FP32_MFMA) {
       if ((s = hip_check(p, nbs::launch_fill_u32(w.maxbits, 0u, 3LL * g.t_count, st), "fill")) != NBS_OK) return s;
       for (int f = 0; f < 3; ++f) {
@@ -622,6 +627,8 @@ nbs_status create_plan(nbs_plan* out, const nbs_geometry* g, int32_t n_geom, con
   p->chan_nf = (int*)tmp;
   if ((s = dev_alloc(p, sizeof(nbs::ContractGeom) * n_geom, &tmp, &countdown)) != NBS_OK) return bail(s);
   p->geo = (nbs::ContractGeom*)tmp;
+  if ((s = dev_alloc(p, 4, &tmp, &countdown)) != NBS_OK) return bail(s);
+  p->nonfinite = (unsigned*)tmp;
   // per geometry: momenta in the order q, -q, q', -q', ...
   std::vector<int*> qorder(n_geom, nullptr);
   for (int i = 0; i < n_geom; ++i) {
@@ -977,6 +984,20 @@ nbs_status nbs_plan_set_tuning(nbs_plan p, const int32_t in[4]) {
     (void)compile_and_upload(p);
     return s;
   }
+  return NBS_OK;
+}
+
+nbs_status nbs_plan_nonfinite(nbs_plan p, int32_t* found) {
+  if (!p || !found) return NBS_ERR_INVALID;
+  *found = 0;
+  if (p->device < 0) return fail(p, NBS_ERR_STATE, "host-only plan");
+  if (p->stage < ST_BUILT) return fail(p, NBS_ERR_STATE, "nbs_build_blocks must come first");
+  if (hipSetDevice(p->device) != hipSuccess) return fail(p, NBS_ERR_DEVICE, "hipSetDevice");
+  nbs_status s;
+  if ((s = hip_check(p, hipDeviceSynchronize(), "synchronize")) != NBS_OK) return s;
+  unsigned v = 0;
+  if ((s = hip_check(p, hipMemcpy(&v, p->nonfinite, 4, hipMemcpyDeviceToHost), "flag read")) != NBS_OK) return s;
+  *found = v ? 1 : 0;
   return NBS_OK;
 }
 
