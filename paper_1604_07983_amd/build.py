@@ -25,6 +25,28 @@ def hipcc_cmd(out: str):
     ] + [os.path.join(CSRC, s) for s in SOURCES]
 
 
+SYNTH_SOURCE = "synth.hip"
+SYNTH_LIB = os.path.join(LIBDIR, "libnbs_synth.so")
+
+
+def build_synth(verbose: bool = False) -> str:
+    """The device generator of the synthetic inputs (a library of its own:
+    input generation, not part of the method's path)."""
+    os.makedirs(LIBDIR, exist_ok=True)
+    tmp = SYNTH_LIB + ".tmp%d" % os.getpid()
+    cmd = ["hipcc", "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument",
+           "-o", tmp, os.path.join(CSRC, SYNTH_SOURCE)]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed building libnbs_synth.so")
+    if verbose:
+        sys.stderr.write(res.stderr)
+    os.replace(tmp, SYNTH_LIB)
+    return SYNTH_LIB
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(LIBDIR, exist_ok=True)
     tmp = LIB + ".tmp%d" % os.getpid()
@@ -36,6 +58,7 @@ def build(verbose: bool = False) -> str:
     if verbose:
         sys.stderr.write(res.stderr)
     os.replace(tmp, LIB)
+    build_synth(verbose)
     return LIB
 
 

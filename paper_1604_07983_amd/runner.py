@@ -68,8 +68,9 @@ def tune_cache_path():
 def _tune_key(plan, geoms):
     torch = _torch()
     arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
-    g = ";".join("%s/%d/%d/%d/%d" % ("x".join(map(str, x["L"])), x["T"], x.get("t0", 0), x.get("t_begin", 0),
-                                        x.get("t_count", 1)) for x in geoms)
+    # launch shapes depend on the extents and window lengths, not on which
+    # slices a window holds
+    g = ";".join("%s/%d/%d" % ("x".join(map(str, x["L"])), x["T"], x.get("t_count") or x["T"]) for x in geoms)
     codes = [[binding.OPS[b] if isinstance(b, str) else int(b) for b in c] for c in plan.chans]
     ch = hashlib.sha256(np.asarray(codes, dtype=np.int32).tobytes()).hexdigest()[:16]
     return "%s|prec%d|%s|%s" % (arch, plan.prec, g, ch)
@@ -211,3 +212,77 @@ class BatchRunner:
 
     def close(self):
         self.plan.close()
+
+
+def sink_slice_phases(lattices):
+    """Split the sink-slice windows of several lattices into phases: window w
+    holds sink slice t0 + w of every source of the lattices with T > w, so a
+    phase is a run of windows with the same set of lattices."""
+    phases, w = [], 0
+    maxT = max(T for _, T in lattices)
+    while w < maxT:
+        lats = [(tuple(L), T) for L, T in lattices if T > w]
+        w_end = min(T for _, T in lats)
+        phases.append((w, w_end, lats))
+        w = w_end
+    return phases
+
+
+def sweep_sink_slices(lattices, n_sources, chans, decay, on_window, prec=binding.NBS_FP32_MFMA, autotune=False,
+                      log=None):
+    """Every sink slice of n_sources source slices (t0 = k T / n_sources) per
+    lattice, as windows of one sink slice per geometry: one plan per phase
+    (sink_slice_phases), its graph captured once on fixed input buffers that
+    the device generator refills before each replay.  Source numbering: the
+    k-th source of the i-th lattice is i * n_sources + k.  After each replay
+    on_window(window, geoms, F, graph_ms) is called with the plan's outputs
+    (F on the device; the caller drains what it needs before returning).
+    Returns (graph milliseconds in total, windows, sites in total)."""
+    torch = _torch()
+    from . import synth_device
+    stream = torch.cuda.current_stream()
+    dt = torch.complex128 if prec == binding.NBS_FP64 else torch.complex64
+    total_ms, n_win, n_sites = 0.0, 0, 0
+    index = {(tuple(L), T): i for i, (L, T) in enumerate(lattices)}
+    for w0, w1, lats in sink_slice_phases(lattices):
+        geoms = []
+        for L, T in lats:
+            for k in range(n_sources):
+                t0 = k * T // n_sources
+                geoms.append(dict(L=L, T=T, t0=t0, t_begin=(t0 + w0) % T, t_count=1,
+                                  source=index[(L, T)] * n_sources + k))
+        if log:
+            log("windows %d-%d: %d geometries" % (w0, w1 - 1, len(geoms)))
+        bufs = [[torch.empty((1, g["L"][2], g["L"][1], g["L"][0], 12, 12), dtype=dt, device="cuda")
+                 for _ in range(3)] for g in geoms]
+
+        def fill(win):
+            for g, b in zip(geoms, bufs):
+                t = (g["t0"] + win) % g["T"]
+                for f, name in enumerate("uds"):
+                    synth_device.fill_slice(b[f], g["L"], t, f, decay[name], g["T"], t0=g["t0"], source=g["source"],
+                                            stream=stream.cuda_stream)
+
+        br = BatchRunner(geoms, chans, prec=prec)
+        try:
+            fill(w0)
+            if autotune:
+                br.autotune(bufs, cache=True)
+            br.run_graph(bufs)  # the capture; later replays read the refilled buffers
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            for win in range(w0, w1):
+                fill(win)
+                e0.record(stream)
+                br.run_graph(bufs)
+                e1.record(stream)
+                e1.synchronize()
+                ms = e0.elapsed_time(e1)
+                total_ms += ms
+                n_win += 1
+                n_sites += sum(g["L"][0] * g["L"][1] * g["L"][2] for g in geoms)
+                on_window(win, geoms, br.F, ms)
+        finally:
+            br.close()
+            del bufs
+    return total_ms, n_win, n_sites

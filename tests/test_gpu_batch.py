@@ -147,3 +147,36 @@ def test_config4_batch_full_size():
             err = np.linalg.norm(got - want, axis=1) / np.linalg.norm(want, axis=1)
             assert err.max() <= 1e-5, (g, q, float(err.max()), int(err.argmax()))
     br.close()
+
+
+def test_tuning_cache_round_trip(tmp_path, monkeypatch):
+    """Autotuned shapes land in the JSON cache under the architecture,
+    precision, extents and channels; a second plan of the same shapes reads
+    them back instead of measuring, and keeps parity."""
+    import json
+
+    import torch
+    announce("tuning cache")
+    monkeypatch.setenv("NBS_TUNE_CACHE", str(tmp_path / "tuning.json"))
+    geoms = small_geoms()[:2]
+    chans = [channels.r52()[c] for c in SUB]
+    prec = binding.NBS_FP32_MFMA
+    hprops = geom_props(geoms, np.complex64)
+    dprops = [runner.device_props(p, prec) for p in hprops]
+    br = runner.BatchRunner(geoms, chans, prec=prec)
+    tune = br.autotune(dprops, cache=True)
+    br.close()
+    d = json.load(open(tmp_path / "tuning.json"))
+    assert len(d) == 1
+    key, val = next(iter(d.items()))
+    assert key.startswith("gfx") and "|prec%d|" % prec in key and "4x4x4/8/2" in key
+    assert val == {k: int(v) for k, v in tune.items()}
+    # plant a distinct valid shape: the next plan must take it from the file
+    val2 = dict(val, engine=1, waves=16 if (val["engine"], val["waves"]) == (1, 8) else 8)
+    json.dump({key: val2}, open(tmp_path / "tuning.json", "w"))
+    br = runner.BatchRunner(geoms, chans, prec=prec)
+    assert br.autotune(dprops, cache=True) == val2
+    F = br.run(dprops)
+    torch.cuda.synchronize()
+    check_against_oracle(geoms, hprops, F, chans, 1e-5)
+    br.close()
