@@ -8,13 +8,13 @@
  * forces" (LATTICE 2015):
  *
  *   nbs_build_blocks       normal baryon blocks [B^(0)](x; xi1, xi2, xi3) of
- *                          Eq. (5) / Sec. 3(i) Eq. (8) on every sink site, then
+ *                          Eq. (5) / Sec. 4(i) Eq. (8) on every sink site, then
  *                          their 3-D Fourier transform to momentum space
- *                          ("replaced by its in momentum space", Sec. 3(i));
+ *                          (Sec. 4(i));
  *   nbs_contract_channels  effective baryon blocks in momentum space
- *                          (Sec. 3(ii), Eq. (9)) and their products summed
+ *                          (Sec. 4(ii), Eq. (9)) and their products summed
  *                          over the shared source indices and diagrams
- *                          (Sec. 3(iii), Eq. (10)), giving F~_c(q) per channel;
+ *                          (Sec. 4(iii), Eq. (10)), giving F~_c(q) per channel;
  *   nbs_relative_sum       inverse Fourier transform with the 1/L^3 of
  *                          Eq. (6): the sum over X at every relative r, i.e.
  *                          F_c(r, t - t0) of Eq. (1).
@@ -57,9 +57,17 @@ typedef enum {
 
 typedef enum {
   NBS_FP64 = 0,     /* plain form: complex128 propagators, FP64 throughout */
-  NBS_FP32_MFMA = 1 /* precision form: complex64 propagators, per-slice
-                       power-of-two scale, FP32 blocks and contractions,
-                       FP64 Fourier transforms and normalisation */
+  NBS_FP32_MFMA = 1 /* precision form: complex64 propagators and blocks
+                       in storage, per-slice power-of-two scale, block
+                       arithmetic in FP32, Fourier transforms computed in
+                       FP64 (stored as complex64), effective blocks and
+                       their products on the FP32 matrix cores
+                       (v_mfma_f32_4x4x1f32, FP32 accumulation) with the
+                       default launch shapes, FP64 channel normalisation.
+                       The name says which matrix-core instruction the
+                       contraction uses; it does not promise that every
+                       step runs on matrix cores (the block build and the
+                       transforms are vector-ALU code in both forms). */
 } nbs_precision;
 
 /* Interpolating fields of Eqs. (2)-(3). */
@@ -85,7 +93,7 @@ typedef struct {
 
 typedef struct nbs_plan_s* nbs_plan;
 
-/* Compile the channel table (Sec. 3(ii)-(iii): diagram classification into
+/* Compile the channel table (Sec. 4(ii)-(iii): diagram classification into
  * structure-of-arrays tables, done once on the host) and allocate device
  * workspace.  g: n_geom geometries, 1 <= n_geom <= 32 (NBS_ERR_UNSUPPORTED
  * above).  Geometries may differ in every field (lattice extents, T, source
@@ -108,10 +116,12 @@ nbs_status nbs_workspace_bytes(const nbs_plan plan, size_t* bytes);
  * [t_count][Lz][Ly][Lx][12][12] complex (complex128 for NBS_FP64,
  * complex64 for NBS_FP32_MFMA), owned by the caller and read-only.
  * prop_d / prop_s may alias prop_u.  When prop_d[g] == prop_u[g] for every
- * geometry (the isospin-symmetric limit S_d = S_u of Sec. 3(i)), only the
- * canonical operator blocks are built and transformed and n, Sigma-, Xi-
- * are read as -p, Sigma+, -Xi0 by the contraction (nbs_plan_table
- * "op_alias", "op_alias_coef").  stream: a hipStream_t (NULL = the default
+ * geometry (the isospin-symmetric limit S_d = S_u of Sec. 4(i)), only the
+ * canonical operator blocks are built and transformed and Sigma-, Xi- are
+ * read as Sigma+, -Xi0 by the contraction (nbs_plan_table "op_alias",
+ * "op_alias_coef"); n keeps its own block, since blocks are stored
+ * antisymmetrised in their same-flavour slot pair and n's pair differs
+ * from p's.  stream: a hipStream_t (NULL = the default
  * stream); the call is asynchronous on it. */
 nbs_status nbs_build_blocks(nbs_plan plan, const void* const* prop_u,
                             const void* const* prop_d, const void* const* prop_s,
@@ -161,32 +171,36 @@ nbs_status nbs_run_graph(nbs_plan plan, const void* const* prop_u, const void* c
 /* Measure launch-shape candidates on the device with the caller's
  * propagators and keep the fastest: for the block transforms, the fused x-y
  * pass over square planes, the register line kernel or LDS tiles of 512,
- * 1024, 2048 or 4096 elements; for the
- * contraction, with or without splitting a product's walked index over
- * lanes and (precision form) 256- or 512-thread workgroups and matrix-core
- * products on or off, then the ranges of sink-operator groups one
- * workgroup walks.  Synchronous;
- * leaves the plan as after nbs_build_blocks.  Results are unchanged up to
- * rounding order (the channel sums keep their order). */
+ * 1024, 2048 or 4096 elements; for the contraction, the matrix-core
+ * segment engine with 8 or 16 wavefronts per workgroup or the lane-team
+ * engine (8 wavefronts in FP64, 4 in the precision form), then the ranges
+ * of sink-operator groups one workgroup walks.  Synchronous; leaves the
+ * plan as after nbs_build_blocks.  Results are unchanged up to rounding
+ * order.  Callers that create the same shapes repeatedly can keep the
+ * result (nbs_plan_tuning) and set it with nbs_plan_set_tuning instead. */
 nbs_status nbs_plan_autotune(nbs_plan plan, const void* const* prop_u, const void* const* prop_d,
                              const void* const* prop_s, void* stream);
 
 /* The plan's launch shapes: out[0] bit 0 register line FFT on/off, bit 1
  * fused x-y pass for square planes on/off; out[1] LDS FFT tile elements;
- * out[2] wavefronts per contraction workgroup; out[3] bit 0 index splitting
- * on/off, bit 1 (precision form) 4 x 4-row products on matrix cores on/off,
- * bits 2-3 the contraction workgroups per (slice, momentum): 0 one that
- * walks every sink-operator group, keeping an operator block in LDS while
- * consecutive groups share it; 1 one per run of groups in which one block
- * stays; 2 one per group. */
+ * out[2] wavefronts per contraction workgroup of the selected engine;
+ * out[3] bit 4 the contraction engine (1: matrix-core segments, the
+ * default in both forms; 0: lane teams), bits 2-3 the contraction
+ * workgroups per (slice, momentum): 0 one that walks every sink-operator
+ * group, keeping an operator block in LDS while consecutive groups share
+ * it; 1 one per run of groups in which one block stays; 2 one per group;
+ * bits 0 and 1 apply to the lane-team engine only: bit 0 splitting a
+ * product's walked index over lanes on/off, bit 1 (precision form) its
+ * 4 x 4-row products on matrix cores on/off. */
 nbs_status nbs_plan_tuning(const nbs_plan plan, int32_t out[4]);
 
 /* Set the launch shapes (same encoding as nbs_plan_tuning) instead of
  * measuring them: waits for the plan's device work, recompiles the channel
  * program for the new shapes; blocks already built stay valid.  Rejects
- * unknown tiles, wavefront counts other than 8 (FP64) or 4 / 8 (precision
- * form), matrix-core products outside the precision form and group-range
- * modes above 2. */
+ * (NBS_ERR_INVALID, the plan unchanged) unknown tiles, bits above bit 4 of
+ * in[3], wavefront counts other than 8 / 16 (segment engine) or 8 (lane
+ * teams, FP64) or 4 / 8 (lane teams, precision form), matrix-core lane-team
+ * products outside the precision form and group-range modes above 2. */
 nbs_status nbs_plan_set_tuning(nbs_plan plan, const int32_t in[4]);
 
 /* Whether the propagators of the plan's last nbs_build_blocks (or
@@ -238,7 +252,7 @@ nbs_status nbs_plan_diagrams(const nbs_plan plan, int32_t ch, nbs_diagram_t* out
                              int32_t cap, int32_t* n);
 
 /* Copy one table of the compiled structure-of-arrays program (the tables
- * the kernels interpret; Sec. 3(ii)-(iii) ship such tables to the device)
+ * the kernels interpret; Sec. 4(ii)-(iii) ship such tables to the device)
  * into buf.  int32 tables: "op_code", "op_nterm", "op_term_trip",
  * "op_term_perm", "group_op1", "group_op2", "group_prod", "group_task",
  * "group_ch", "group_channels", "ch_contrib", "contrib_prod", "prod_desc",

@@ -1,7 +1,7 @@
 """Channel tables (data): operator names and the 52-channel reading R52.
 
 The paper computes 52 octet two-baryon channels but only cites the
-companion paper's Tables 1-4 for the list (Sec. 3(iii)).  R52 is a reading:
+companion paper's Tables 1-4 for the list (Sec. 4(iii)).  R52 is a reading:
 particle-basis operators, isospin-symmetric coupled sectors at I_z = I, and
 u<->d-independent representatives of the S = -2, I_z = 0 block.  A corrected
 list drops in here without code changes.

@@ -564,8 +564,10 @@ std::string compile_channels(const std::vector<ChannelSpec>& chans, const Compil
 
   // ---- 1b. the isospin-symmetric limit: with S_d = S_u a block depends on
   // its recipe with d read as u; slots whose recipes agree up to a common
-  // factor are one block (n = -p, Sigma- = Sigma+, Xi- = -Xi0).  Canonical
-  // slots are moved to the front.
+  // factor and that are stored antisymmetrised in the same slot pair are one
+  // block (Sigma- = Sigma+, Xi- = -Xi0; n equals -p as a plain block, but
+  // the two are antisymmetrised in different slot pairs, so n keeps its own
+  // block).  Canonical slots are moved to the front.
   {
     const int n = P.n_ops;
     std::vector<int> alias(n);

@@ -2,14 +2,14 @@
 // to the structure-of-arrays program the contraction kernel interprets.
 //
 // The paper does the "symbolical manipulations" and "diagrammatical
-// classification" on the CPU and ships SoA data to the device (Sec. 3(ii),
+// classification" on the CPU and ships SoA data to the device (Sec. 4(ii),
 // 3(iii)).  Here that step turns each channel into diagrams d (a split of the
 // six source quarks between the two sink baryons), each diagram into a pair
 // of effective blocks E1^(d)(q), E2^(d)(-q) (Eq. (9)) that absorb every
 // same-flavour reordering of the quarks inside a block, and the channel into
 // sum_d sigma_d sum_{xi~_d} E1 E2 (Eq. (10)).
 //
-// Blocks are built per sink *operator* (Sec. 3(i): the Lambda and Sigma0
+// Blocks are built per sink *operator* (Sec. 4(i): the Lambda and Sigma0
 // blocks are combinations of the X_u, X_d, X_s blocks), so every effective
 // block reads one operator block.  The device program is coarse: per block
 // product a fixed-size descriptor, per wavefront a 64-lane work list; the
@@ -154,7 +154,7 @@ struct Program {
   std::vector<int> op_term_perm;    // [slot * 3 + k] pi(0) | pi(1) << 2 | pi(2) << 4
   std::vector<double> op_term_w;    // [slot * 3 + k]
   std::vector<int> op_pair;         // [slot] s1 | s2 << 2 of the antisymmetrised slot pair, or -1
-  // Isospin-symmetric limit (S_d = S_u, Sec. 3(i)): slot s equals
+  // Isospin-symmetric limit (S_d = S_u, Sec. 4(i)): slot s equals
   // op_alias_coef[s] times slot op_alias[s]; the n_canon canonical slots
   // come first and are the only ones built in that limit.
   std::vector<int> op_alias;

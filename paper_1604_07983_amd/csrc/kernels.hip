@@ -1,10 +1,10 @@
 // kernels.hip -- HIP kernels for gfx950 (MI355X) of the NBS four-point function.
 //
-//   k_nbb       normal baryon blocks, Eq. (5) / Sec. 3(i) Eq. (8)
+//   k_nbb       normal baryon blocks, Eq. (5) / Sec. 4(i) Eq. (8)
 //   k_fft_line  one axis of the in-house batched 3-D FFT (Eq. (6)), one line
 //               per thread in registers
 //   k_fft_pass  the same through LDS tiles, for the lengths k_fft_line lacks
-//   k_contract  effective blocks and their products, Sec. 3(ii)-(iii),
+//   k_contract  effective blocks and their products, Sec. 4(ii)-(iii),
 //               Eqs. (9)-(10), driven by the compiled SoA program
 //   k_absmax / k_scale_exps / k_channel_scale   per-slice power-of-two
 //               scale of the precision form and its exact undo
@@ -89,7 +89,7 @@ __global__ void k_channel_scale(const int* exps, const int* chan_nf, double* osc
 //   N_op[al][j0][j1][j2] = sum_k w_k sum_c D_k[c][i0][i1] S_{f3,k}[(al,c)][i2],
 //   (i0, i1, i2) = (j_pi(0), j_pi(1), j_pi(2)),
 // (the Lambda and Sigma0 blocks as combinations of the X_u, X_d, X_s blocks,
-// Sec. 3(i)) is written as 3456 contiguous complex values.
+// Sec. 4(i)) is written as 3456 contiguous complex values.
 // ---------------------------------------------------------------------------
 template <typename Tin, typename T>
 __global__ __launch_bounds__(kThreads) void k_nbb(NbbArgs a) {
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_plane(FftPlaneArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Effective blocks and their products (Sec. 3(ii)-(iii), Eqs. (9)-(10)).
+// Effective blocks and their products (Sec. 4(ii)-(iii), Eqs. (9)-(10)).
 //
 // One workgroup per (sink-operator group, momentum q, slice) stages the two
 // operator blocks N~_op1(q) and N~_op2(-q) in LDS, then every wavefront works

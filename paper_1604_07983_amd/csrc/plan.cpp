@@ -368,7 +368,7 @@ nbs_status enqueue_build(nbs_plan p, const void* const* pu, const void* const* p
                          hipStream_t st) {
   nbs_status s;
   // in the isospin-symmetric limit only the canonical operator blocks (the
-  // first n_canon slots) are built and transformed (Sec. 3(i))
+  // first n_canon slots) are built and transformed (Sec. 4(i))
   p->iso = isospin_limit(p, pu, pd);
   const int n_build = p->iso ? p->comp.prog.n_canon : p->comp.prog.n_ops;
   // the non-finite input flag of this build (a fill kernel, not a memset,

@@ -65,7 +65,8 @@ def test_two_point_matches_oracle(prec):
 
 @pytest.mark.parametrize("prec", [binding.NBS_FP64, binding.NBS_FP32_MFMA])
 def test_two_point_isospin_limit(prec):
-    """u and d as the same memory: n, Sigma-, Xi- come from their aliases;
+    """u and d as the same memory: Sigma-, Xi- come from their aliases, n
+    from its own block (equal to p's two-point function in this limit);
     Lambda and Sigma0 do not mix."""
     announce("two-point isospin limit, prec %d" % prec)
     L = (4, 4, 2)
