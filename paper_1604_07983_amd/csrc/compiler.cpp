@@ -809,6 +809,8 @@ std::string compile_channels(const std::vector<ChannelSpec>& chans, const Compil
           const int lbl = (s1.lbl3 ? 1 : 0) | (s1.lbl4 ? 2 : 0);
           P.contrib_prod.push_back(local[p] | (s1.rows() << 16) | (lbl << 20));
           P.contrib_coef.push_back(it->second);
+          const size_t pe = (size_t)P.group_prod.back() + (size_t)local[p];
+          P.contrib_ext.push_back(pe < P.prod_ext.size() ? P.prod_ext[pe] : 0);
         }
         P.ch_contrib.push_back((int)P.contrib_prod.size());
       }

@@ -141,7 +141,9 @@ int product_class(int K, int rows1, int lone1, int lone2, int nm1, int nm2);
 // For kSegC1 the three units are those of the baryon's quarks 2, 0, 1.
 // The first segment of product p writes result slot p; further segments
 // take slots from the number of products on, and prod_ext[p] = first extra
-// slot | count << 16 lists them for the sum that precedes the channel sums.
+// slot | count << 16 lists them; contrib_ext[c] repeats the word of
+// contribution c's product, so that each channel sum adds a product's
+// segments itself.
 // (the shape codes kSegC144 .. kSegIdle are defined in kernels.hpp)
 
 struct Program {
@@ -182,6 +184,7 @@ struct Program {
   std::vector<int> seg_task;      // [task][team][kSegInts]
   std::vector<int> group_stask;   // n_groups + 1
   std::vector<int> prod_ext;      // per product (global index)
+  std::vector<int> contrib_ext;   // per contribution: prod_ext of its product
   int max_group_slots = 0;        // result slots (products + extra segments)
   int max_group_stasks = 0;
   int max_group_products = 0;

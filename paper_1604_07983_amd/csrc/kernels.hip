@@ -1698,11 +1698,15 @@ __device__ __forceinline__ void seg_run(const int* d, const cx<T>* S1, const cx<
   }
 }
 
+// LDS of the segment contraction: the two blocks, the result slots, one set
+// of task descriptors, two sets of channel tables (coefficients, product
+// words, segment words, channel offsets: the group being summed and the
+// next one) and the task counter.
 size_t contract_seg_lds_bytes(int prec, int max_gslots, int max_gcontrib, int max_gch, int max_gstask) {
   const size_t el = prec == 0 ? sizeof(cd) : sizeof(cf);
   const size_t real = prec == 0 ? sizeof(double) : sizeof(float);
-  return el * (2 * (size_t)kLdsBlock + (size_t)max_gslots * 16) + real * max_gcontrib +
-         sizeof(int) * ((size_t)max_gstask * kSegTeams * kSegInts + max_gcontrib + max_gch + 1 + 1);
+  return el * (2 * (size_t)kLdsBlock + (size_t)max_gslots * 16) + 2 * real * max_gcontrib +
+         sizeof(int) * ((size_t)max_gstask * kSegTeams * kSegInts + 2 * (2 * (size_t)max_gcontrib + max_gch + 1) + 1);
 }
 
 // One operator block moved from HBM to LDS in chunks of four consecutive
@@ -1744,6 +1748,67 @@ template <typename T, int NT> struct BlockRegs {
   }
 };
 
+// One group's tables (task descriptors, channel contributions) read into
+// registers while the previous group computes, written to LDS when it is
+// done with them.  Descriptor ints beyond kTd per thread and contributions
+// beyond one per thread are copied straight from global memory.  In the
+// precision form (two workgroups per CU, no registers to spare) everything
+// is copied at the store: the other workgroup hides that latency.
+template <typename T, int NT> struct GroupTables {
+  static constexpr bool kRegs = sizeof(T) == 8;
+  static constexpr int kTd = kRegs ? (NT >= 1024 ? 2 : 3) : 1;
+  int td[kTd];
+  int cw = 0, ce = 0, co = 0;
+  T cc = 0;
+  long long tb = 0, cbase = 0;
+  int ntd = 0, ncon = 0, nch = 0, gc0 = 0;
+  __device__ __forceinline__ void load(const ContractArgs& a, int g, int tid) {
+    gc0 = a.group_ch[g];
+    nch = a.group_ch[g + 1] - gc0;
+    cbase = a.ch_contrib[gc0];
+    ncon = (int)(a.ch_contrib[gc0 + nch] - cbase);
+    tb = (long long)a.group_stask[g] * (kSegTeams * kSegInts);
+    ntd = (a.group_stask[g + 1] - a.group_stask[g]) * (kSegTeams * kSegInts);
+    if constexpr (kRegs) {
+#pragma unroll
+      for (int k = 0; k < kTd; ++k) {
+        const int i = tid + k * NT;
+        td[k] = i < ntd ? a.seg_task[tb + i] : 0;
+      }
+      if (tid < ncon) {
+        cw = a.contrib_prod[cbase + tid];
+        ce = a.contrib_ext[cbase + tid];
+        cc = (T)a.contrib_coef[cbase + tid];
+      }
+      if (tid <= nch) co = (int)(a.ch_contrib[gc0 + tid] - cbase);
+    }
+  }
+  __device__ __forceinline__ void store(const ContractArgs& a, int* tdesc, int* cword, int* cext, T* ccoef, int* coff,
+                                        int tid) const {
+    const int nr = kRegs ? NT : 0;
+    if constexpr (kRegs) {
+#pragma unroll
+      for (int k = 0; k < kTd; ++k) {
+        const int i = tid + k * NT;
+        if (i < ntd) tdesc[i] = td[k];
+      }
+      if (tid < ncon) {
+        cword[tid] = cw;
+        cext[tid] = ce;
+        ccoef[tid] = cc;
+      }
+      if (tid <= nch) coff[tid] = co;
+    }
+    for (int i = (kRegs ? kTd * NT : 0) + tid; i < ntd; i += NT) tdesc[i] = a.seg_task[tb + i];
+    for (int i = nr + tid; i < ncon; i += NT) {
+      cword[i] = a.contrib_prod[cbase + i];
+      cext[i] = a.contrib_ext[cbase + i];
+      ccoef[i] = (T)a.contrib_coef[cbase + i];
+    }
+    for (int i = nr + tid; i <= nch; i += NT) coff[i] = (int)(a.ch_contrib[gc0 + i] - cbase);
+  }
+};
+
 template <typename T, int NT> __device__ __forceinline__ void contract_seg_body(const ContractArgs& a) {
   extern __shared__ __align__(16) char smem_raw[];
   const long long nb8 = (a.n_chunk + 7) / 8 * 8;
@@ -1761,46 +1826,38 @@ template <typename T, int NT> __device__ __forceinline__ void contract_seg_body(
   cx<T>* const slotA = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* const slotB = slotA + kLdsBlock;
   cx<T>* const R = slotB + kLdsBlock;
+  // channel tables in two sets [2][...]: the group being summed, the next
   T* const ccoef = reinterpret_cast<T*>(R + a.max_gslots * 16);
-  int* const tdesc = reinterpret_cast<int*>(ccoef + a.max_gcontrib);
+  int* const tdesc = reinterpret_cast<int*>(ccoef + 2 * a.max_gcontrib);
   int* const cword = tdesc + a.max_gstask * (kSegTeams * kSegInts);
-  int* const coff = cword + a.max_gcontrib;
-  int* const counter = coff + a.max_gch + 1;
+  int* const cext = cword + 2 * a.max_gcontrib;
+  int* const coff = cext + 2 * a.max_gcontrib;
+  int* const counter = coff + 2 * (a.max_gch + 1);
   const int tid = threadIdx.x, lane = tid & 63;
   const cx<T>* Nq = reinterpret_cast<const cx<T>*>(G.Nq);
   const int gbeg = a.gchunk[chunk], gend = a.gchunk[chunk + 1];
   auto block_src = [&](int op, int qq) {
     return Nq + ((long long)(op * G.t_count + t) * G.V + qq) * kBlockEntries;
   };
-  // the first group's two blocks
+  // the first group's blocks and tables
   {
     BlockRegs<T, NT> ra, rb;
+    GroupTables<T, NT> tg;
     ra.load(block_src(a.group_op1[gbeg], q), tid);
     rb.load(block_src(a.group_op2[gbeg], mq), tid);
+    tg.load(a, gbeg, tid);
     ra.store(slotA, tid);
     rb.store(slotB, tid);
-  }
-  for (int g = gbeg; g < gend; ++g) {
-    // the group's channel contributions
-    const int gc0 = a.group_ch[g], nch = a.group_ch[g + 1] - gc0;
-    const int cbase = a.ch_contrib[gc0], ncon = a.ch_contrib[gc0 + nch] - cbase;
-    for (int i = tid; i < ncon; i += NT) {
-      cword[i] = a.contrib_prod[cbase + i];
-      ccoef[i] = (T)a.contrib_coef[cbase + i];
-    }
-    if (tid <= nch) coff[tid] = a.ch_contrib[gc0 + tid] - cbase;
+    tg.store(a, tdesc, cword, cext, ccoef, coff, tid);
     if (tid == 0) *counter = 0;
-    // the group's task descriptors: read from LDS during the products, so
-    // that no global load there waits behind the prefetch below
-    const int tb = a.group_stask[g], ntask = a.group_stask[g + 1] - tb;
-    for (int i = tid; i < ntask * (kSegTeams * kSegInts); i += NT)
-      tdesc[i] = a.seg_task[(long long)tb * (kSegTeams * kSegInts) + i];
-    __syncthreads();
-
+  }
+  __syncthreads();
+  for (int g = gbeg; g < gend; ++g) {
+    const int cur = (g - gbeg) & 1, nxt = cur ^ 1;
     // the next group's changed block (the walk changes one operator at a
-    // time where it can) is loaded into registers now and written to LDS
-    // after this group's last LDS read, so its HBM latency overlaps the
-    // products
+    // time where it can) and its tables go into registers now and into LDS
+    // once this group's products are done, so that their latency overlaps
+    // the products
     const bool more = g + 1 < gend;
     const bool nA = more && a.group_op1[g + 1] != a.group_op1[g];
     const bool nB = more && a.group_op2[g + 1] != a.group_op2[g];
@@ -1809,8 +1866,12 @@ template <typename T, int NT> __device__ __forceinline__ void contract_seg_body(
       pf.load(block_src(a.group_op1[g + 1], q), tid);
     else if (nB)
       pf.load(block_src(a.group_op2[g + 1], mq), tid);
+    using Tables = GroupTables<T, NT>;
+    Tables tn;
+    if (Tables::kRegs && more) tn.load(a, g + 1, tid);
 
     // products: wavefronts claim tasks (longest first) from the counter
+    const int ntask = a.group_stask[g + 1] - a.group_stask[g];
     for (;;) {
       int claim = 0;
       if (lane == 0) claim = atomicAdd(counter, 1);
@@ -1828,57 +1889,54 @@ template <typename T, int NT> __device__ __forceinline__ void contract_seg_body(
       for (int k = 0; k < kSegInts; ++k) d[k] = dt[tm * kSegInts + k];
       seg_run<T>(d, slotA, slotB, R, shape, nsteps, lane);
     }
-    __syncthreads();
+    __syncthreads();  // results complete; blocks, descriptors, counter free
 
-    // segments of one product: sum into the product's first slot
-    const int pbase = a.group_prod[g], nprod = a.group_prod[g + 1] - pbase;
-    for (int i = tid; i < nprod * 16; i += NT) {
-      const int p = i >> 4, o = i & 15;
-      const int ext = a.prod_ext[pbase + p];
-      const int ne = ext >> 16, e0 = ext & 0xffff;
-      if (ne > 0) {
-        cx<T> v = R[p * 16 + o];
-        for (int e = 0; e < ne; ++e) v += R[(e0 + e) * 16 + o];
-        R[p * 16 + o] = v;
-      }
-    }
-    __syncthreads();
-
-    // channel sums: 8 lanes per output (spin s of local channel cl)
-    cx<T>* Ft = reinterpret_cast<cx<T>*>(G.Ft);
-    for (int i0 = 0; i0 < nch * 16 * 8; i0 += NT) {
-      const int i = i0 + tid;
-      const int o = i >> 3, sub = i & 7;
-      const int cl = o >> 4, s = o & 15;
-      cx<T> v{0, 0};
-      if (cl < nch) {
-        const int a1 = (s >> 3) & 1, a2 = (s >> 2) & 1, a3 = (s >> 1) & 1, a4 = s & 1;
-        for (int c = coff[cl] + sub; c < coff[cl + 1]; c += 8) {
-          const int w = cword[c];
-          const int p = w & 0xffff, rows2 = 16 / ((w >> 16) & 15);
-          const bool l3 = (w >> 20) & 1, l4 = (w >> 21) & 1;
-          const int r1 = (a1 * (l3 ? 2 : 1) + (l3 ? a3 : 0)) * (l4 ? 2 : 1) + (l4 ? a4 : 0);
-          const int r2 = (a2 * (l3 ? 1 : 2) + (l3 ? 0 : a3)) * (l4 ? 1 : 2) + (l4 ? 0 : a4);
-          const T cf = ccoef[c];
-          const cx<T> xv = R[p * 16 + r1 * rows2 + r2];
-          v.re = fma(cf, xv.re, v.re);
-          v.im = fma(cf, xv.im, v.im);
+    // channel sums: 8 lanes per output (spin s of local channel cl); each
+    // contribution adds its product's result slot and extra segment slots
+    {
+      const int* cw_ = cword + cur * a.max_gcontrib;
+      const int* ce_ = cext + cur * a.max_gcontrib;
+      const T* cc_ = ccoef + cur * a.max_gcontrib;
+      const int* co_ = coff + cur * (a.max_gch + 1);
+      const int gc0 = a.group_ch[g], nch = a.group_ch[g + 1] - gc0;
+      cx<T>* Ft = reinterpret_cast<cx<T>*>(G.Ft);
+      for (int i0 = 0; i0 < nch * 16 * 8; i0 += NT) {
+        const int i = i0 + tid;
+        const int o = i >> 3, sub = i & 7;
+        const int cl = o >> 4, s = o & 15;
+        cx<T> v{0, 0};
+        if (cl < nch) {
+          const int a1 = (s >> 3) & 1, a2 = (s >> 2) & 1, a3 = (s >> 1) & 1, a4 = s & 1;
+          for (int c = co_[cl] + sub; c < co_[cl + 1]; c += 8) {
+            const int w = cw_[c];
+            const int p = w & 0xffff, rows2 = 16 / ((w >> 16) & 15);
+            const bool l3 = (w >> 20) & 1, l4 = (w >> 21) & 1;
+            const int r1 = (a1 * (l3 ? 2 : 1) + (l3 ? a3 : 0)) * (l4 ? 2 : 1) + (l4 ? a4 : 0);
+            const int r2 = (a2 * (l3 ? 1 : 2) + (l3 ? 0 : a3)) * (l4 ? 1 : 2) + (l4 ? 0 : a4);
+            const int e = ce_[c], ne = e >> 16, e0 = e & 0xffff, ro = r1 * rows2 + r2;
+            cx<T> xv = R[p * 16 + ro];
+            for (int k = 0; k < ne; ++k) xv += R[(e0 + k) * 16 + ro];
+            const T cf = cc_[c];
+            v.re = fma(cf, xv.re, v.re);
+            v.im = fma(cf, xv.im, v.im);
+          }
+        }
+        // sum of the 8 lanes of the output: DPP moves within each 8-lane
+        // half row (partners lane ^ 1, lane ^ 2, then the mirrored quad)
+        v.re += dpp_move<kDppQuadSwap>(v.re);
+        v.im += dpp_move<kDppQuadSwap>(v.im);
+        v.re += dpp_move<kDppQuadSwap2>(v.re);
+        v.im += dpp_move<kDppQuadSwap2>(v.im);
+        v.re += dpp_move<kDppRowHalfMirror>(v.re);
+        v.im += dpp_move<kDppRowHalfMirror>(v.im);
+        if (cl < nch && sub == 0) {
+          const int ch = a.group_channels[gc0 + cl];
+          Ft[(((long long)ch * G.t_count + t) * 16 + s) * G.V + q] = v;
         }
       }
-      // sum of the 8 lanes of the output: DPP moves within each 8-lane
-      // half row (partners lane ^ 1, lane ^ 2, then the mirrored quad)
-      v.re += dpp_move<kDppQuadSwap>(v.re);
-      v.im += dpp_move<kDppQuadSwap>(v.im);
-      v.re += dpp_move<kDppQuadSwap2>(v.re);
-      v.im += dpp_move<kDppQuadSwap2>(v.im);
-      v.re += dpp_move<kDppRowHalfMirror>(v.re);
-      v.im += dpp_move<kDppRowHalfMirror>(v.im);
-      if (cl < nch && sub == 0) {
-        const int ch = a.group_channels[gc0 + cl];
-        Ft[(((long long)ch * G.t_count + t) * 16 + s) * G.V + q] = v;
-      }
     }
-    __syncthreads();  // every LDS read of this group is done
+    // the next group's block and tables (the channel sums read neither the
+    // blocks, nor the descriptors, nor the other table set)
     if (nA) {
       pf.store(slotA, tid);
       if (nB) {
@@ -1889,6 +1947,13 @@ template <typename T, int NT> __device__ __forceinline__ void contract_seg_body(
     } else if (nB) {
       pf.store(slotB, tid);
     }
+    if (more) {
+      if (!Tables::kRegs) tn.load(a, g + 1, tid);
+      tn.store(a, tdesc, cword + nxt * a.max_gcontrib, cext + nxt * a.max_gcontrib, ccoef + nxt * a.max_gcontrib,
+               coff + nxt * (a.max_gch + 1), tid);
+    }
+    if (tid == 0) *counter = 0;
+    __syncthreads();
   }
 }
 

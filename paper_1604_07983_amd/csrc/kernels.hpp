@@ -105,7 +105,7 @@ struct ContractArgs {
   // matrix-core contraction (engine 1): segment tasks per group, extra
   // result slots per product, result slots per group
   int engine;
-  const int *seg_task, *group_stask, *prod_ext;
+  const int *seg_task, *group_stask, *prod_ext, *contrib_ext;
   int max_gslots, max_gstask;
   long long block0, n_chunk;  // logical workgroups [block0, block0 + n_chunk) in this launch
 };

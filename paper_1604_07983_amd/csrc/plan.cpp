@@ -288,6 +288,7 @@ nbs_status compile_and_upload(nbs_plan p) {
   put("task_lanes", P.task_lanes);
   put("group_op1_iso", P.group_op1_iso); put("group_op2_iso", P.group_op2_iso);
   put("seg_task", P.seg_task); put("group_stask", P.group_stask); put("prod_ext", P.prod_ext);
+  put("contrib_ext", P.contrib_ext);
   const std::vector<int> gchunk = group_chunks(P.group_op1, P.group_op2, p->tune.gchunk);
   put("gchunk", gchunk);
   int countdown = 0;
@@ -343,6 +344,7 @@ nbs_status compile_and_upload(nbs_plan p) {
   c.seg_task = T("seg_task");
   c.group_stask = T("group_stask");
   c.prod_ext = T("prod_ext");
+  c.contrib_ext = T("contrib_ext");
   c.max_gslots = std::max(1, P.max_group_slots);
   c.max_gstask = std::max(1, P.max_group_stasks);
   c.waves = c.engine == 1 ? p->tune.seg_waves : p->tune.waves;
@@ -1069,7 +1071,7 @@ nbs_status nbs_plan_table(const nbs_plan p, const char* name, void* buf, int64_t
       {"group_channels", &P.group_channels}, {"ch_contrib", &P.ch_contrib}, {"contrib_prod", &P.contrib_prod},
       {"prod_desc", &P.prod_desc}, {"task_lanes", &P.task_lanes}, {"op_alias", &P.op_alias},
       {"group_op1_iso", &P.group_op1_iso}, {"group_op2_iso", &P.group_op2_iso}, {"op_pair", &P.op_pair},
-      {"seg_task", &P.seg_task}, {"group_stask", &P.group_stask}, {"prod_ext", &P.prod_ext}};
+      {"seg_task", &P.seg_task}, {"group_stask", &P.group_stask}, {"prod_ext", &P.prod_ext}, {"contrib_ext", &P.contrib_ext}};
   auto it = tabs.find(nm);
   if (it == tabs.end()) return NBS_ERR_INVALID;
   *n = (int64_t)it->second->size();

@@ -321,7 +321,7 @@ def quad_team_reduce(vals, lg):
 
 
 # ---- the matrix-core contraction's segment program ---------------------------
-SEG_NAMES = ("seg_task", "group_stask", "prod_ext")
+SEG_NAMES = ("seg_task", "group_stask", "prod_ext", "contrib_ext")
 SEG_INTS, SEG_TEAMS = 16, 4
 SEG_C144, SEG_C9, SEG_C36, SEG_C1, SEG_IDLE = 0, 1, 2, 3, 15
 LDS_AL, LDS_BLOCK = 1892, 2 * 1892
@@ -435,8 +435,9 @@ def seg_run(d, S1, S2, shape, nsteps):
 
 def emulate_q_seg(T, Nq_plus, Nq_minus, n_ch, check_slots=True):
     """F~(q) [n_ch, 16] from the segment program of the matrix-core
-    contraction, following its kernel: segments into result slots, extra
-    slots summed into the product's first, channel sums."""
+    contraction, following its kernel: segments into result slots, then
+    channel sums in which each contribution adds its product's segment
+    slots (contrib_ext)."""
     out = np.zeros((n_ch, 16), dtype=np.complex128)
     tasks = T["seg_task"].reshape(-1, SEG_TEAMS, SEG_INTS)
     n_groups = len(T["group_prod"]) - 1
@@ -457,12 +458,14 @@ def emulate_q_seg(T, Nq_plus, Nq_minus, n_ch, check_slots=True):
                 assert slot not in R, "result slot written twice"
                 R[slot] = r
         np_ = pe - pb
+        # every slot written: a product's first segment at slot p, the
+        # others at the extra slots prod_ext lists
+        want = set(range(np_))
         for p in range(np_):
             ext = int(T["prod_ext"][pb + p])
-            for e in range(ext >> 16):
-                R[p] = R[p] + R.pop((ext & 0xFFFF) + e)
+            want.update((ext & 0xFFFF) + e for e in range(ext >> 16))
         if check_slots:
-            assert sorted(R) == list(range(np_)), "result slots do not match the products"
+            assert sorted(R) == sorted(want), "result slots do not match the products' segments"
         c0 = T["group_ch"][g]
         for cl in range(T["group_ch"][g + 1] - c0):
             ch = T["group_channels"][c0 + cl]
@@ -477,6 +480,13 @@ def emulate_q_seg(T, Nq_plus, Nq_minus, n_ch, check_slots=True):
                     rows2 = 16 // rows1
                     r1 = (a1 * (2 if l3 else 1) + (a3 if l3 else 0)) * (2 if l4 else 1) + (a4 if l4 else 0)
                     r2 = (a2 * (1 if l3 else 2) + (0 if l3 else a3)) * (1 if l4 else 2) + (0 if l4 else a4)
-                    v += T["contrib_coef"][c] * R[p][r1 * rows2 + r2]
+                    # the product's value: its first segment, then its
+                    # extra segments in order (the kernel's summation order)
+                    ext = int(T["contrib_ext"][c])
+                    assert ext == int(T["prod_ext"][pb + p]), "contrib_ext differs from the product's prod_ext"
+                    xv = R[p][r1 * rows2 + r2]
+                    for e in range(ext >> 16):
+                        xv = xv + R[(ext & 0xFFFF) + e][r1 * rows2 + r2]
+                    v += T["contrib_coef"][c] * xv
                 out[ch, s] = v
     return out
