@@ -3,6 +3,7 @@
 #include "kernels.hpp"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <map>
 #include <set>
@@ -323,6 +324,159 @@ double seg_step_cost(int shape) {
 }
 constexpr double kSegOverhead = 8.0;
 
+// LDS entries a segment's team reads, per read instruction of the kernel's
+// step loop (the 4 x 4 and 8 x 2 shapes): 16 lanes in (slot h, row x)
+// order, -1 where the lane is inactive.  The same index arithmetic as the
+// kernel's step loop.
+void seg_read_addrs(const std::vector<int>& d, std::vector<std::array<int, 16>>& out) {
+  out.clear();
+  const int shape = d[0], s0 = d[1], n = d[2];
+  const bool tr = (d[3] >> 17) & 1;
+  const int SA = tr ? nbs::kLdsBlock : 0, SB = tr ? 0 : nbs::kLdsBlock;
+  const int* wa = &d[7];
+  const int* wb = &d[13];
+  auto row = [](int r, const int* w) { return (r & 1) * w[0] + ((r >> 1) & 1) * w[1] + ((r >> 2) & 1) * w[2]; };
+  auto pair2 = [](int v, int up, int uq, int& o0, int& o1) {
+    const int sp = v / 3, c = v % 3, c1 = (c + 1) % 3, c2 = (c + 2) % 3, jp = 3 * (sp ^ 1);
+    const int a = (jp + c1) * up + c2 * uq, b = (jp + c2) * up + c1 * uq;
+    o0 = (sp & 1) ? b : a;
+    o1 = (sp & 1) ? a : b;
+  };
+  std::array<int, 16> A;
+  if (shape == kSegC144) {
+    for (int it = 0; it < n / 3; ++it) {
+      const int v1 = s0 / 3 + it;
+      int a0, a1;
+      pair2(v1, d[5], d[6], a0, a1);
+      for (int m = 0; m < 3; ++m)
+        for (int which = 0; which < 4; ++which) {
+          for (int h = 0; h < 4; ++h) {
+            int b0, b1;
+            pair2(4 * m + h, d[11], d[12], b0, b1);
+            for (int x = 0; x < 4; ++x)
+              A[4 * h + x] = which < 2 ? SA + row(x, wa) + h * d[4] + (which ? a1 : a0) + 4 * m * d[4]
+                                       : SB + row(x, wb) + v1 * d[10] + (which == 2 ? b0 : b1);
+          }
+          out.push_back(A);
+        }
+    }
+  } else if (shape == kSegC36) {
+    for (int it = 0; it < n / 3; ++it) {
+      const int v2 = s0 / 3 + it;
+      const int c1 = (v2 + 1) % 3, c2 = (v2 + 2) % 3;
+      const int o0 = c1 * d[11] + c2 * d[12], o1 = c2 * d[11] + c1 * d[12];
+      for (int m = 0; m < 3; ++m)
+        for (int which = 0; which < 12; ++which) {
+          for (int h = 0; h < 4; ++h) {
+            int p0, p1;
+            pair2(4 * m + h, d[5], d[6], p0, p1);
+            for (int x = 0; x < 4; ++x) {
+              int a;
+              if (which < 4) {
+                const int bA = (which < 2 ? row(x, wa) : row(x + 4, wa)) + v2 * d[4];
+                a = SA + bA + ((which & 1) ? p1 : p0);
+              } else if (x >= 2) {
+                a = -1;
+              } else {
+                const int sp = (which - 4) / 2;
+                const int so = 3 * sp * d[11] + 3 * (sp ^ 1) * d[12];
+                a = SB + row(x & 1, wb) + h * d[10] + 4 * m * d[10] + so + (((which - 4) & 1) ? o1 : o0);
+              }
+              A[4 * h + x] = a;
+            }
+          }
+          out.push_back(A);
+        }
+    }
+  }
+}
+
+// Extra LDS cycles of the teams' reads when they share a task: 64 banks of
+// four bytes; FP64 entries (16 bytes) are served 16 lanes per cycle, one
+// slot h of all four teams (lane 16 h + 4 tm + x); FP32 entries (8 bytes)
+// 32 lanes per cycle, two whole teams (lane 16 tm + 4 h + x).  A cycle
+// serves distinct entries in distinct bank sets; equal entries broadcast.
+long long seg_conflicts(const std::vector<const std::vector<std::array<int, 16>>*>& teams, bool fp32) {
+  long long extra = 0;
+  if (teams.empty()) return 0;
+  const size_t n = teams[0]->size();
+  const int mod = fp32 ? 32 : 16;
+  int cnt[32];
+  int seen[64];
+  auto cycle = [&](const int* addrs, int na) {
+    for (int b = 0; b < mod; ++b) cnt[b] = 0;
+    int ns = 0, mx = 0;
+    for (int i = 0; i < na; ++i) {
+      const int a = addrs[i];
+      if (a < 0) continue;
+      bool dup = false;
+      for (int j = 0; j < ns && !dup; ++j) dup = seen[j] == a;
+      if (dup) continue;
+      seen[ns++] = a;
+      mx = std::max(mx, ++cnt[a % mod]);
+    }
+    return mx > 1 ? mx - 1 : 0;
+  };
+  int buf[64];
+  for (size_t i = 0; i < n; ++i) {
+    if (!fp32) {
+      for (int h = 0; h < 4; ++h) {
+        int na = 0;
+        for (const auto* t : teams)
+          for (int x = 0; x < 4; ++x) buf[na++] = (*t)[i][4 * h + x];
+        extra += cycle(buf, na);
+      }
+    } else {
+      for (size_t g = 0; g < teams.size(); g += 2) {
+        int na = 0;
+        for (size_t k = g; k < std::min(teams.size(), g + 2); ++k)
+          for (int e = 0; e < 16; ++e) buf[na++] = (*teams[k])[i][e];
+        extra += cycle(buf, na);
+      }
+    }
+  }
+  return extra;
+}
+
+// Order the segments of one (shape, step count) so that consecutive fours
+// (the tasks) read LDS with few bank conflicts: greedily, each task (FP64)
+// or each pair of teams sharing a cycle (FP32) takes the segment that adds
+// the fewest extra cycles.
+void pack_segments(std::vector<std::vector<int>>& segs, bool fp32) {
+  const int shape = segs.empty() ? -1 : segs[0][0];
+  if (segs.size() <= 1 || (shape != kSegC144 && shape != kSegC36)) return;
+  std::vector<std::vector<std::array<int, 16>>> addrs(segs.size());
+  for (size_t i = 0; i < segs.size(); ++i) seg_read_addrs(segs[i], addrs[i]);
+  const size_t unit = fp32 ? 2 : kSegTeams;
+  std::vector<int> rem(segs.size());
+  for (size_t i = 0; i < rem.size(); ++i) rem[i] = (int)i;
+  std::vector<int> order;
+  while (!rem.empty()) {
+    std::vector<int> grp = {rem.front()};
+    rem.erase(rem.begin());
+    while (grp.size() < unit && !rem.empty()) {
+      long long best = -1;
+      size_t bi = 0;
+      for (size_t j = 0; j < rem.size(); ++j) {
+        std::vector<const std::vector<std::array<int, 16>>*> t;
+        for (int k : grp) t.push_back(&addrs[k]);
+        t.push_back(&addrs[rem[j]]);
+        const long long c = seg_conflicts(t, fp32);
+        if (best < 0 || c < best) {
+          best = c;
+          bi = j;
+        }
+      }
+      grp.push_back(rem[bi]);
+      rem.erase(rem.begin() + bi);
+    }
+    order.insert(order.end(), grp.begin(), grp.end());
+  }
+  std::vector<std::vector<int>> out;
+  for (int i : order) out.push_back(segs[i]);
+  segs = out;
+}
+
 struct SegPlan {
   std::vector<std::vector<int>> tasks;  // per task kSegTeams * kSegInts ints
   std::vector<int> ext;                 // per product
@@ -335,7 +489,7 @@ struct SegPlan {
 // segments of one shape and one step count four to a task, and balance the
 // tasks over `waves` wavefronts longest first.
 SegPlan plan_segments(const std::vector<std::vector<int>>& base, const std::vector<int>& steps, int l144, int l36,
-                      int waves) {
+                      int waves, bool fp32, bool pack) {
   SegPlan sp;
   const int np = (int)base.size();
   sp.ext.assign(np, 0);
@@ -361,6 +515,7 @@ SegPlan plan_segments(const std::vector<std::vector<int>>& base, const std::vect
   std::vector<double> cost;
   for (auto& kv : by_key) {
     auto& segs = kv.second;
+    if (pack) pack_segments(segs, fp32);
     for (size_t i = 0; i < segs.size(); i += kSegTeams) {
       std::vector<int> t(kSegTeams * kSegInts, 0);
       for (int k = 0; k < kSegTeams; ++k) {
@@ -737,17 +892,23 @@ std::string compile_channels(const std::vector<ChannelSpec>& chans, const Compil
         if (!ok) seg_error = "a block product has no matrix-core shape";
         SegPlan best;
         bool have = false;
+        int bl144 = 0, bl36 = 0;
         for (int l144 : {36, 18, 12, 9, 6, 3})
           for (int l36 : {9, 6, 3}) {
-            SegPlan sp = plan_segments(base, nsteps, l144, l36, opt.seg_waves);
+            SegPlan sp = plan_segments(base, nsteps, l144, l36, opt.seg_waves, opt.fp32, false);
             if (sp.slots > opt.max_group_slots) continue;
             if (!have || sp.makespan < best.makespan - 1e-9 ||
                 (std::fabs(sp.makespan - best.makespan) <= 1e-9 && sp.slots < best.slots)) {
               best = sp;
+              bl144 = l144;
+              bl36 = l36;
               have = true;
             }
           }
         if (!have) seg_error = "a channel group needs more result slots than the contraction holds";
+        // the chosen cut, its tasks composed against LDS bank conflicts
+        // (the same segments, slots and balance)
+        else best = plan_segments(base, nsteps, bl144, bl36, opt.seg_waves, opt.fp32, true);
         for (const auto& t : best.tasks) P.seg_task.insert(P.seg_task.end(), t.begin(), t.end());
         P.prod_ext.insert(P.prod_ext.end(), best.ext.begin(), best.ext.end());
         P.group_stask.push_back((int)(P.seg_task.size() / (kSegTeams * kSegInts)));

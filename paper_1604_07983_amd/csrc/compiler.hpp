@@ -200,6 +200,7 @@ struct CompileOptions {
   int max_group_slots = 160;    // result slots of the matrix-core contraction
   bool split = true;            // may split a product's walked index over lanes
   bool mfma = false;            // 4 x 4-row split products on matrix cores (precision form)
+  bool fp32 = false;            // precision form: the LDS bank model of 8-byte entries
 };
 
 struct Compiled {

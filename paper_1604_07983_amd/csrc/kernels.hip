@@ -1512,7 +1512,7 @@ template <typename T> __device__ __forceinline__ cx<T> cdiff(cx<T> u, cx<T> w) {
 // One segment of a team.  d: the team's descriptor; SA, SB: the staged
 // blocks of sides A and B; R: result slots (16 complex each).
 template <typename T>
-__device__ __forceinline__ void seg_run(const int* d, const cx<T>* S1, const cx<T>* S2, cx<T>* R, int shape,
+__device__ __forceinline__ void seg_run(const int* d, const cx<T>* S1, const cx<T>* S2, cx<T>* R, int rstride, int shape,
                                         int nsteps, int lane) {
   int tm, h, x;
   seg_roles<T>(lane, tm, h, x);
@@ -1651,7 +1651,7 @@ __device__ __forceinline__ void seg_run(const int* d, const cx<T>* S1, const cx<
     } else {
       idx = i * 4 + j;
     }
-    R[slot * 16 + idx] = cx<T>{sgn * re, sgn * im};
+    R[slot * rstride + idx] = cx<T>{sgn * re, sgn * im};
   };
   if constexpr (sizeof(T) == 8) {
     if (live) {
@@ -1702,10 +1702,10 @@ __device__ __forceinline__ void seg_run(const int* d, const cx<T>* S1, const cx<
 // of task descriptors, two sets of channel tables (coefficients, product
 // words, segment words, channel offsets: the group being summed and the
 // next one) and the task counter.
-size_t contract_seg_lds_bytes(int prec, int max_gslots, int max_gcontrib, int max_gch, int max_gstask) {
+size_t contract_seg_lds_bytes(int prec, int max_gslots, int max_gcontrib, int max_gch, int max_gstask, int rstride) {
   const size_t el = prec == 0 ? sizeof(cd) : sizeof(cf);
   const size_t real = prec == 0 ? sizeof(double) : sizeof(float);
-  return el * (2 * (size_t)kLdsBlock + (size_t)max_gslots * 16) + 2 * real * max_gcontrib +
+  return el * (2 * (size_t)kLdsBlock + (size_t)max_gslots * rstride) + 2 * real * max_gcontrib +
          sizeof(int) * ((size_t)max_gstask * kSegTeams * kSegInts + 2 * (2 * (size_t)max_gcontrib + max_gch + 1) + 1);
 }
 
@@ -1827,7 +1827,8 @@ template <typename T, int NT> __device__ __forceinline__ void contract_seg_body(
   cx<T>* const slotB = slotA + kLdsBlock;
   cx<T>* const R = slotB + kLdsBlock;
   // channel tables in two sets [2][...]: the group being summed, the next
-  T* const ccoef = reinterpret_cast<T*>(R + a.max_gslots * 16);
+  const int rstride = a.rstride;
+  T* const ccoef = reinterpret_cast<T*>(R + a.max_gslots * rstride);
   int* const tdesc = reinterpret_cast<int*>(ccoef + 2 * a.max_gcontrib);
   int* const cword = tdesc + a.max_gstask * (kSegTeams * kSegInts);
   int* const cext = cword + 2 * a.max_gcontrib;
@@ -1887,7 +1888,7 @@ template <typename T, int NT> __device__ __forceinline__ void contract_seg_body(
       int d[kSegInts];
 #pragma unroll
       for (int k = 0; k < kSegInts; ++k) d[k] = dt[tm * kSegInts + k];
-      seg_run<T>(d, slotA, slotB, R, shape, nsteps, lane);
+      seg_run<T>(d, slotA, slotB, R, rstride, shape, nsteps, lane);
     }
     __syncthreads();  // results complete; blocks, descriptors, counter free
 
@@ -1914,8 +1915,8 @@ template <typename T, int NT> __device__ __forceinline__ void contract_seg_body(
             const int r1 = (a1 * (l3 ? 2 : 1) + (l3 ? a3 : 0)) * (l4 ? 2 : 1) + (l4 ? a4 : 0);
             const int r2 = (a2 * (l3 ? 1 : 2) + (l3 ? 0 : a3)) * (l4 ? 1 : 2) + (l4 ? 0 : a4);
             const int e = ce_[c], ne = e >> 16, e0 = e & 0xffff, ro = r1 * rows2 + r2;
-            cx<T> xv = R[p * 16 + ro];
-            for (int k = 0; k < ne; ++k) xv += R[(e0 + k) * 16 + ro];
+            cx<T> xv = R[p * rstride + ro];
+            for (int k = 0; k < ne; ++k) xv += R[(e0 + k) * rstride + ro];
             const T cf = cc_[c];
             v.re = fma(cf, xv.re, v.re);
             v.im = fma(cf, xv.im, v.im);
@@ -2282,7 +2283,8 @@ template <typename T, int NT, bool SEG> hipError_t launch_contract_t(const Contr
 
 hipError_t launch_contract(int prec, const ContractArgs& a, hipStream_t st) {
   if (a.engine == 1) {
-    const size_t lds = contract_seg_lds_bytes(prec, a.max_gslots, a.max_gcontrib, a.max_gch, a.max_gstask);
+    if (a.rstride != 16 && a.rstride != kSegRStride) return hipErrorInvalidValue;
+    const size_t lds = contract_seg_lds_bytes(prec, a.max_gslots, a.max_gcontrib, a.max_gch, a.max_gstask, a.rstride);
     if (a.waves != 8 && a.waves != 16) return hipErrorInvalidValue;
     if (prec == 0)
       return a.waves == 16 ? launch_contract_t<double, 1024, true>(a, lds, st)

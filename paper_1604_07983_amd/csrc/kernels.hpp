@@ -70,6 +70,10 @@ constexpr int kProdInts = 48;
 // Segment descriptors of the matrix-core contraction: integers per
 // descriptor, teams (one descriptor each) per wavefront task.
 constexpr int kSegInts = 16, kSegTeams = 4;
+// result slots of the segment contraction: 16 complex values, spaced 17
+// apart so that the lanes summing one channel output (same entry of
+// different slots) fall in different LDS banks
+constexpr int kSegRStride = 17;
 constexpr int kSegC144 = 0, kSegC9 = 1, kSegC36 = 2, kSegC1 = 3, kSegIdle = 15;
 
 // One geometry of a contraction launch: its blocks, its F~ output and its
@@ -107,6 +111,7 @@ struct ContractArgs {
   int engine;
   const int *seg_task, *group_stask, *prod_ext, *contrib_ext;
   int max_gslots, max_gstask;
+  int rstride;  // complex values between result slots: kSegRStride, or 16 where that does not fit
   long long block0, n_chunk;  // logical workgroups [block0, block0 + n_chunk) in this launch
 };
 
@@ -150,7 +155,7 @@ int fft_plane_fields(int n, long long inner, int kind);
 hipError_t launch_fft_plane(int kind, int n, const FftPlaneArgs& a, hipStream_t st);
 hipError_t launch_fft_line(int kind, const FftArgs& a, hipStream_t st);
 size_t contract_lds_bytes(int prec, int max_gprod, int max_gcontrib, int max_gch, int max_gtask);
-size_t contract_seg_lds_bytes(int prec, int max_gslots, int max_gcontrib, int max_gch, int max_gstask);
+size_t contract_seg_lds_bytes(int prec, int max_gslots, int max_gcontrib, int max_gch, int max_gstask, int rstride);
 // Wavefronts per contraction workgroup for a precision (the channel compiler
 // balances each group's tasks over this many).
 int contract_waves(int prec);

@@ -268,6 +268,7 @@ nbs_status compile_and_upload(nbs_plan p) {
   p->opt.split = p->tune.split != 0;
   p->opt.mfma = p->prec == NBS_FP32_MFMA && p->tune.mfma != 0;
   p->opt.seg_waves = p->tune.seg_waves;
+  p->opt.fp32 = p->prec == NBS_FP32_MFMA;
   p->opt.max_group_slots = 128;
   Compiled comp;
   std::string msg = nbs::compile_channels(p->specs, p->opt, &comp);
@@ -348,9 +349,14 @@ nbs_status compile_and_upload(nbs_plan p) {
   c.max_gslots = std::max(1, P.max_group_slots);
   c.max_gstask = std::max(1, P.max_group_stasks);
   c.waves = c.engine == 1 ? p->tune.seg_waves : p->tune.waves;
-  const size_t lds = c.engine == 1
-                         ? nbs::contract_seg_lds_bytes(p->prec, c.max_gslots, c.max_gcontrib, c.max_gch, c.max_gstask)
-                         : nbs::contract_lds_bytes(p->prec, c.max_gprod, c.max_gcontrib, c.max_gch, c.max_gtask);
+  // result slots spaced kSegRStride apart where the LDS allows it
+  c.rstride = nbs::kSegRStride;
+  if (nbs::contract_seg_lds_bytes(p->prec, c.max_gslots, c.max_gcontrib, c.max_gch, c.max_gstask, c.rstride) >
+      160 * 1024)
+    c.rstride = 16;
+  const size_t lds = c.engine == 1 ? nbs::contract_seg_lds_bytes(p->prec, c.max_gslots, c.max_gcontrib, c.max_gch,
+                                                                 c.max_gstask, c.rstride)
+                                   : nbs::contract_lds_bytes(p->prec, c.max_gprod, c.max_gcontrib, c.max_gch, c.max_gtask);
   if (lds > 160 * 1024) return fail(p, NBS_ERR_UNSUPPORTED, "a channel group needs more LDS than a CU has");
   return hip_check(p, nbs::prepare_kernels(p->prec, c.waves, lds, c.engine), "kernel attributes");
 }

@@ -17,7 +17,7 @@ int fft_plane_fields(int, long long, int) { return 0; }
 hipError_t launch_fft_plane(int, int, const FftPlaneArgs&, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_fft_line(int, const FftArgs&, hipStream_t) { return hipErrorNotSupported; }
 size_t contract_lds_bytes(int, int, int, int, int) { return 0; }
-size_t contract_seg_lds_bytes(int, int, int, int, int) { return 0; }
+size_t contract_seg_lds_bytes(int, int, int, int, int, int) { return 0; }
 int contract_waves(int prec) { return prec == 0 ? 8 : 4; }
 hipError_t launch_contract(int, const ContractArgs&, hipStream_t) { return hipErrorNotSupported; }
 hipError_t prepare_kernels(int, int, size_t, int) { return hipErrorNotSupported; }
