@@ -236,7 +236,7 @@ class Plan:
         self._check(lib().nbs_plan_tuning(self._h, out), "nbs_plan_tuning")
         return {"fft_line": out[0] & 1, "fft_plane": (out[0] >> 1) & 1, "fft_tile": out[1], "waves": out[2],
                 "split": out[3] & 1, "mfma": (out[3] >> 1) & 1, "gchunk": (out[3] >> 2) & 3,
-                "engine": (out[3] >> 4) & 1}
+                "engine": (out[3] >> 4) & 1, "persist": (out[3] >> 5) & 1}
 
     def set_tuning(self, **kw):
         """Change some launch shapes (keys as returned by tuning())."""
@@ -245,7 +245,7 @@ class Plan:
         arr = (ctypes.c_int32 * 4)(int(t["fft_line"]) | (int(t["fft_plane"]) << 1), int(t["fft_tile"]),
                                    int(t["waves"]),
                                    int(t["split"]) | (int(t["mfma"]) << 1) | (int(t["gchunk"]) << 2)
-                                   | (int(t["engine"]) << 4))
+                                   | (int(t["engine"]) << 4) | (int(t["persist"]) << 5))
         self._check(lib().nbs_plan_set_tuning(self._h, arr), "nbs_plan_set_tuning")
 
     def info(self):

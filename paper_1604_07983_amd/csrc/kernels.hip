@@ -1701,12 +1701,12 @@ __device__ __forceinline__ void seg_run(const int* d, const cx<T>* S1, const cx<
 // LDS of the segment contraction: the two blocks, the result slots, one set
 // of task descriptors, two sets of channel tables (coefficients, product
 // words, segment words, channel offsets: the group being summed and the
-// next one) and the task counter.
+// next one), the task counter and the claimed work item.
 size_t contract_seg_lds_bytes(int prec, int max_gslots, int max_gcontrib, int max_gch, int max_gstask, int rstride) {
   const size_t el = prec == 0 ? sizeof(cd) : sizeof(cf);
   const size_t real = prec == 0 ? sizeof(double) : sizeof(float);
   return el * (2 * (size_t)kLdsBlock + (size_t)max_gslots * rstride) + 2 * real * max_gcontrib +
-         sizeof(int) * ((size_t)max_gstask * kSegTeams * kSegInts + 2 * (2 * (size_t)max_gcontrib + max_gch + 1) + 1);
+         sizeof(int) * ((size_t)max_gstask * kSegTeams * kSegInts + 2 * (2 * (size_t)max_gcontrib + max_gch + 1) + 2);
 }
 
 // One operator block moved from HBM to LDS in chunks of four consecutive
@@ -1809,12 +1809,10 @@ template <typename T, int NT> struct GroupTables {
   }
 };
 
-template <typename T, int NT> __device__ __forceinline__ void contract_seg_body(const ContractArgs& a) {
+// One work item: (geometry, slice, momentum, range of groups) number
+// `local` of the launch.  Ends with a barrier, so the LDS can be reused.
+template <typename T, int NT> __device__ __forceinline__ void contract_seg_item(const ContractArgs& a, long long local) {
   extern __shared__ __align__(16) char smem_raw[];
-  const long long nb8 = (a.n_chunk + 7) / 8 * 8;
-  const long long b = blockIdx.x;
-  const long long local = (b % 8) * (nb8 / 8) + b / 8;
-  if (local >= a.n_chunk) return;
   const long long logical = a.block0 + local;
   const long long qtl = logical / a.n_gchunk;
   const int chunk = (int)(logical - qtl * a.n_gchunk);
@@ -1958,13 +1956,53 @@ template <typename T, int NT> __device__ __forceinline__ void contract_seg_body(
   }
 }
 
-template <typename T, int NT> __global__ __launch_bounds__(NT) void k_contract_seg(ContractArgs a) {
-  contract_seg_body<T, NT>(a);
+// Work items [0, n_chunk) in eight equal shares, item x * per + k of share
+// x, where the share of XCD x holds every range of groups of one momentum
+// (its pair q, -q in one L2).  One workgroup per item (workgroup b takes
+// item k = b / 8 of share b % 8), or, in the persistent variant, as many
+// workgroups as stay resident, each claiming items of its XCD's share from
+// a counter in a.queue (zeroed before the launch) and then those of the
+// other shares; every workgroup leaves once every counter has passed its
+// share's end.  (Separate kernels: the claim loop costs registers.)
+template <typename T, int NT, bool kPersist> __device__ __forceinline__ void contract_seg_body(const ContractArgs& a) {
+  const long long per = (a.n_chunk + 7) / 8;
+  const int xcd = blockIdx.x % 8;
+  if constexpr (!kPersist) {
+    const long long local = xcd * per + blockIdx.x / 8;
+    if (local < a.n_chunk) contract_seg_item<T, NT>(a, local);
+    return;
+  }
+  // the int after the task counter (the item's LDS layout)
+  extern __shared__ __align__(16) char smem_raw[];
+  cx<T>* const R = reinterpret_cast<cx<T>*>(smem_raw) + 2 * kLdsBlock;
+  T* const ccoef = reinterpret_cast<T*>(R + a.max_gslots * a.rstride);
+  int* const claim = reinterpret_cast<int*>(ccoef + 2 * a.max_gcontrib) + a.max_gstask * (kSegTeams * kSegInts) +
+                     2 * (2 * a.max_gcontrib + a.max_gch + 1) + 1;
+  for (int off = 0; off < 8; ++off) {
+    const int share = (xcd + off) & 7;
+    for (;;) {
+      if (threadIdx.x == 0) *claim = (int)atomicAdd(&a.queue[share], 1u);
+      __syncthreads();
+      const long long k = *claim;
+      __syncthreads();  // read by every thread before the next claim
+      if (k >= per) break;
+      const long long local = share * per + k;
+      if (local < a.n_chunk) contract_seg_item<T, NT>(a, local);
+    }
+  }
+}
+
+template <typename T, int NT, bool kPersist = false>
+__global__ __launch_bounds__(NT) void k_contract_seg(ContractArgs a) {
+  contract_seg_body<T, NT, kPersist>(a);
 }
 // Precision form, 512 threads: four wavefronts per SIMD (registers for two
 // workgroups per CU), so that one stages blocks while the other computes.
-template <> __global__ __launch_bounds__(512, 4) void k_contract_seg<float, 512>(ContractArgs a) {
-  contract_seg_body<float, 512>(a);
+template <> __global__ __launch_bounds__(512, 4) void k_contract_seg<float, 512, false>(ContractArgs a) {
+  contract_seg_body<float, 512, false>(a);
+}
+template <> __global__ __launch_bounds__(512, 4) void k_contract_seg<float, 512, true>(ContractArgs a) {
+  contract_seg_body<float, 512, true>(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -2246,12 +2284,17 @@ hipError_t prepare_kernels(int prec, int waves, size_t contract_lds, int engine)
   set((const void*)k_fft_plane<32, plane_ib<float>(32), float>, 128 * 1024);
   set((const void*)k_fft_plane<40, plane_ib<float>(40), float>, 128 * 1024);
   if (engine == 1) {
-    if (prec == 0)
+    if (prec == 0) {
       set(waves == 16 ? (const void*)k_contract_seg<double, 1024> : (const void*)k_contract_seg<double, 512>,
           (int)contract_lds);
-    else
+      set(waves == 16 ? (const void*)k_contract_seg<double, 1024, true> : (const void*)k_contract_seg<double, 512, true>,
+          (int)contract_lds);
+    } else {
       set(waves == 16 ? (const void*)k_contract_seg<float, 1024> : (const void*)k_contract_seg<float, 512>,
           (int)contract_lds);
+      set(waves == 16 ? (const void*)k_contract_seg<float, 1024, true> : (const void*)k_contract_seg<float, 512, true>,
+          (int)contract_lds);
+    }
   } else if (prec == 0) {
     set((const void*)k_contract<double, 512>, (int)contract_lds);
   } else if (waves == 8) {
@@ -2265,6 +2308,25 @@ hipError_t prepare_kernels(int prec, int waves, size_t contract_lds, int engine)
 namespace {
 template <typename T, int NT, bool SEG> hipError_t launch_contract_t(const ContractArgs& a, size_t lds, hipStream_t st) {
   hipError_t e = hipSuccess;
+  if constexpr (SEG) {
+    if (a.persistent) {
+      // every work item in one launch of as many workgroups as stay resident
+      int dev = 0, cus = 0, per_cu = 0;
+      if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+      if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+      if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_contract_seg<T, NT, true>, NT,
+                                                            lds)) != hipSuccess)
+        return e;
+      if (a.queue == nullptr || per_cu < 1 || a.n_blocks > (1LL << 31) - 8) return hipErrorInvalidValue;
+      ContractArgs c = a;
+      c.block0 = 0;
+      c.n_chunk = a.n_blocks;
+      const long long nb8 = (c.n_chunk + 7) / 8 * 8;
+      const long long res = ((long long)cus * per_cu + 7) / 8 * 8;
+      hipLaunchKernelGGL((k_contract_seg<T, NT, true>), dim3((unsigned)(nb8 < res ? nb8 : res)), dim3(NT), lds, st, c);
+      return hipGetLastError();
+    }
+  }
   const long long chunk = kMaxLaunchItems / NT / 8 * 8;
   for (long long b0 = 0; b0 < a.n_blocks; b0 += chunk) {
     ContractArgs c = a;

@@ -112,6 +112,10 @@ struct ContractArgs {
   const int *seg_task, *group_stask, *prod_ext, *contrib_ext;
   int max_gslots, max_gstask;
   int rstride;  // complex values between result slots: kSegRStride, or 16 where that does not fit
+  // persistent launch: resident workgroups claim work items from eight
+  // counters (queue[8], zeroed before each launch)
+  int persistent;
+  unsigned* queue;
   long long block0, n_chunk;  // logical workgroups [block0, block0 + n_chunk) in this launch
 };
 

@@ -53,6 +53,9 @@ struct Tuning {
   // matrix cores; wavefronts per workgroup of the matrix-core engine
   int engine = 1;
   int seg_waves = 16;
+  // matrix-core engine: 1 resident workgroups claiming work items from
+  // counters, 0 one workgroup per item
+  int persist = 0;
 };
 
 }  // namespace
@@ -77,6 +80,7 @@ struct nbs_plan_s {
   int* chan_nf = nullptr;  // [n_ch][3] quark counts
   nbs::ContractGeom* geo = nullptr;
   unsigned* nonfinite = nullptr;  // set by the block kernel on NaN / infinite propagator entries
+  unsigned* queue = nullptr;      // eight work-item counters of the persistent contraction
   long long n_qt = 0;  // (slice, momentum) pairs over all geometries
   size_t dev_bytes = 0;
   std::map<std::string, size_t> prog_off;  // table name -> offset (ints) into prog
@@ -349,6 +353,8 @@ nbs_status compile_and_upload(nbs_plan p) {
   c.max_gslots = std::max(1, P.max_group_slots);
   c.max_gstask = std::max(1, P.max_group_stasks);
   c.waves = c.engine == 1 ? p->tune.seg_waves : p->tune.waves;
+  c.persistent = c.engine == 1 ? p->tune.persist : 0;
+  c.queue = p->queue;
   // result slots spaced kSegRStride apart where the LDS allows it
   c.rstride = nbs::kSegRStride;
   if (nbs::contract_seg_lds_bytes(p->prec, c.max_gslots, c.max_gcontrib, c.max_gch, c.max_gstask, c.rstride) >
@@ -417,6 +423,13 @@ nbs_status enqueue_build(nbs_plan p, const void* const* pu, const void* const* p
 
 nbs_status enqueue_contract(nbs_plan p, hipStream_t st) {
   nbs::ContractArgs a = p->con;
+  if (a.persistent) {
+    // the work-item counters start at zero (a fill kernel, not a memset,
+    // so that the sequence can be captured into a graph)
+    nbs_status s = hip_check(p, nbs::launch_fill_u32(p->queue, 0u, 8, st), "fill");
+    if (s != NBS_OK) return s;
+    a.queue = p->queue;
+  }
   if (p->iso) {
     a.group_op1 = (const int*)(p->prog + p->prog_off["group_op1_iso"]);
     a.group_op2 = (const int*)(p->prog + p->prog_off["group_op2_iso"]);
@@ -637,6 +650,8 @@ nbs_status create_plan(nbs_plan* out, const nbs_geometry* g, int32_t n_geom, con
   p->geo = (nbs::ContractGeom*)tmp;
   if ((s = dev_alloc(p, 4, &tmp, &countdown)) != NBS_OK) return bail(s);
   p->nonfinite = (unsigned*)tmp;
+  if ((s = dev_alloc(p, 8 * 4, &tmp, &countdown)) != NBS_OK) return bail(s);
+  p->queue = (unsigned*)tmp;
   // per geometry: momenta in the order q, -q, q', -q', ...
   std::vector<int*> qorder(n_geom, nullptr);
   for (int i = 0; i < n_geom; ++i) {
@@ -944,6 +959,17 @@ nbs_status nbs_plan_autotune(nbs_plan p, const void* const* prop_u, const void* 
     if (ms < best_ms) { best_ms = ms; best_g = gc; }
   }
   p->tune.gchunk = best_g;
+  // 4. matrix-core engine: resident workgroups claiming work items, or one
+  //    workgroup per item
+  if (p->tune.engine == 1) {
+    p->tune.persist = 1;
+    if ((s = compile_and_upload(p)) != NBS_OK) return finish(s);
+    float ms = 0;
+    if ((s = timed([&]() { return enqueue_contract(p, st); }, &ms)) != NBS_OK) return finish(s);
+    if (!(ms < best_ms)) p->tune.persist = 0;
+  } else {
+    p->tune.persist = 0;
+  }
   if ((s = compile_and_upload(p)) != NBS_OK) return finish(s);
   // leave the plan built with the chosen shapes
   if ((s = enqueue_build(p, prop_u, prop_d, prop_s, st)) != NBS_OK) return finish(s);
@@ -957,7 +983,7 @@ nbs_status nbs_plan_tuning(const nbs_plan p, int32_t out[4]) {
   out[0] = p->tune.fft_line | (p->tune.fft_plane << 1);
   out[1] = p->tune.fft_tile;
   out[2] = p->tune.engine == 1 ? p->tune.seg_waves : p->tune.waves;
-  out[3] = p->tune.split | (p->tune.mfma << 1) | (p->tune.gchunk << 2) | (p->tune.engine << 4);
+  out[3] = p->tune.split | (p->tune.mfma << 1) | (p->tune.gchunk << 2) | (p->tune.engine << 4) | (p->tune.persist << 5);
   return NBS_OK;
 }
 
@@ -967,7 +993,9 @@ nbs_status nbs_plan_set_tuning(nbs_plan p, const int32_t in[4]) {
   if (tile != 512 && tile != 1024 && tile != 2048 && tile != 4096) return fail(p, NBS_ERR_INVALID, "fft tile");
   const int waves = in[2];
   const int engine = (in[3] >> 4) & 1;
-  if (in[3] < 0 || (in[3] >> 5) != 0) return fail(p, NBS_ERR_INVALID, "unknown tuning bits");
+  const int persist = (in[3] >> 5) & 1;
+  if (in[3] < 0 || (in[3] >> 6) != 0) return fail(p, NBS_ERR_INVALID, "unknown tuning bits");
+  if (persist && engine != 1) return fail(p, NBS_ERR_INVALID, "persistent workgroups need the matrix-core engine");
   if (engine == 1 ? (waves != 8 && waves != 16)
                   : (p->prec == NBS_FP64 ? waves != 8 : (waves != 4 && waves != 8)))
     return fail(p, NBS_ERR_INVALID, "waves");
@@ -985,6 +1013,7 @@ nbs_status nbs_plan_set_tuning(nbs_plan p, const int32_t in[4]) {
   p->tune.split = in[3] & 1;
   p->tune.mfma = (in[3] >> 1) & 1;
   p->tune.gchunk = (in[3] >> 2) & 3;
+  p->tune.persist = persist;
   drop_graph(p);
   const nbs_status s = compile_and_upload(p);
   if (s != NBS_OK) {

@@ -334,11 +334,16 @@ def test_matrix_core_program_reproduces_oracle():
 
 def test_set_tuning_rejects_bad_shapes():
     p = host_plan([("p", "p", "p", "p")])
-    for kw in (dict(fft_tile=300), dict(waves=4), dict(mfma=1), dict(gchunk=3), dict(engine=0, waves=16)):
+    for kw in (dict(fft_tile=300), dict(waves=4), dict(mfma=1), dict(gchunk=3), dict(engine=0, waves=16),
+               dict(engine=0, waves=8, persist=1)):
         with pytest.raises(binding.NbsError):
             p.set_tuning(**kw)
-    # the matrix-core engine with 8-wavefront workgroups by default
-    assert p.tuning()["waves"] == 8 and p.tuning()["engine"] == 1
+    # the matrix-core engine with 8-wavefront workgroups, one per work item,
+    # by default
+    assert p.tuning()["waves"] == 8 and p.tuning()["engine"] == 1 and p.tuning()["persist"] == 0
+    p.set_tuning(persist=1)
+    assert p.tuning()["persist"] == 1
+    p.set_tuning(persist=0)
     p.set_tuning(engine=0, waves=8)
     assert p.tuning()["waves"] == 8 and p.tuning()["engine"] == 0
 

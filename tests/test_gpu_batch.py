@@ -59,6 +59,33 @@ def test_batch_uneven_lattices_match_oracle(prec, tol):
     br.close()
 
 
+@pytest.mark.parametrize("prec,tol", [(binding.NBS_FP64, 1e-12), (binding.NBS_FP32_MFMA, 1e-5)])
+def test_batch_persistent_contraction(prec, tol):
+    """Resident workgroups claiming (geometry, slice, momentum) items from
+    the XCD counters, eagerly and in graph replays (the counters are reset
+    by a fill kernel inside the graph)."""
+    import torch
+    announce("batch persistent contraction, prec %d" % prec)
+    geoms = small_geoms()
+    chans = [channels.r52()[c] for c in SUB]
+    dt = np.complex128 if prec == binding.NBS_FP64 else np.complex64
+    hprops = geom_props(geoms, dt)
+    dprops = [runner.device_props(p, prec) for p in hprops]
+    br = runner.BatchRunner(geoms, chans, prec=prec)
+    br.plan.set_tuning(persist=1)
+    F = [f.clone() for f in br.run(dprops)]
+    torch.cuda.synchronize()
+    check_against_oracle(geoms, hprops, F, chans, tol)
+    for rep in range(3):
+        for f in br.F:
+            f.fill_(float("nan"))
+        br.run_graph(dprops)
+        torch.cuda.synchronize()
+        for a, b in zip(br.F, F):
+            assert torch.equal(a, b), rep
+    br.close()
+
+
 def test_batch_graph_replays_match_eager():
     """Graph replays with eager work in between; every replay equals the
     eager result bit for bit; new output pointers trigger a new capture."""

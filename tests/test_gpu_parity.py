@@ -141,7 +141,8 @@ def test_square_plane_lattice(prec):
 @pytest.mark.parametrize("tuning", [dict(engine=0, waves=4), dict(engine=0, mfma=1, waves=4),
                                     dict(engine=0, mfma=1, waves=8),
                                     dict(engine=0, waves=4, split=0, fft_line=0, fft_tile=2048), dict(fft_plane=1),
-                                    dict(gchunk=1), dict(gchunk=2, waves=8), dict(waves=16)])
+                                    dict(gchunk=1), dict(gchunk=2, waves=8), dict(waves=16), dict(persist=1),
+                                    dict(persist=1, gchunk=1, waves=16)])
 def test_precision_form_launch_shapes(tuning):
     """The precision form under other launch shapes (the lane-team engine
     with and without its matrix-core quads, 256- and 512-thread workgroups,
@@ -173,7 +174,8 @@ def test_long_register_lines(L, prec):
     assert err.max() <= TOL[prec], (err.max(), int(err.argmax()))
 
 
-@pytest.mark.parametrize("tuning", [dict(gchunk=1), dict(gchunk=2), dict(engine=0, waves=8),
+@pytest.mark.parametrize("tuning", [dict(gchunk=1), dict(gchunk=2), dict(persist=1), dict(persist=1, gchunk=1),
+                                    dict(engine=0, waves=8),
                                     dict(engine=0, waves=8, gchunk=2), dict(waves=16)])
 def test_fp64_launch_shapes(tuning):
     """Double precision with workgroups that walk one run of sink-operator
