@@ -174,7 +174,8 @@ nbs_status nbs_run_graph(nbs_plan plan, const void* const* prop_u, const void* c
  * 1024, 2048 or 4096 elements; for the contraction, the matrix-core
  * segment engine with 8 or 16 wavefronts per workgroup or the lane-team
  * engine (8 wavefronts in FP64, 4 in the precision form), then the ranges
- * of sink-operator groups one workgroup walks.  Synchronous; leaves the
+ * of sink-operator groups one workgroup walks, then (segment engine) a
+ * workgroup per work item or resident workgroups claiming work items.  Synchronous; leaves the
  * plan as after nbs_build_blocks.  Results are unchanged up to rounding
  * order.  Callers that create the same shapes repeatedly can keep the
  * result (nbs_plan_tuning) and set it with nbs_plan_set_tuning instead. */
@@ -189,6 +190,9 @@ nbs_status nbs_plan_autotune(nbs_plan plan, const void* const* prop_u, const voi
  * workgroups per (slice, momentum): 0 one that walks every sink-operator
  * group, keeping an operator block in LDS while consecutive groups share
  * it; 1 one per run of groups in which one block stays; 2 one per group;
+ * bit 5 (segment engine) persistent launch: as many workgroups as stay
+ * resident, claiming (geometry, slice, momentum) work items from counters,
+ * instead of one workgroup per item;
  * bits 0 and 1 apply to the lane-team engine only: bit 0 splitting a
  * product's walked index over lanes on/off, bit 1 (precision form) its
  * 4 x 4-row products on matrix cores on/off. */
@@ -197,10 +201,11 @@ nbs_status nbs_plan_tuning(const nbs_plan plan, int32_t out[4]);
 /* Set the launch shapes (same encoding as nbs_plan_tuning) instead of
  * measuring them: waits for the plan's device work, recompiles the channel
  * program for the new shapes; blocks already built stay valid.  Rejects
- * (NBS_ERR_INVALID, the plan unchanged) unknown tiles, bits above bit 4 of
+ * (NBS_ERR_INVALID, the plan unchanged) unknown tiles, bits above bit 5 of
  * in[3], wavefront counts other than 8 / 16 (segment engine) or 8 (lane
  * teams, FP64) or 4 / 8 (lane teams, precision form), matrix-core lane-team
- * products outside the precision form and group-range modes above 2. */
+ * products outside the precision form, group-range modes above 2 and the
+ * persistent launch with the lane-team engine. */
 nbs_status nbs_plan_set_tuning(nbs_plan plan, const int32_t in[4]);
 
 /* Whether the propagators of the plan's last nbs_build_blocks (or
