@@ -305,23 +305,29 @@ __global__ __launch_bounds__(kThreads) void k_fft_line2(FftArgs a) {
 // one HBM read and one write for two axes.  The tile is kept in LDS in the
 // storage type (the precision form keeps complex64 between the axes, as it
 // does between passes); arithmetic is FP64.
-template <int N, int IB, typename T>
-__global__ __launch_bounds__(kThreads) void k_fft_plane(FftPlaneArgs a) {
+template <int N, int IB, typename T, int NT>
+__global__ __launch_bounds__(NT) void k_fft_plane(FftPlaneArgs a) {
   extern __shared__ __align__(16) char smem_plane[];
   cx<T>* tile = reinterpret_cast<cx<T>*>(smem_plane);  // [y][x][f]
   const long long n_ftiles = a.inner / IB;
-  const long long wg = a.unit0 + blockIdx.x;
+  // consecutive field tiles (halves of one 128-byte run when IB x element
+  // is 64 bytes) on the same XCD at about the same time, so that they
+  // share its L2
+  const long long per = (a.n_units + 7) / 8;
+  const long long local = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (local >= a.n_units) return;
+  const long long wg = a.unit0 + local;
   const long long plane = wg / n_ftiles, f0 = (wg % n_ftiles) * IB;
   const cx<T>* in = reinterpret_cast<const cx<T>*>(a.in) + plane * N * N * a.inner + f0;
   cx<T>* out = reinterpret_cast<cx<T>*>(a.out) + plane * N * N * a.inner + f0;
   constexpr int kTile = N * N * IB;
-  for (int e = threadIdx.x; e < kTile; e += kThreads) {
+  for (int e = threadIdx.x; e < kTile; e += NT) {
     const int f = e % IB, xy = e / IB;
     tile[e] = in[(long long)xy * a.inner + f];
   }
   __syncthreads();
   // lines along x: (y, f) -> elements (y N + x) IB + f
-  for (int l = threadIdx.x; l < N * IB; l += kThreads) {
+  for (int l = threadIdx.x; l < N * IB; l += NT) {
     const int f = l % IB, y = l / IB;
     cd v[N];
 #pragma unroll
@@ -332,7 +338,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_plane(FftPlaneArgs a) {
   }
   __syncthreads();
   // lines along y: (x, f)
-  for (int l = threadIdx.x; l < N * IB; l += kThreads) {
+  for (int l = threadIdx.x; l < N * IB; l += NT) {
     const int f = l % IB, x = l / IB;
     cd v[N];
 #pragma unroll
@@ -342,7 +348,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_plane(FftPlaneArgs a) {
     for (int y = 0; y < N; ++y) tile[(y * N + x) * IB + f] = conv<T>(v[y]);
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < kTile; e += kThreads) {
+  for (int e = threadIdx.x; e < kTile; e += NT) {
     const int f = e % IB, xy = e / IB;
     out[(long long)xy * a.inner + f] = tile[e];
   }
@@ -2167,17 +2173,22 @@ template <typename T> constexpr int plane_ib(int n) {
   return ib;
 }
 
+// threads of a plane workgroup: 512 where the tile leaves one workgroup per
+// CU (complex64 planes of 32 and 40 points), else 256
+template <typename T> constexpr int plane_threads(int n) { return sizeof(T) == 8 || n < 32 ? kThreads : 512; }
+
 template <int N, typename T> hipError_t launch_plane_t(const FftPlaneArgs& a, hipStream_t st) {
   constexpr int IB = plane_ib<T>(N);
+  constexpr int NT = plane_threads<T>(N);
   if (a.IB != IB) return hipErrorInvalidValue;
   const size_t lds = sizeof(cx<T>) * N * N * IB;
   const long long wgs = a.planes * (a.inner / IB);
-  const long long chunk = kMaxLaunchItems / kThreads;
+  const long long chunk = kMaxLaunchItems / NT / 8 * 8;
   for (long long w0 = 0; w0 < wgs; w0 += chunk) {
     FftPlaneArgs c = a;
     c.unit0 = w0;
-    hipLaunchKernelGGL((k_fft_plane<N, IB, T>), dim3((unsigned)(wgs - w0 < chunk ? wgs - w0 : chunk)), dim3(kThreads),
-                       lds, st, c);
+    c.n_units = wgs - w0 < chunk ? wgs - w0 : chunk;
+    hipLaunchKernelGGL((k_fft_plane<N, IB, T, NT>), dim3((unsigned)((c.n_units + 7) / 8 * 8)), dim3(NT), lds, st, c);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -2273,16 +2284,16 @@ hipError_t prepare_kernels(int prec, int waves, size_t contract_lds, int engine)
   set((const void*)k_fft_pass<double, double>, mx);
   set((const void*)k_fft_pass<float, float>, mx);
   set((const void*)k_fft_pass<float, double>, mx);
-  set((const void*)k_fft_plane<8, plane_ib<double>(8), double>, 128 * 1024);
-  set((const void*)k_fft_plane<16, plane_ib<double>(16), double>, 128 * 1024);
-  set((const void*)k_fft_plane<24, plane_ib<double>(24), double>, 128 * 1024);
-  set((const void*)k_fft_plane<32, plane_ib<double>(32), double>, 128 * 1024);
-  set((const void*)k_fft_plane<40, plane_ib<double>(40), double>, 128 * 1024);
-  set((const void*)k_fft_plane<8, plane_ib<float>(8), float>, 128 * 1024);
-  set((const void*)k_fft_plane<16, plane_ib<float>(16), float>, 128 * 1024);
-  set((const void*)k_fft_plane<24, plane_ib<float>(24), float>, 128 * 1024);
-  set((const void*)k_fft_plane<32, plane_ib<float>(32), float>, 128 * 1024);
-  set((const void*)k_fft_plane<40, plane_ib<float>(40), float>, 128 * 1024);
+  set((const void*)k_fft_plane<8, plane_ib<double>(8), double, plane_threads<double>(8)>, 128 * 1024);
+  set((const void*)k_fft_plane<16, plane_ib<double>(16), double, plane_threads<double>(16)>, 128 * 1024);
+  set((const void*)k_fft_plane<24, plane_ib<double>(24), double, plane_threads<double>(24)>, 128 * 1024);
+  set((const void*)k_fft_plane<32, plane_ib<double>(32), double, plane_threads<double>(32)>, 128 * 1024);
+  set((const void*)k_fft_plane<40, plane_ib<double>(40), double, plane_threads<double>(40)>, 128 * 1024);
+  set((const void*)k_fft_plane<8, plane_ib<float>(8), float, plane_threads<float>(8)>, 128 * 1024);
+  set((const void*)k_fft_plane<16, plane_ib<float>(16), float, plane_threads<float>(16)>, 128 * 1024);
+  set((const void*)k_fft_plane<24, plane_ib<float>(24), float, plane_threads<float>(24)>, 128 * 1024);
+  set((const void*)k_fft_plane<32, plane_ib<float>(32), float, plane_threads<float>(32)>, 128 * 1024);
+  set((const void*)k_fft_plane<40, plane_ib<float>(40), float, plane_threads<float>(40)>, 128 * 1024);
   if (engine == 1) {
     if (prec == 0) {
       set(waves == 16 ? (const void*)k_contract_seg<double, 1024> : (const void*)k_contract_seg<double, 512>,

@@ -48,7 +48,8 @@ struct FftPlaneArgs {
   void* out;
   long long planes, inner;
   int IB;
-  long long unit0;  // first workgroup of this launch
+  long long unit0;    // first workgroup of this launch
+  long long n_units;  // workgroups of this launch
 };
 
 // Workgroups per launch stay below this bound, so that workgroups x threads

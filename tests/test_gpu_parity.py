@@ -159,6 +159,24 @@ def test_precision_form_launch_shapes(tuning):
 
 
 @pytest.mark.parametrize("prec", [binding.NBS_FP64, binding.NBS_FP32_MFMA])
+@pytest.mark.parametrize("L", [(24, 24, 2), (32, 32, 2), (40, 40, 2)])
+def test_plane_pass_wide_planes(L, prec):
+    """The fused x-y pass on 24^2, 32^2 and 40^2 planes (512-thread
+    workgroups and XCD-paired field tiles for complex64 32^2 and 40^2)
+    against the line passes and the oracle."""
+    announce("plane pass %s prec=%d" % (L, prec))
+    chans = [channels.r52()[c] for c in (0, 12, 22, 51)]
+    dt = np.complex128 if prec == binding.NBS_FP64 else np.complex64
+    props = runner.host_props(L, 2, range(1), dtype=dt)
+    Fp = run_gpu(L, 2, chans, props, prec, t_count=1, tuning=dict(fft_plane=1))
+    Fl = run_gpu(L, 2, chans, props, prec, t_count=1, tuning=dict(fft_plane=0))
+    Fo = oracle_F(L, props, chans)
+    for Fg in (Fp, Fl):
+        err = rel_err_per_channel(Fg, Fo)
+        assert err.max() <= TOL[prec], (err.max(), int(err.argmax()))
+
+
+@pytest.mark.parametrize("prec", [binding.NBS_FP64, binding.NBS_FP32_MFMA])
 @pytest.mark.parametrize("L", [(64, 2, 3), (80, 2, 2), (96, 2, 2)])
 def test_long_register_lines(L, prec):
     """Lines of 64, 80 and 96 points, two threads per line with FP64
