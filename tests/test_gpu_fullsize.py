@@ -54,6 +54,10 @@ def test_config2_fp64_16c32_all_channels():
     assert np.isfinite(Fg).all()
     check_sampled_momenta(L, props, Fg, chans, slices=(0, 31), qs=((0, 0, 0), (1, 2, 3), (15, 8, 1)),
                           tol=1e-12)
+    # every slice at one momentum of its own (q = (t, 3t + 1, 5t + 2) mod 16)
+    for ti in range(1, 31):
+        q = (ti % 16, (3 * ti + 1) % 16, (5 * ti + 2) % 16)
+        check_sampled_momenta(L, props, Fg, chans, slices=(ti,), qs=(q,), tol=1e-12)
     # a full slice for channels of each sector
     sub = [0, 1, 12, 30, 51]
     Fo = oracle.correlators(L, flat_props(props, 17), [chans[c] for c in sub], mode="fft")
@@ -112,6 +116,42 @@ def test_config5_96cubed_slice_closed_form():
         want = separable.channel(ch, C[c], phi)
         err = np.linalg.norm(got - want) / np.linalg.norm(want)
         assert err <= 1e-5, (c, ch, float(err))
+
+
+def test_config5_96cubed_gaussian_flavour_limit():
+    """Slice 0 of the 96^3 slab with the seeded Gaussian generator, u = d = s
+    (one propagator, decay 0.4): pp <- pp, Sigma+ Sigma+ <- Sigma+ Sigma+ and
+    Xi0 Xi0 <- Xi0 Xi0 agree everywhere (flavour relabelling, which holds at
+    any size), and pp's F~(0) = sum_r F(r) matches the oracle's
+    zero-momentum value computed from the same propagator."""
+    import gc
+    import torch
+    from paper_1604_07983_amd import synth
+    gc.collect()
+    torch.cuda.empty_cache()
+    announce("96^3 slice 0, Gaussian, u = d = s")
+    L, T = (96, 96, 96), 64
+    chans = [channels.r52()[c] for c in (0, 12, 50)]
+    S = synth.propagator_slice(L, 0, 0, 0.4, T=T, dtype=np.complex64)
+    d = torch.from_numpy(S).to("cuda").reshape(1, *S.shape)
+    r = runner.Runner(L, T, chans, prec=binding.NBS_FP32_MFMA, t_begin=0, t_count=1)
+    F = r.run(d, d, d)
+    torch.cuda.synchronize()
+    r.close()
+    del d
+    Fh = F[:, 0].cpu().numpy()
+    del F
+    torch.cuda.empty_cache()
+    assert np.isfinite(Fh).all()
+    for c in (1, 2):
+        err = np.linalg.norm(Fh[c] - Fh[0]) / np.linalg.norm(Fh[0])
+        assert err <= 1e-5, (c, float(err))
+    S128 = np.ascontiguousarray(S.reshape(-1, 12, 12).astype(np.complex128))
+    del S
+    want = oracle.correlators_at_q(L, [S128, S128, S128], chans[:1], (0, 0, 0))[0]
+    got = Fh[0].reshape(16, -1).sum(axis=1)
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    assert err <= 1e-5, float(err)
 
 
 @pytest.mark.parametrize("prec", [binding.NBS_FP64, binding.NBS_FP32_MFMA])
