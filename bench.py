@@ -227,7 +227,10 @@ def plain_leg(args, name):
     stage = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(3)] for e in evs])  # ms
     ms_step = wall * 1e3 / args.steps
     sites = V * tc
-    n_types = r.plan.info()["n_types"]
+    # complex entries per site of the stored operator blocks: operators with
+    # a same-flavour slot pair are stored antisymmetrised and packed (1584),
+    # the others whole (3456)
+    stored = int(sum(1584 if pr >= 0 else 3456 for pr in r.plan.table("op_pair")))
     tune = r.plan.tuning()
     fl, fl_sh, ebb, meb = contraction_work(r.plan)
     contract_ms = float(stage[:, 1].mean())
@@ -236,20 +239,20 @@ def plain_leg(args, name):
     # (when on and the plane is square) and the z pass each read and write
     # them, else three line passes
     passes = 1 + 2 * (2 if tune["fft_plane"] and L[0] == L[1] and prec == 0 else 3)
-    build_bytes = sites * (3 * 144 * el + n_types * 3456 * el * passes)
-    blocks = sites * n_types * 3456 * el
+    build_bytes = sites * (3 * 144 * el + stored * el * passes)
+    blocks = sites * stored * el
     fields = sites * len(chans) * 16
     peak = PEAK["fp64"] if prec == 0 else PEAK["fp32_mfma"]
     # whole-step roofline: per stage the larger of its flops at the peak and
     # its algorithmic bytes at the HBM peak (propagators read, blocks written
     # once and transformed with one read and one write, blocks read once by
     # the contraction, F~ written, read and F written)
-    parts = {"build_blocks": max(sites * n_types * 3456 * (3 * 8 + 5 * np.log2(V)) / peak,
+    parts = {"build_blocks": max(sites * stored * (3 * 8 + 5 * np.log2(V)) / peak,
                                  (sites * 3 * 144 * el + 3 * blocks) / PEAK["hbm"]),
              "contract_channels": max(fl * sites / peak, (blocks + fields * el) / PEAK["hbm"]),
              "relative_sum": max(fields * 5 * np.log2(V) / PEAK["fp64"], fields * (el + 16) / PEAK["hbm"])}
     step_roof_ms = sum(parts.values()) * 1e3
-    total_flops = fl * sites + sites * n_types * 3456 * (3 * 8 + 5 * np.log2(V)) + fields * 5 * np.log2(V)
+    total_flops = fl * sites + sites * stored * (3 * 8 + 5 * np.log2(V)) + fields * 5 * np.log2(V)
     leg = {
         "workload": label, "lattice": list(L), "T": T, "slices": tc, "channels": len(chans),
         "sites_per_step": sites, "ms_per_step": ms_step, "value": sites * len(chans) / (ms_step * 1e-3),

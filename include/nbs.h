@@ -259,9 +259,13 @@ nbs_status nbs_plan_diagrams(const nbs_plan plan, int32_t ch, nbs_diagram_t* out
 /* Copy one table of the compiled structure-of-arrays program (the tables
  * the kernels interpret; Sec. 4(ii)-(iii) ship such tables to the device)
  * into buf.  int32 tables: "op_code", "op_nterm", "op_term_trip",
- * "op_term_perm", "group_op1", "group_op2", "group_prod", "group_task",
+ * "op_term_perm", "op_pair" (s1 | s2 << 2 of the slot pair a block is
+ * stored antisymmetrised and packed in, or -1), "op_alias", "group_op1",
+ * "group_op2", "group_op1_iso", "group_op2_iso", "group_prod", "group_task",
  * "group_ch", "group_channels", "ch_contrib", "contrib_prod", "prod_desc",
- * "task_lanes"; double tables: "contrib_coef", "op_term_w".  *n gets the
+ * "task_lanes", "seg_task", "group_stask", "prod_ext", "contrib_ext";
+ * double tables: "contrib_coef", "op_term_w", "op_alias_coef",
+ * "contrib_coef_iso".  *n gets the
  * element count; at most cap elements are written.  Unknown name:
  * NBS_ERR_INVALID.  Layouts are described in the compiler's header. */
 nbs_status nbs_plan_table(const nbs_plan plan, const char* name, void* buf, int64_t cap, int64_t* n);

@@ -89,8 +89,21 @@ __global__ void k_channel_scale(const int* exps, const int* chan_nf, double* osc
 //   N_op[al][j0][j1][j2] = sum_k w_k sum_c D_k[c][i0][i1] S_{f3,k}[(al,c)][i2],
 //   (i0, i1, i2) = (j_pi(0), j_pi(1), j_pi(2)),
 // (the Lambda and Sigma0 blocks as combinations of the X_u, X_d, X_s blocks,
-// Sec. 4(i)) is written as 3456 contiguous complex values.
+// Sec. 4(i)) is written in the block layout of BlockLayout: operators with
+// a same-flavour slot pair antisymmetrised in it and packed (1584 complex
+// per site), the others whole (3456).
 // ---------------------------------------------------------------------------
+// Index p of the pair (a, b), a < b, of 12 x 12, and its inverse: the 66
+// pairs as 6 rows of 11, row r holding (r, r + 1 .. 11) and then
+// (11 - r, 12 - r .. 11), so that decoding takes one division.
+__host__ __device__ inline int pair_index(int a, int b) { return a < 6 ? 11 * a + (b - a - 1) : 11 * (11 - a) + (b - 1); }
+__host__ __device__ inline void pair_decode(int p, int& a, int& b) {
+  const int r = p / 11, c = p - 11 * r;
+  const bool first = c < 11 - r;
+  a = first ? r : 11 - r;
+  b = first ? r + 1 + c : c + 1;
+}
+
 template <typename Tin, typename T>
 __global__ __launch_bounds__(kThreads) void k_nbb(NbbArgs a) {
   __shared__ cx<T> S[3][144];
@@ -134,9 +147,9 @@ __global__ __launch_bounds__(kThreads) void k_nbb(NbbArgs a) {
   }
   __syncthreads();
   for (int op = 0; op < a.n_ops; ++op) {
-    cx<T>* out = reinterpret_cast<cx<T>*>(a.Nq) + ((long long)(op * a.t_count + t) * a.V + site) * kBlockEntries;
+    cx<T>* out = reinterpret_cast<cx<T>*>(a.Nq) + block_offset(a.lay, op, a.t_count, t, a.V, site);
     const int nt = a.op_nterm[op];
-    const int pair = a.op_pair[op];
+    const int pair = a.lay.pair[op];
     // N_op[al][j0][j1][j2]
     auto pick = [](int m, int j0, int j1, int j2) { return m == 0 ? j0 : (m == 1 ? j1 : j2); };
     auto entry = [&](int al, int j0, int j1, int j2) {
@@ -156,8 +169,29 @@ __global__ __launch_bounds__(kThreads) void k_nbb(NbbArgs a) {
       }
       return v;
     };
-    for (int o = threadIdx.x; o < kBlockEntries; o += kThreads) {
-      const int al = o / 1728, j0 = (o / 144) % 12, j1 = (o / 12) % 12, j2 = o % 12;
+    const int ne = a.lay.ne[op];
+    for (int o = threadIdx.x; o < ne; o += kThreads) {
+      int al, j0, j1, j2;
+      if (pair < 0) {
+        al = o / 1728;
+        j0 = (o / 144) % 12;
+        j1 = (o / 12) % 12;
+        j2 = o % 12;
+      } else {
+        // packed: (al, j_s3, pair index of j_s1 < j_s2)
+        const int s1 = pair & 3, s2 = (pair >> 2) & 3;
+        al = o / 792;
+        const int r = o - 792 * al, js3 = r / 66;
+        int pa, pb;
+        pair_decode(r - 66 * js3, pa, pb);
+        int j[3];
+        j[3 - s1 - s2] = js3;
+        j[s1] = pa;
+        j[s2] = pb;
+        j0 = j[0];
+        j1 = j[1];
+        j2 = j[2];
+      }
       cx<T> v = entry(al, j0, j1, j2);
       if (pair >= 0) {
         // antisymmetrised in the same-flavour slot pair: N - N(s1 <-> s2)
@@ -443,6 +477,42 @@ __device__ __forceinline__ int part_term(int in, int lone, int x, int al, int t,
 __device__ __forceinline__ int lds_index(int i) {
   const int al = i / 1728, j0 = (i / 144) % 12, j1 = (i / 12) % 12, j2 = i % 12;
   return al * kLdsAl + j0 * kLdsJ0 + j1 * kLdsJ1 + j2;
+}
+
+// Entry i of an operator's stored block (BlockLayout) written into a staged
+// block in LDS: unpacked entries at their place; a packed entry (pair
+// (s1, s2), j_s1 < j_s2) at (j_s1, j_s2) and negated at (j_s2, j_s1).
+template <typename T> __device__ __forceinline__ void put_entry(cx<T>* slot, int pair, int i, cx<T> v) {
+  if (pair < 0) {
+    slot[lds_index(i)] = v;
+    return;
+  }
+  const int s1 = pair & 3, s2 = (pair >> 2) & 3;
+  const int al = i / 792, r = i - 792 * al, js3 = r / 66;
+  int a, b;
+  pair_decode(r - 66 * js3, a, b);
+  int j[3];
+  j[3 - s1 - s2] = js3;
+  j[s1] = a;
+  j[s2] = b;
+  slot[al * kLdsAl + j[0] * kLdsJ0 + j[1] * kLdsJ1 + j[2]] = v;
+  j[s1] = b;
+  j[s2] = a;
+  slot[al * kLdsAl + j[0] * kLdsJ0 + j[1] * kLdsJ1 + j[2]] = cx<T>{-v.re, -v.im};
+}
+
+// The 288 entries with j_s1 = j_s2 of a staged packed block are zero.
+template <typename T> __device__ __forceinline__ void zero_pair_diagonal(cx<T>* slot, int pair, int tid, int nt) {
+  if (pair < 0) return;
+  const int s1 = pair & 3, s2 = (pair >> 2) & 3;
+  for (int k = tid; k < 288; k += nt) {
+    const int al = k / 144, js3 = (k / 12) % 12, a = k % 12;
+    int j[3];
+    j[3 - s1 - s2] = js3;
+    j[s1] = a;
+    j[s2] = a;
+    slot[al * kLdsAl + j[0] * kLdsJ0 + j[1] * kLdsJ1 + j[2]] = cx<T>{0, 0};
+  }
 }
 
 __device__ __forceinline__ int pick6(int m, int j0, int j1, int j2, int j3, int j4, int j5) {
@@ -1153,8 +1223,15 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
   // stage the two operator blocks, the group's channel contributions and
   // the pair table
   const cx<T>* Nq = reinterpret_cast<const cx<T>*>(G.Nq);
-  const cx<T>* srcA = Nq + ((long long)(A.group_op1[g] * G.t_count + t) * G.V + q) * kBlockEntries;
-  const cx<T>* srcB = Nq + ((long long)(A.group_op2[g] * G.t_count + t) * G.V + mq) * kBlockEntries;
+  // first entry of operator op's block at site (A lives in the constant
+  // address space, so the layout is read field by field)
+  auto boff = [&](int op, int site) {
+    return (long long)A.lay.cum[op] * G.t_count * G.V + ((long long)t * G.V + site) * A.lay.ne[op];
+  };
+  const cx<T>* srcA = Nq + boff(A.group_op1[g], q);
+  const cx<T>* srcB = Nq + boff(A.group_op2[g], mq);
+  const int neA = A.lay.ne[A.group_op1[g]], neB = A.lay.ne[A.group_op2[g]];
+  const int prA = A.lay.pair[A.group_op1[g]], prB = A.lay.pair[A.group_op2[g]];
   constexpr int kPer = (kBlockEntries + kContractThreads - 1) / kContractThreads;
   const int gc0 = A.group_ch[g], nch = A.group_ch[g + 1] - gc0;
   const int cbase = A.ch_contrib[gc0], ncon = A.ch_contrib[gc0 + nch] - cbase;
@@ -1173,9 +1250,14 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       const int i = tid + k * kContractThreads;
-      const int ii = i < kBlockEntries ? i : kBlockEntries - 1;
-      if constexpr (kA) va[k] = cx<T>{gA[ii].re, gA[ii].im};
-      if constexpr (kB) vb[k] = cx<T>{gB[ii].re, gB[ii].im};
+      if constexpr (kA) {
+        const int ii = i < neA ? i : neA - 1;
+        va[k] = cx<T>{gA[ii].re, gA[ii].im};
+      }
+      if constexpr (kB) {
+        const int ii = i < neB ? i : neB - 1;
+        vb[k] = cx<T>{gB[ii].re, gB[ii].im};
+      }
     }
     const bool has_con = tid < ncon;
     const int cw = has_con ? A.contrib_prod[cbase + tid] : 0;
@@ -1192,11 +1274,13 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       const int i = tid + k * kContractThreads;
-      if (i < kBlockEntries) {
-        if constexpr (kA) slotA[lds_index(i)] = va[k];
-        if constexpr (kB) slotB[lds_index(i)] = vb[k];
-      }
+      if constexpr (kA)
+        if (i < neA) put_entry(slotA, prA, i, va[k]);
+      if constexpr (kB)
+        if (i < neB) put_entry(slotB, prB, i, vb[k]);
     }
+    if constexpr (kA) zero_pair_diagonal(slotA, prA, tid, kContractThreads);
+    if constexpr (kB) zero_pair_diagonal(slotB, prB, tid, kContractThreads);
     if (has_con) {
       cword[tid] = cw;
       ccoef[tid] = (T)cc;
@@ -1226,25 +1310,34 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
     constexpr int NTH = decltype(nthreads)::value;
     constexpr int kP = (kBlockEntries + NTH - 1) / NTH;
     using gptr = const __attribute__((address_space(1))) cx<T>*;
-    const gptr gA = (gptr)(Nq + ((long long)(A.group_op1[gg] * G.t_count + t) * G.V + q) * kBlockEntries);
-    const gptr gB = (gptr)(Nq + ((long long)(A.group_op2[gg] * G.t_count + t) * G.V + mq) * kBlockEntries);
+    const gptr gA = (gptr)(Nq + boff(A.group_op1[gg], q));
+    const gptr gB = (gptr)(Nq + boff(A.group_op2[gg], mq));
+    const int nA = A.lay.ne[A.group_op1[gg]], nB = A.lay.ne[A.group_op2[gg]];
+    const int pA = A.lay.pair[A.group_op1[gg]], pB = A.lay.pair[A.group_op2[gg]];
     const int lt = tid - first;
     cx<T> va[kA ? kP : 1], vb[kB ? kP : 1];
 #pragma unroll
     for (int k = 0; k < kP; ++k) {
       const int i = lt + k * NTH;
-      const int ii = i < kBlockEntries ? i : kBlockEntries - 1;
-      if constexpr (kA) va[k] = cx<T>{gA[ii].re, gA[ii].im};
-      if constexpr (kB) vb[k] = cx<T>{gB[ii].re, gB[ii].im};
+      if constexpr (kA) {
+        const int ii = i < nA ? i : nA - 1;
+        va[k] = cx<T>{gA[ii].re, gA[ii].im};
+      }
+      if constexpr (kB) {
+        const int ii = i < nB ? i : nB - 1;
+        vb[k] = cx<T>{gB[ii].re, gB[ii].im};
+      }
     }
 #pragma unroll
     for (int k = 0; k < kP; ++k) {
       const int i = lt + k * NTH;
-      if (i < kBlockEntries) {
-        if constexpr (kA) slotA[lds_index(i)] = va[k];
-        if constexpr (kB) slotB[lds_index(i)] = vb[k];
-      }
+      if constexpr (kA)
+        if (i < nA) put_entry(slotA, pA, i, va[k]);
+      if constexpr (kB)
+        if (i < nB) put_entry(slotB, pB, i, vb[k]);
     }
+    if constexpr (kA) zero_pair_diagonal(slotA, pA, lt, NTH);
+    if constexpr (kB) zero_pair_diagonal(slotB, pB, lt, NTH);
   };
   auto stage_blocks_of = [&](int gg, int first, auto nthreads) {
     const bool nA = gg == gbeg || A.group_op1[gg] != A.group_op1[gg - 1];
@@ -1730,27 +1823,70 @@ __device__ __forceinline__ int chunk_lds_base(int c) {
 template <typename T, int NT> struct BlockRegs {
   static constexpr int kCh = (kBlockChunks + NT - 1) / NT;
   cx<T> v[kCh][4];
-  __device__ __forceinline__ void load(const cx<T>* src, int tid) {
+  int nch = 0, pair = -1;  // chunks of the stored block, its packed pair
+  // ne entries (kBlockEntries, or kPackedEntries for a packed block with
+  // pair pr) from HBM, four consecutive per chunk
+  __device__ __forceinline__ void load(const cx<T>* src, int ne, int pr, int tid) {
     using gptr = const __attribute__((address_space(1))) cx<T>*;
     const gptr g = (gptr)src;
+    // uniform over the workgroup: scalar registers
+    nch = __builtin_amdgcn_readfirstlane(ne / 4);
+    pair = __builtin_amdgcn_readfirstlane(pr);
 #pragma unroll
     for (int k = 0; k < kCh; ++k) {
       const int c = tid + k * NT;
-      const int cc = c < kBlockChunks ? c : kBlockChunks - 1;
+      const int cc = c < nch ? c : nch - 1;
 #pragma unroll
       for (int e = 0; e < 4; ++e) v[k][e] = cx<T>{g[4 * cc + e].re, g[4 * cc + e].im};
     }
   }
+  // into a staged block in LDS (a packed block unpacked, its diagonal zeroed)
   __device__ __forceinline__ void store(cx<T>* slot, int tid) const {
+    if (pair < 0) {
+#pragma unroll
+      for (int k = 0; k < kCh; ++k) {
+        const int c = tid + k * NT;
+        if (c < nch) {
+          const int b = chunk_lds_base(c);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) slot[b + e] = v[k][e];
+        }
+      }
+      return;
+    }
+    const int s1 = pair & 3, s2 = (pair >> 2) & 3, s3 = 3 - s1 - s2;
+    const int u1 = s1 == 0 ? kLdsJ0 : s1 == 1 ? kLdsJ1 : 1, u2 = s2 == 0 ? kLdsJ0 : s2 == 1 ? kLdsJ1 : 1;
+    const int u3 = s3 == 0 ? kLdsJ0 : s3 == 1 ? kLdsJ1 : 1;
 #pragma unroll
     for (int k = 0; k < kCh; ++k) {
       const int c = tid + k * NT;
-      if (c < kBlockChunks) {
-        const int b = chunk_lds_base(c);
+      if (c < nch) {
+        // the chunk's first entry decoded once, then stepped
+        const int i = 4 * c;
+        const int al = i / 792, r0 = i - 792 * al;
+        int j3 = r0 / 66, p = r0 - 66 * j3;
+        int base = al * kLdsAl + j3 * u3;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) slot[b + e] = v[k][e];
+        for (int e = 0; e < 4; ++e) {
+          int pa, pb;
+          pair_decode(p, pa, pb);
+          const cx<T> x = v[k][e];
+          slot[base + pa * u1 + pb * u2] = x;
+          slot[base + pb * u1 + pa * u2] = cx<T>{-x.re, -x.im};
+          if (++p == 66) {
+            // the next j_s3, or after j_s3 = 11 the next al
+            p = 0;
+            if (++j3 == 12) {
+              j3 = 0;
+              base += kLdsAl - 11 * u3;
+            } else {
+              base += u3;
+            }
+          }
+        }
       }
     }
+    zero_pair_diagonal(slot, pair, tid, NT);
   }
 };
 
@@ -1841,15 +1977,14 @@ template <typename T, int NT> __device__ __forceinline__ void contract_seg_item(
   const int tid = threadIdx.x, lane = tid & 63;
   const cx<T>* Nq = reinterpret_cast<const cx<T>*>(G.Nq);
   const int gbeg = a.gchunk[chunk], gend = a.gchunk[chunk + 1];
-  auto block_src = [&](int op, int qq) {
-    return Nq + ((long long)(op * G.t_count + t) * G.V + qq) * kBlockEntries;
-  };
+  auto block_src = [&](int op, int qq) { return Nq + block_offset(a.lay, op, G.t_count, t, G.V, qq); };
   // the first group's blocks and tables
   {
     BlockRegs<T, NT> ra, rb;
     GroupTables<T, NT> tg;
-    ra.load(block_src(a.group_op1[gbeg], q), tid);
-    rb.load(block_src(a.group_op2[gbeg], mq), tid);
+    const int op1 = a.group_op1[gbeg], op2 = a.group_op2[gbeg];
+    ra.load(block_src(op1, q), a.lay.ne[op1], a.lay.pair[op1], tid);
+    rb.load(block_src(op2, mq), a.lay.ne[op2], a.lay.pair[op2], tid);
     tg.load(a, gbeg, tid);
     ra.store(slotA, tid);
     rb.store(slotB, tid);
@@ -1867,10 +2002,14 @@ template <typename T, int NT> __device__ __forceinline__ void contract_seg_item(
     const bool nA = more && a.group_op1[g + 1] != a.group_op1[g];
     const bool nB = more && a.group_op2[g + 1] != a.group_op2[g];
     BlockRegs<T, NT> pf;
+    auto load_next = [&](BlockRegs<T, NT>& r, bool side_a) {
+      const int op = side_a ? a.group_op1[g + 1] : a.group_op2[g + 1];
+      r.load(block_src(op, side_a ? q : mq), a.lay.ne[op], a.lay.pair[op], tid);
+    };
     if (nA)
-      pf.load(block_src(a.group_op1[g + 1], q), tid);
+      load_next(pf, true);
     else if (nB)
-      pf.load(block_src(a.group_op2[g + 1], mq), tid);
+      load_next(pf, false);
     using Tables = GroupTables<T, NT>;
     Tables tn;
     if (Tables::kRegs && more) tn.load(a, g + 1, tid);
@@ -1946,7 +2085,7 @@ template <typename T, int NT> __device__ __forceinline__ void contract_seg_item(
       pf.store(slotA, tid);
       if (nB) {
         BlockRegs<T, NT> rb;
-        rb.load(block_src(a.group_op2[g + 1], mq), tid);
+        load_next(rb, false);
         rb.store(slotB, tid);
       }
     } else if (nB) {
@@ -2023,8 +2162,8 @@ template <> __global__ __launch_bounds__(512, 4) void k_contract_seg<float, 512,
 template <typename T>
 __global__ __launch_bounds__(64) void k_two_point(TwoPointArgs a) {
   const int k = blockIdx.x, t = blockIdx.y, lane = threadIdx.x;
-  const cx<T>* N = reinterpret_cast<const cx<T>*>(a.Nq) +
-                   (long long)(a.slot[k] * a.t_count + t) * a.V * kBlockEntries;  // q = 0
+  const int slot = a.slot[k], pair = a.lay.pair[slot];
+  const cx<T>* N = reinterpret_cast<const cx<T>*>(a.Nq) + block_offset(a.lay, slot, a.t_count, t, a.V, 0);  // q = 0
   double acc[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) acc[i] = 0.0;
@@ -2034,11 +2173,21 @@ __global__ __launch_bounds__(64) void k_two_point(TwoPointArgs a) {
     int j[3] = {0, 0, 0};
     const int c = part_term(3, -1, 0, ap, s, j[0], j[1], j[2]);
     const int mp = a.term_map[k][term];
-    const int idx = (j[mp & 3] * 12 + j[(mp >> 2) & 3]) * 12 + j[(mp >> 4) & 3];
-    const double w = a.term_coef[k][term] * c;
+    const int jj[3] = {j[mp & 3], j[(mp >> 2) & 3], j[(mp >> 4) & 3]};
+    // the stored entry: whole blocks at (j0, j1, j2); packed blocks at the
+    // ordered pair, negated for j_s1 > j_s2, zero for j_s1 = j_s2
+    int idx = (jj[0] * 12 + jj[1]) * 12 + jj[2], stride = 1728;
+    double w = a.term_coef[k][term] * c;
+    if (pair >= 0) {
+      const int s1 = pair & 3, s2 = (pair >> 2) & 3, pa = jj[s1], pb = jj[s2];
+      if (pa == pb) w = 0.0;
+      if (pa > pb) w = -w;
+      idx = pa == pb ? 0 : jj[3 - s1 - s2] * 66 + (pa < pb ? pair_index(pa, pb) : pair_index(pb, pa));
+      stride = 792;
+    }
 #pragma unroll
     for (int al = 0; al < 2; ++al) {
-      const cx<T> v = N[al * 1728 + idx];
+      const cx<T> v = N[al * stride + idx];
       acc[4 * al + 2 * ap] = fma(w, (double)v.re, acc[4 * al + 2 * ap]);
       acc[4 * al + 2 * ap + 1] = fma(w, (double)v.im, acc[4 * al + 2 * ap + 1]);
     }

@@ -11,17 +11,37 @@ constexpr int kThreads = 256;
 // Operator blocks (Eq. (5)/(8) combined per Eqs. (2)-(3)) of every sink
 // operator: N_op[al][j0][j1][j2] = sum_k w_k N_{trip_k}[al][j_pi(0)][j_pi(1)][j_pi(2)].
 constexpr int kMaxOps = 11;
+
+// Operator blocks in HBM.  An operator with a same-flavour slot pair
+// (s1, s2) is stored antisymmetrised in that pair (N - N with the two slot
+// indices exchanged) and packed: only the entries with j_s1 < j_s2, as
+// [al][j_s3][p], p the index of the pair (j_s1, j_s2) among the 66 (six
+// rows of eleven: row r holds (r, r + 1 .. 11) then (11 - r, 12 - r .. 11)),
+// kPackedEntries complex per site (the others are zero or negated copies).  Operators without a pair are stored
+// as [al][j0][j1][j2], kBlockEntries complex per site.  Per geometry the
+// blocks of operator op start at cum[op] * t_count * V entries and hold
+// [t][site][ne[op]].
+constexpr int kPackedEntries = 2 * 12 * 66;
+struct BlockLayout {
+  int ne[kMaxOps];    // entries per site: kBlockEntries or kPackedEntries
+  int cum[kMaxOps];   // sum of ne over the earlier operators
+  int pair[kMaxOps];  // s1 | s2 << 2 of the stored antisymmetrised pair, or -1
+};
+// first entry of the block of operator op, slice t (of t_count), site
+__host__ __device__ inline long long block_offset(const BlockLayout& b, int op, int t_count, int t, long long V,
+                                                  long long site) {
+  return (long long)b.cum[op] * t_count * V + ((long long)t * V + site) * b.ne[op];
+}
+
 struct NbbArgs {
   const void* S[3];      // u, d, s propagators: [t_count][V][12][12]
-  void* Nq;              // [n_ops][t_count][V][3456]
+  void* Nq;              // operator blocks, BlockLayout
   int V, t_count, n_ops;
   int n_dq, dq_f1[4], dq_f2[4];    // diquark flavour pairs
   int op_nterm[kMaxOps];
   int op_dq[kMaxOps][3], op_f3[kMaxOps][3], op_perm[kMaxOps][3];  // perm: pi(0) | pi(1) << 2 | pi(2) << 4
   double op_w[kMaxOps][3];
-  // s1 | s2 << 2: the block is stored antisymmetrised in slots s1, s2
-  // (N - N with the two slot indices exchanged); -1: stored as is
-  int op_pair[kMaxOps];
+  BlockLayout lay;
   int flavour_used[3];
   const int* scale_exp;  // [3][t_count] power-of-two exponents (precision form) or null
   unsigned* nonfinite;   // set to 1 when a propagator entry read is NaN or infinite
@@ -81,7 +101,7 @@ constexpr int kSegC144 = 0, kSegC9 = 1, kSegC36 = 2, kSegC1 = 3, kSegIdle = 15;
 // first (slice, momentum) pair: geometry i owns the pairs [block0, block0 +
 // V * t_count), in geometry order.
 struct ContractGeom {
-  const void* Nq;  // [n_ops][t_count][V][3456]
+  const void* Nq;  // operator blocks, BlockLayout
   void* Ft;        // [n_ch][t_count][16][V]
   int V, Lx, Ly, Lz, t_count, pad;
   long long block0;
@@ -118,6 +138,7 @@ struct ContractArgs {
   int persistent;
   unsigned* queue;
   long long block0, n_chunk;  // logical workgroups [block0, block0 + n_chunk) in this launch
+  BlockLayout lay;
 };
 
 // Zero-momentum single-baryon two-point functions of one geometry: pair k
@@ -129,7 +150,8 @@ struct ContractArgs {
 // C[k][t][a][a'].
 constexpr int kMaxTwoPointPairs = 8, kMaxTwoPointTerms = 18;
 struct TwoPointArgs {
-  const void* Nq;
+  const void* Nq;  // operator blocks, BlockLayout
+  BlockLayout lay;
   void* C;
   const int* exps;
   int V, t_count, n_pairs;

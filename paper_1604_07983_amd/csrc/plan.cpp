@@ -30,7 +30,7 @@ enum Stage { ST_NEW = 0, ST_BUILT = 1, ST_CONTRACTED = 2 };
 struct GeomWork {
   nbs_geometry g{};
   long long V = 0;
-  void* Nq = nullptr;          // [n_ops][t_count][V][3456] blocks, then N~(q) in place
+  void* Nq = nullptr;          // operator blocks (nbs::BlockLayout), then N~(q) in place
   void* Ft = nullptr;          // [n_ch][t_count][16][V] F~_c(q)
   unsigned* maxbits = nullptr; // precision form: [3][t_count] max |Re|, |Im| as float bits
   int* exps = nullptr;         // precision form: [3][t_count] power-of-two exponents
@@ -86,6 +86,8 @@ struct nbs_plan_s {
   std::map<std::string, size_t> prog_off;  // table name -> offset (ints) into prog
   nbs::NbbArgs nbb{};                      // geometry-independent part
   nbs::ContractArgs con{};
+  nbs::BlockLayout lay{};                  // operator blocks in HBM
+  long long lay_entries = 0;               // entries per site over all operators
   // captured launch sequence (nbs_run_graph)
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -353,6 +355,7 @@ nbs_status compile_and_upload(nbs_plan p) {
   c.max_gslots = std::max(1, P.max_group_slots);
   c.max_gstask = std::max(1, P.max_group_stasks);
   c.waves = c.engine == 1 ? p->tune.seg_waves : p->tune.waves;
+  c.lay = p->lay;
   c.persistent = c.engine == 1 ? p->tune.persist : 0;
   c.queue = p->queue;
   // result slots spaced kSegRStride apart where the LDS allows it
@@ -376,6 +379,20 @@ bool isospin_limit(nbs_plan p, const void* const* pu, const void* const* pd) {
   for (size_t i = 0; i < p->gw.size(); ++i)
     if (pu[i] != pd[i]) return false;
   return true;
+}
+
+// Forward transform of the first n_build operators' blocks of one geometry,
+// operator by operator (each [t][site][ne] with its own field count).
+nbs_status transform_blocks(nbs_plan p, GeomWork& w, int n_build, hipStream_t st) {
+  const int kind = p->prec == NBS_FP64 ? 0 : 1;
+  const size_t el = p->prec == NBS_FP64 ? 16 : 8;
+  for (int op = 0; op < n_build; ++op) {
+    char* base = (char*)w.Nq + (size_t)p->lay.cum[op] * w.g.t_count * w.V * el;
+    const nbs_status s =
+        fft3d(p, kind, kind, base, base, (long long)w.g.t_count, w.g.L, p->lay.ne[op], -1, nullptr, 1, 1.0, st);
+    if (s != NBS_OK) return s;
+  }
+  return NBS_OK;
 }
 
 nbs_status enqueue_build(nbs_plan p, const void* const* pu, const void* const* pd, const void* const* ps,
@@ -413,10 +430,7 @@ nbs_status enqueue_build(nbs_plan p, const void* const* pu, const void* const* p
       a.scale_exp = w.exps;
     }
     if ((s = hip_check(p, nbs::launch_nbb(p->prec, a, st), "nbb")) != NBS_OK) return s;
-    const int kind = p->prec == NBS_FP64 ? 0 : 1;
-    s = fft3d(p, kind, kind, w.Nq, w.Nq, (long long)g.t_count * n_build, g.L, nbs::kBlockEntries, -1, nullptr, 1,
-              1.0, st);
-    if (s != NBS_OK) return s;
+    if ((s = transform_blocks(p, w, n_build, st)) != NBS_OK) return s;
   }
   return NBS_OK;
 }
@@ -580,11 +594,22 @@ nbs_status create_plan(nbs_plan* out, const nbs_geometry* g, int32_t n_geom, con
   const int nt = P.n_ops;
   if (nt > nbs::kMaxOps) { delete p; return NBS_ERR_UNSUPPORTED; }
   // diquark flavour pairs and per-operator recipes for the NBB kernel
+  // block layout: operators with a stored antisymmetrised pair packed
+  {
+    int cum = 0;
+    for (int s = 0; s < nt; ++s) {
+      p->lay.pair[s] = P.op_pair[s];
+      p->lay.ne[s] = P.op_pair[s] >= 0 ? nbs::kPackedEntries : nbs::kBlockEntries;
+      p->lay.cum[s] = cum;
+      cum += p->lay.ne[s];
+    }
+    p->lay_entries = cum;
+  }
   nbs::NbbArgs& nb = p->nbb;
+  nb.lay = p->lay;
   std::map<int, int> dq;
   for (int s = 0; s < nt; ++s) {
     nb.op_nterm[s] = P.op_nterm[s];
-    nb.op_pair[s] = P.op_pair[s];
     for (int k = 0; k < P.op_nterm[s]; ++k) {
       const int code = P.op_term_trip[3 * s + k];
       const int f1 = code / 9, f2 = (code / 3) % 3, f3 = code % 3;
@@ -611,7 +636,7 @@ nbs_status create_plan(nbs_plan* out, const nbs_geometry* g, int32_t n_geom, con
   size_t need = (1 << 22);
   long long n_qt = 0;
   for (auto& w : p->gw) {
-    need += (size_t)w.g.t_count * nt * w.V * nbs::kBlockEntries * el + (size_t)n_ch * w.g.t_count * 16 * w.V * el;
+    need += (size_t)w.g.t_count * p->lay_entries * w.V * el + (size_t)n_ch * w.g.t_count * 16 * w.V * el;
     n_qt += w.V * w.g.t_count;
   }
   if (!p->arena) {
@@ -633,7 +658,7 @@ nbs_status create_plan(nbs_plan* out, const nbs_geometry* g, int32_t n_geom, con
   };
   for (auto& w : p->gw) {
     const int tc = w.g.t_count;
-    if ((s = dev_alloc(p, (size_t)tc * nt * w.V * nbs::kBlockEntries * el, &w.Nq, &countdown)) != NBS_OK ||
+    if ((s = dev_alloc(p, (size_t)tc * p->lay_entries * w.V * el, &w.Nq, &countdown)) != NBS_OK ||
         (s = dev_alloc(p, (size_t)n_ch * tc * 16 * w.V * el, &w.Ft, &countdown)) != NBS_OK)
       return bail(s);
     if ((s = dev_alloc(p, 3 * tc * 4, &tmp, &countdown)) != NBS_OK) return bail(s);
@@ -773,6 +798,7 @@ nbs_status nbs_two_point(nbs_plan p, const nbs_baryon_pair* pairs, int32_t n_pai
   if (!ptrs_ok(C_out, p->gw.size())) return fail(p, NBS_ERR_INVALID, "null output pointer");
   const auto& P = p->comp.prog;
   nbs::TwoPointArgs a{};
+  a.lay = p->lay;
   a.n_pairs = n_pairs;
   for (int k = 0; k < n_pairs; ++k) {
     const int sink = pairs[k].sink, src = pairs[k].src;
@@ -900,9 +926,7 @@ nbs_status nbs_plan_autotune(nbs_plan p, const void* const* prop_u, const void* 
     float ms = 0;
     s = timed([&]() {
       for (auto& w : p->gw) {
-        const int kind = p->prec == NBS_FP64 ? 0 : 1;
-        nbs_status r = fft3d(p, kind, kind, w.Nq, w.Nq, (long long)w.g.t_count * p->comp.prog.n_ops, w.g.L,
-                             nbs::kBlockEntries, -1, nullptr, 1, 1.0, st);
+        nbs_status r = transform_blocks(p, w, p->comp.prog.n_ops, st);
         if (r != NBS_OK) return r;
       }
       return NBS_OK;
