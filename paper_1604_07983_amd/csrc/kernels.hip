@@ -1840,8 +1840,10 @@ template <typename T, int NT> struct BlockRegs {
       for (int e = 0; e < 4; ++e) v[k][e] = cx<T>{g[4 * cc + e].re, g[4 * cc + e].im};
     }
   }
-  // into a staged block in LDS (a packed block unpacked, its diagonal zeroed)
-  __device__ __forceinline__ void store(cx<T>* slot, int tid) const {
+  // into a staged block in LDS (a packed block unpacked, its diagonal
+  // zeroed unless the slot's previous block was packed in the same pair:
+  // slot_pair tracks that, -2 at the start)
+  __device__ __forceinline__ void store(cx<T>* slot, int tid, int& slot_pair) const {
     if (pair < 0) {
 #pragma unroll
       for (int k = 0; k < kCh; ++k) {
@@ -1852,6 +1854,7 @@ template <typename T, int NT> struct BlockRegs {
           for (int e = 0; e < 4; ++e) slot[b + e] = v[k][e];
         }
       }
+      slot_pair = -1;
       return;
     }
     const int s1 = pair & 3, s2 = (pair >> 2) & 3, s3 = 3 - s1 - s2;
@@ -1886,7 +1889,8 @@ template <typename T, int NT> struct BlockRegs {
         }
       }
     }
-    zero_pair_diagonal(slot, pair, tid, NT);
+    if (slot_pair != pair) zero_pair_diagonal(slot, pair, tid, NT);
+    slot_pair = pair;
   }
 };
 
@@ -1978,6 +1982,8 @@ template <typename T, int NT> __device__ __forceinline__ void contract_seg_item(
   const cx<T>* Nq = reinterpret_cast<const cx<T>*>(G.Nq);
   const int gbeg = a.gchunk[chunk], gend = a.gchunk[chunk + 1];
   auto block_src = [&](int op, int qq) { return Nq + block_offset(a.lay, op, G.t_count, t, G.V, qq); };
+  // the packed pair of the block each slot holds (-1 whole, -2 none yet)
+  int pairA = -2, pairB = -2;
   // the first group's blocks and tables
   {
     BlockRegs<T, NT> ra, rb;
@@ -1986,8 +1992,8 @@ template <typename T, int NT> __device__ __forceinline__ void contract_seg_item(
     ra.load(block_src(op1, q), a.lay.ne[op1], a.lay.pair[op1], tid);
     rb.load(block_src(op2, mq), a.lay.ne[op2], a.lay.pair[op2], tid);
     tg.load(a, gbeg, tid);
-    ra.store(slotA, tid);
-    rb.store(slotB, tid);
+    ra.store(slotA, tid, pairA);
+    rb.store(slotB, tid, pairB);
     tg.store(a, tdesc, cword, cext, ccoef, coff, tid);
     if (tid == 0) *counter = 0;
   }
@@ -2082,14 +2088,14 @@ template <typename T, int NT> __device__ __forceinline__ void contract_seg_item(
     // the next group's block and tables (the channel sums read neither the
     // blocks, nor the descriptors, nor the other table set)
     if (nA) {
-      pf.store(slotA, tid);
+      pf.store(slotA, tid, pairA);
       if (nB) {
         BlockRegs<T, NT> rb;
         load_next(rb, false);
-        rb.store(slotB, tid);
+        rb.store(slotB, tid, pairB);
       }
     } else if (nB) {
-      pf.store(slotB, tid);
+      pf.store(slotB, tid, pairB);
     }
     if (more) {
       if (!Tables::kRegs) tn.load(a, g + 1, tid);
