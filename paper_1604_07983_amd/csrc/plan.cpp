@@ -204,7 +204,7 @@ int pick_ib(long long inner) {
 }
 
 // Launch the three axis passes of a batched 3-D transform on an array
-// [batch][Lz][Ly][Lx][inner0] (inner0 = 3456 for blocks, 1 for F).
+// [batch][Lz][Ly][Lx][inner0] (inner0 = an operator's block entries, 1 for F).
 nbs_status fft3d(nbs_plan p, int kind_first, int kind_rest, const void* in, void* out, long long batch,
                  const int L[3], long long inner0, int sign, const double* oscale, long long oscale_div,
                  double gscale, hipStream_t st) {
