@@ -65,16 +65,17 @@ def test_config2_fp64_16c32_all_channels():
     assert err.max() <= 1e-12, err
 
 
-@pytest.mark.parametrize("t_begin", [0, 62])
+@pytest.mark.parametrize("t_begin", [0, 30, 62])
 def test_config3_fp32_32c64_windows(t_begin):
-    """Precision form at 32^3, two-slice windows at both ends of T = 64 (the
-    latest slices decay by e^-(0.4*4+0.55*2)*63 ~ 1e-74 in some channels)."""
+    """Precision form at 32^3, two-slice windows at both ends and the middle
+    of T = 64 (slices 0, 1, 30, 31, 62, 63; the latest decay by
+    e^-(0.4*4+0.55*2)*63 ~ 1e-74 in some channels)."""
     announce("32^3 x 64 precision form window %d" % t_begin)
     L, T = (32, 32, 32), 64
     chans = channels.r52()
     props, Fg = run_window(L, T, binding.NBS_FP32_MFMA, t_begin, 2, chans)
     assert np.isfinite(Fg).all()
-    check_sampled_momenta(L, props, Fg, chans, slices=(1,), qs=((0, 0, 0), (3, 30, 7)), tol=1e-5)
+    check_sampled_momenta(L, props, Fg, chans, slices=(0, 1), qs=((0, 0, 0), (3, 30, 7)), tol=1e-5)
 
 
 def test_config3_fp32_32c64_bench_window():
