@@ -94,14 +94,21 @@ __global__ void k_channel_scale(const int* exps, const int* chan_nf, double* osc
 // per site), the others whole (3456).
 // ---------------------------------------------------------------------------
 // Index p of the pair (a, b), a < b, of 12 x 12, and its inverse: the 66
-// pairs as 6 rows of 11, row r holding (r, r + 1 .. 11) and then
-// (11 - r, 12 - r .. 11), so that decoding takes one division.
-__host__ __device__ inline int pair_index(int a, int b) { return a < 6 ? 11 * a + (b - a - 1) : 11 * (11 - a) + (b - 1); }
+// pairs by bands of equal difference d = b - a (d = 1 .. 11, a = 0 ..
+// 11 - d), band d starting at band_start(d) = (d - 1)(24 - d) / 2.  Along a
+// band both (a, b) and (b, a) move by one step of each index, so a staged
+// block is unpacked with additions only.
+__host__ __device__ inline int band_start(int d) { return (d - 1) * (24 - d) / 2; }
+__host__ __device__ inline int pair_index(int a, int b) { return band_start(b - a) + a; }
 __host__ __device__ inline void pair_decode(int p, int& a, int& b) {
-  const int r = p / 11, c = p - 11 * r;
-  const bool first = c < 11 - r;
-  a = first ? r : 11 - r;
-  b = first ? r + 1 + c : c + 1;
+  // the largest d with band_start(d) <= p, from the quadratic, then checked
+  int d = (int)((25.0f - sqrtf((float)(529 - 8 * p))) * 0.5f);
+  if (d < 1) d = 1;
+  if (d > 11) d = 11;
+  if (band_start(d) > p) --d;
+  if (d < 11 && band_start(d + 1) <= p) ++d;
+  a = p - band_start(d);
+  b = a + d;
 }
 
 template <typename Tin, typename T>
@@ -1864,27 +1871,41 @@ template <typename T, int NT> struct BlockRegs {
     for (int k = 0; k < kCh; ++k) {
       const int c = tid + k * NT;
       if (c < nch) {
-        // the chunk's first entry decoded once, then stepped
+        // the chunk's first entry decoded once, then stepped along its band
+        // of pairs (direct position (a, a + d), mirrored (a + d, a))
         const int i = 4 * c;
         const int al = i / 792, r0 = i - 792 * al;
-        int j3 = r0 / 66, p = r0 - 66 * j3;
+        int j3 = r0 / 66, pa, pb;
+        pair_decode(r0 - 66 * j3, pa, pb);
+        int d = pb - pa, left = 11 - pb;  // pairs after this one in its band
         int base = al * kLdsAl + j3 * u3;
+        const int uu = u1 + u2;
+        int od = base + pa * u1 + pb * u2, om = base + pb * u1 + pa * u2;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          int pa, pb;
-          pair_decode(p, pa, pb);
           const cx<T> x = v[k][e];
-          slot[base + pa * u1 + pb * u2] = x;
-          slot[base + pb * u1 + pa * u2] = cx<T>{-x.re, -x.im};
-          if (++p == 66) {
-            // the next j_s3, or after j_s3 = 11 the next al
-            p = 0;
-            if (++j3 == 12) {
-              j3 = 0;
-              base += kLdsAl - 11 * u3;
+          slot[od] = x;
+          slot[om] = cx<T>{-x.re, -x.im};
+          if (left > 0) {
+            od += uu;
+            om += uu;
+            --left;
+          } else {
+            if (d < 11) {
+              ++d;
             } else {
-              base += u3;
+              // the next j_s3, or after j_s3 = 11 the next al
+              d = 1;
+              if (++j3 == 12) {
+                j3 = 0;
+                base += kLdsAl - 11 * u3;
+              } else {
+                base += u3;
+              }
             }
+            od = base + d * u2;
+            om = base + d * u1;
+            left = 11 - d;
           }
         }
       }

@@ -15,9 +15,10 @@ constexpr int kMaxOps = 11;
 // Operator blocks in HBM.  An operator with a same-flavour slot pair
 // (s1, s2) is stored antisymmetrised in that pair (N - N with the two slot
 // indices exchanged) and packed: only the entries with j_s1 < j_s2, as
-// [al][j_s3][p], p the index of the pair (j_s1, j_s2) among the 66 (six
-// rows of eleven: row r holds (r, r + 1 .. 11) then (11 - r, 12 - r .. 11)),
-// kPackedEntries complex per site (the others are zero or negated copies).  Operators without a pair are stored
+// [al][j_s3][p], p the index of the pair (j_s1, j_s2) among the 66 (by
+// bands of equal difference j_s2 - j_s1 = 1 .. 11, ascending j_s1 within a
+// band), kPackedEntries complex per site (the others are zero or negated
+// copies).  Operators without a pair are stored
 // as [al][j0][j1][j2], kBlockEntries complex per site.  Per geometry the
 // blocks of operator op start at cum[op] * t_count * V entries and hold
 // [t][site][ne[op]].
