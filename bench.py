@@ -235,10 +235,7 @@ def plain_leg(args, name):
     fl, fl_sh, ebb, meb = contraction_work(r.plan)
     contract_ms = float(stage[:, 1].mean())
     el = 16 if prec == 0 else 8
-    # block passes of the build: normal blocks written; the fused x-y pass
-    # (when on and the plane is square) and the z pass each read and write
-    # them, else three line passes
-    passes = 1 + 2 * (2 if tune["fft_plane"] and L[0] == L[1] and prec == 0 else 3)
+    passes = 1 + 2 * transform_passes(tune, L)
     build_bytes = sites * (3 * 144 * el + stored * el * passes)
     blocks = sites * stored * el
     fields = sites * len(chans) * 16
@@ -549,6 +546,17 @@ def bench_slab96(args):
     }
     r.close()
     print(json.dumps(out), flush=True)
+
+
+def transform_passes(tune, L):
+    """HBM passes (one read and one write of the blocks each) of the forward
+    block transform: one for 8^3 and 16^3 cubes with the one-pass kernel on,
+    two with the fused x-y pass on a square plane, else three line passes."""
+    if tune["fft_cube"] and L[0] == L[1] == L[2] and L[0] in (8, 16):
+        return 1
+    if tune["fft_plane"] and L[0] == L[1] and L[0] in (8, 16, 24, 32, 40):
+        return 2
+    return 3
 
 
 def main():

@@ -169,8 +169,9 @@ nbs_status nbs_run_graph(nbs_plan plan, const void* const* prop_u, const void* c
                          const void* const* prop_s, void* const* F_out, void* stream);
 
 /* Measure launch-shape candidates on the device with the caller's
- * propagators and keep the fastest: for the block transforms, the fused x-y
- * pass over square planes, the register line kernel or LDS tiles of 512,
+ * propagators and keep the fastest: for the block transforms, the one-pass
+ * transform of 8^3 and 16^3 cubes, the fused x-y pass over square planes,
+ * the register line kernel or LDS tiles of 512,
  * 1024, 2048 or 4096 elements; for the contraction, the matrix-core
  * segment engine with 8 or 16 wavefronts per workgroup or the lane-team
  * engine (8 wavefronts in FP64, 4 in the precision form), then the ranges
@@ -183,7 +184,9 @@ nbs_status nbs_plan_autotune(nbs_plan plan, const void* const* prop_u, const voi
                              const void* const* prop_s, void* stream);
 
 /* The plan's launch shapes: out[0] bit 0 register line FFT on/off, bit 1
- * fused x-y pass for square planes on/off; out[1] LDS FFT tile elements;
+ * fused x-y pass for square planes on/off, bit 2 one pass for all three
+ * axes of 8^3 and 16^3 lattices on/off (on by default; the three choices
+ * give the same values bit for bit); out[1] LDS FFT tile elements;
  * out[2] wavefronts per contraction workgroup of the selected engine;
  * out[3] bit 4 the contraction engine (1: matrix-core segments, the
  * default in both forms; 0: lane teams), bits 2-3 the contraction
@@ -201,8 +204,8 @@ nbs_status nbs_plan_tuning(const nbs_plan plan, int32_t out[4]);
 /* Set the launch shapes (same encoding as nbs_plan_tuning) instead of
  * measuring them: waits for the plan's device work, recompiles the channel
  * program for the new shapes; blocks already built stay valid.  Rejects
- * (NBS_ERR_INVALID, the plan unchanged) unknown tiles, bits above bit 5 of
- * in[3], wavefront counts other than 8 / 16 (segment engine) or 8 (lane
+ * (NBS_ERR_INVALID, the plan unchanged) unknown tiles, bits above bit 2 of
+ * in[0] or bit 5 of in[3], wavefront counts other than 8 / 16 (segment engine) or 8 (lane
  * teams, FP64) or 4 / 8 (lane teams, precision form), matrix-core lane-team
  * products outside the precision form, group-range modes above 2 and the
  * persistent launch with the lane-team engine. */

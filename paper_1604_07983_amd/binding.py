@@ -234,7 +234,8 @@ class Plan:
     def tuning(self):
         out = (ctypes.c_int32 * 4)()
         self._check(lib().nbs_plan_tuning(self._h, out), "nbs_plan_tuning")
-        return {"fft_line": out[0] & 1, "fft_plane": (out[0] >> 1) & 1, "fft_tile": out[1], "waves": out[2],
+        return {"fft_line": out[0] & 1, "fft_plane": (out[0] >> 1) & 1, "fft_cube": (out[0] >> 2) & 1,
+                "fft_tile": out[1], "waves": out[2],
                 "split": out[3] & 1, "mfma": (out[3] >> 1) & 1, "gchunk": (out[3] >> 2) & 3,
                 "engine": (out[3] >> 4) & 1, "persist": (out[3] >> 5) & 1}
 
@@ -242,7 +243,8 @@ class Plan:
         """Change some launch shapes (keys as returned by tuning())."""
         t = self.tuning()
         t.update(kw)
-        arr = (ctypes.c_int32 * 4)(int(t["fft_line"]) | (int(t["fft_plane"]) << 1), int(t["fft_tile"]),
+        arr = (ctypes.c_int32 * 4)(int(t["fft_line"]) | (int(t["fft_plane"]) << 1) | (int(t["fft_cube"]) << 2),
+                                   int(t["fft_tile"]),
                                    int(t["waves"]),
                                    int(t["split"]) | (int(t["mfma"]) << 1) | (int(t["gchunk"]) << 2)
                                    | (int(t["engine"]) << 4) | (int(t["persist"]) << 5))

@@ -63,7 +63,9 @@ struct FftArgs {
 
 // The x and y axes of a batched transform in one pass: the array is
 // [planes][Ly][Lx][inner]; a workgroup transforms IB consecutive fields of
-// one plane through LDS.  in may equal out.
+// one plane through LDS.  The same arguments serve the one-pass transform
+// of cubic lattices, planes then counting cubes [Lz][Ly][Lx][inner].  in
+// may equal out.
 struct FftPlaneArgs {
   const void* in;
   void* out;
@@ -180,6 +182,10 @@ bool fft_line_supported(int n, int kind);
 // Square planes with a fused x-y kernel (forward transforms of the blocks,
 // kinds 0 and 1); fields per workgroup for an inner extent, 0 if none fits.
 int fft_plane_fields(int n, long long inner, int kind);
+// fields per workgroup of the one-pass transform of an n^3 cube (0: no
+// kernel for this length, storage kind or field count)
+int fft_cube_fields(int n, long long inner, int kind);
+hipError_t launch_fft_cube(int kind, int n, const FftPlaneArgs& a, hipStream_t st);
 hipError_t launch_fft_plane(int kind, int n, const FftPlaneArgs& a, hipStream_t st);
 hipError_t launch_fft_line(int kind, const FftArgs& a, hipStream_t st);
 size_t contract_lds_bytes(int prec, int max_gprod, int max_gcontrib, int max_gch, int max_gtask);

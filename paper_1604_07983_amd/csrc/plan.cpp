@@ -42,6 +42,7 @@ struct Tuning {
   int fft_tile = 1024;  // elements of an LDS tile of k_fft_pass (FP64 pairs)
   int fft_line = 1;     // 1: register line kernel where the length has one
   int fft_plane = 1;    // 1: fused x-y pass for square planes of the block transforms
+  int fft_cube = 1;     // 1: one pass for all three axes of cubic block transforms
   int split = 1;        // 1: compiler may split the walked index of a product over lanes
   int waves = 8;        // wavefronts per contraction workgroup
   int mfma = 0;         // precision form: 4 x 4-row products on matrix cores
@@ -210,6 +211,20 @@ nbs_status fft3d(nbs_plan p, int kind_first, int kind_rest, const void* in, void
                  double gscale, hipStream_t st) {
   const long long V = (long long)L[0] * L[1] * L[2];
   int ax0 = 0;
+  // cubic lattices of a forward block transform: all three axes in one pass
+  const int cib = p->tune.fft_cube && L[0] == L[1] && L[1] == L[2] && sign < 0 && oscale == nullptr &&
+                          gscale == 1.0 && kind_first == kind_rest
+                      ? nbs::fft_cube_fields(L[0], inner0, kind_first)
+                      : 0;
+  if (cib > 0) {
+    nbs::FftPlaneArgs ca{};
+    ca.in = in;
+    ca.out = out;
+    ca.planes = batch;
+    ca.inner = inner0;
+    ca.IB = cib;
+    return hip_check(p, nbs::launch_fft_cube(kind_first, L[0], ca, st), "fft cube");
+  }
   // square x-y planes of a forward block transform: both axes in one pass
   const int pib = p->tune.fft_plane && L[0] == L[1] && sign < 0 && oscale == nullptr && gscale == 1.0 &&
                           kind_first == kind_rest
@@ -555,8 +570,11 @@ nbs_status create_plan(nbs_plan* out, const nbs_geometry* g, int32_t n_geom, con
   // both forms; in the precision form two of them share a CU)
   p->tune.seg_waves = 8;
   // the fused x-y pass pays off for FP64 storage (128-byte runs in 64 KB
-  // tiles at 16^3); for complex64 the separate passes measured faster
+  // tiles at 16^3); for complex64 the separate passes measured faster at
+  // 32^3 and 40^3.  8^3 and 16^3 cubes take the one-pass transform in both
+  // forms (measured faster than either at 16^3).
   p->tune.fft_plane = prec == NBS_FP64 ? 1 : 0;
+  p->tune.fft_cube = 1;
   // matrix-core products are an autotuner candidate: measured slower than
   // the vector loops for these 4 x 4 products (a quad walks a product's
   // shared indices one step at a time, four times the steps of a lane team)
@@ -914,12 +932,14 @@ nbs_status nbs_plan_autotune(nbs_plan p, const void* const* prop_u, const void* 
   // 1. forward transforms: register line kernel or LDS tiles of 512 .. 4096
   //    elements (repeating the in-place transform only costs time; the blocks
   //    are rebuilt at the end)
-  struct FftChoice { int plane, line, tile; };
-  const FftChoice fft_cands[] = {{1, 1, 1024}, {0, 1, 1024}, {0, 0, 512}, {0, 0, 1024}, {0, 0, 2048}, {0, 0, 4096}};
+  struct FftChoice { int cube, plane, line, tile; };
+  const FftChoice fft_cands[] = {{1, 1, 1, 1024}, {0, 1, 1, 1024}, {0, 0, 1, 1024}, {0, 0, 0, 512},
+                                 {0, 0, 0, 1024}, {0, 0, 0, 2048}, {0, 0, 0, 4096}};
   float best_ms = 0;
   FftChoice best_fft = fft_cands[0];
   bool first = true;
   for (const auto& c : fft_cands) {
+    p->tune.fft_cube = c.cube;
     p->tune.fft_plane = c.plane;
     p->tune.fft_line = c.line;
     p->tune.fft_tile = c.tile;
@@ -934,6 +954,7 @@ nbs_status nbs_plan_autotune(nbs_plan p, const void* const* prop_u, const void* 
     if (s != NBS_OK) return finish(s);
     if (first || ms < best_ms) { best_ms = ms; best_fft = c; first = false; }
   }
+  p->tune.fft_cube = best_fft.cube;
   p->tune.fft_plane = best_fft.plane;
   p->tune.fft_line = best_fft.line;
   p->tune.fft_tile = best_fft.tile;
@@ -1004,7 +1025,7 @@ nbs_status nbs_plan_autotune(nbs_plan p, const void* const* prop_u, const void* 
 
 nbs_status nbs_plan_tuning(const nbs_plan p, int32_t out[4]) {
   if (!p || !out) return NBS_ERR_INVALID;
-  out[0] = p->tune.fft_line | (p->tune.fft_plane << 1);
+  out[0] = p->tune.fft_line | (p->tune.fft_plane << 1) | (p->tune.fft_cube << 2);
   out[1] = p->tune.fft_tile;
   out[2] = p->tune.engine == 1 ? p->tune.seg_waves : p->tune.waves;
   out[3] = p->tune.split | (p->tune.mfma << 1) | (p->tune.gchunk << 2) | (p->tune.engine << 4) | (p->tune.persist << 5);
@@ -1018,7 +1039,8 @@ nbs_status nbs_plan_set_tuning(nbs_plan p, const int32_t in[4]) {
   const int waves = in[2];
   const int engine = (in[3] >> 4) & 1;
   const int persist = (in[3] >> 5) & 1;
-  if (in[3] < 0 || (in[3] >> 6) != 0) return fail(p, NBS_ERR_INVALID, "unknown tuning bits");
+  if (in[0] < 0 || (in[0] >> 3) != 0 || in[3] < 0 || (in[3] >> 6) != 0)
+    return fail(p, NBS_ERR_INVALID, "unknown tuning bits");
   if (persist && engine != 1) return fail(p, NBS_ERR_INVALID, "persistent workgroups need the matrix-core engine");
   if (engine == 1 ? (waves != 8 && waves != 16)
                   : (p->prec == NBS_FP64 ? waves != 8 : (waves != 4 && waves != 8)))
@@ -1030,6 +1052,7 @@ nbs_status nbs_plan_set_tuning(nbs_plan p, const int32_t in[4]) {
   const Tuning old = p->tune;
   p->tune.fft_line = in[0] & 1;
   p->tune.fft_plane = (in[0] >> 1) & 1;
+  p->tune.fft_cube = (in[0] >> 2) & 1;
   p->tune.fft_tile = tile;
   p->tune.engine = engine;
   if (engine == 1) p->tune.seg_waves = waves;

@@ -348,6 +348,27 @@ def test_set_tuning_rejects_bad_shapes():
     assert p.tuning()["waves"] == 8 and p.tuning()["engine"] == 0
 
 
+def test_transform_tuning_bits():
+    """The block transform's shapes: the one-pass cube transform on by
+    default in both forms, round-tripped with the other bits; unknown bits
+    of the first word are rejected and leave the plan unchanged."""
+    import ctypes
+    for prec in (binding.NBS_FP64, binding.NBS_FP32_MFMA):
+        p = host_plan([("p", "p", "p", "p")], prec=prec)
+        t = p.tuning()
+        assert t["fft_cube"] == 1 and t["fft_line"] == 1 and t["fft_plane"] == (1 if prec == binding.NBS_FP64 else 0)
+        p.set_tuning(fft_cube=0, fft_plane=1)
+        assert p.tuning()["fft_cube"] == 0 and p.tuning()["fft_plane"] == 1
+        p.set_tuning(fft_cube=1)
+        assert p.tuning()["fft_cube"] == 1 and p.tuning()["fft_plane"] == 1
+        before = p.tuning()
+        L = binding.lib()
+        for word0 in (1 << 3, -1):
+            arr = (ctypes.c_int32 * 4)(word0, before["fft_tile"], before["waves"], 1 | (1 << 4))
+            assert L.nbs_plan_set_tuning(p.handle, arr) == 1  # NBS_ERR_INVALID
+        assert p.tuning() == before
+
+
 def test_group_range_modes():
     """Contraction workgroups per (slice, momentum): by default one that
     walks every group; every mode is accepted and reported back."""

@@ -225,3 +225,23 @@ def test_isospin_limit_builds_canonical_blocks_only(prec):
     Fo = oracle_F(L, props, chans)
     assert rel_err_per_channel(Fi, Fo).max() <= TOL[prec]
     assert rel_err_per_channel(Fi, Fc).max() <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [binding.NBS_FP64, binding.NBS_FP32_MFMA])
+@pytest.mark.parametrize("L", [(8, 8, 8), (16, 16, 16)])
+def test_cube_pass(L, prec):
+    """The one-pass transform of 8^3 and 16^3 cubes rounds where the separate
+    passes round: the same output bit for bit as the fused x-y pass with the
+    z line pass and as three line passes, and the oracle's."""
+    announce("cube pass %s prec=%d" % (L, prec))
+    chans = [channels.r52()[c] for c in (0, 12, 22, 51)]
+    dt = np.complex128 if prec == binding.NBS_FP64 else np.complex64
+    props = runner.host_props(L, 2, range(1), dtype=dt)
+    Fc = run_gpu(L, 2, chans, props, prec, t_count=1, tuning=dict(fft_cube=1, fft_plane=0))
+    Fp = run_gpu(L, 2, chans, props, prec, t_count=1, tuning=dict(fft_cube=0, fft_plane=1))
+    Fl = run_gpu(L, 2, chans, props, prec, t_count=1, tuning=dict(fft_cube=0, fft_plane=0))
+    assert np.array_equal(Fc.view(np.float64), Fp.view(np.float64))
+    assert np.array_equal(Fc.view(np.float64), Fl.view(np.float64))
+    Fo = oracle_F(L, props, chans)
+    err = rel_err_per_channel(Fc, Fo)
+    assert err.max() <= TOL[prec], (err.max(), int(err.argmax()))
