@@ -397,21 +397,24 @@ __global__ __launch_bounds__(NT) void k_fft_plane(FftPlaneArgs a) {
 
 // All three axes of a forward block transform on a cubic lattice in one
 // pass.  Workgroup (cube, field tile) keeps the N^3 x IB tile in registers:
-// thread (x, y) loads the z column (x, y) of IB consecutive fields (runs of
-// IB entries per site).  The x and y axes go through LDS, ZB planes of z at
-// a time: the threads write the planes, transform every x line, then every
-// y line, of each (plane, field), each line by one thread in registers, and
+// LP lanes share the z column (x, y) of the tile's IB fields, lane l of
+// them holding fields l, l + LP, ..., so that adjacent lanes load adjacent
+// fields of a site.  The x and y axes go through LDS, ZB planes of z at a
+// time: the threads write the planes, transform every x line, then every y
+// line, of each (plane, field), each line by one thread in registers, and
 // read their values back; the z axis is then transformed in registers and
 // stored: one HBM read and one write for the three axes.  Rows in LDS are
-// padded to N + 1 entries so that the x lines, whose threads differ in y,
-// fall in different banks.  Values are rounded to the storage type after
-// each axis, in the order x, y, z, and the arithmetic is FP64, as in the
-// separate passes, so the results are the same bit for bit.  In place is
-// allowed: a workgroup reads its whole tile before writing it.
-template <int N, int IB, int ZB, typename T>
-__global__ __launch_bounds__(N * N) void k_fft_cube(FftPlaneArgs a) {
-  constexpr int NT = N * N, SY = N + 1, SP = N * SY, LINES = ZB * IB * N;
-  static_assert(N % ZB == 0 && LINES % NT == 0, "cube tile shape");
+// padded to N + 1 entries, so that the x lines, whose threads differ in y,
+// fall in different banks, and the planes of the fields lie 8 entries off
+// a multiple of the bank cycle, so that the lanes of one site do too.
+// Values are rounded to the storage type after each axis, in the order x,
+// y, z, and the arithmetic is FP64, as in the separate passes, so the
+// results are the same bit for bit.  In place is allowed: a workgroup reads
+// its whole tile before writing it.
+template <int N, int IB, int LP, int ZB, typename T>
+__global__ __launch_bounds__(N * N * LP) void k_fft_cube(FftPlaneArgs a) {
+  constexpr int NT = N * N * LP, FT = IB / LP, SY = N + 1, SP = N * SY + 8, LINES = ZB * IB * N;
+  static_assert(N % ZB == 0 && IB % LP == 0, "cube tile shape");
   extern __shared__ __align__(16) char smem_cube[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_cube);  // [plane][field][y][x], rows padded
   const long long n_ftiles = a.inner / IB;
@@ -423,21 +426,21 @@ __global__ __launch_bounds__(N * N) void k_fft_cube(FftPlaneArgs a) {
   const long long wg = a.unit0 + local;
   const long long cube = wg / n_ftiles, f0 = (wg % n_ftiles) * IB;
   constexpr long long V = (long long)N * N * N;
-  const cx<T>* in = reinterpret_cast<const cx<T>*>(a.in) + cube * V * a.inner + f0;
-  cx<T>* out = reinterpret_cast<cx<T>*>(a.out) + cube * V * a.inner + f0;
-  const int px = threadIdx.x % N, py = threadIdx.x / N;
-  cx<T> R[IB][N];
+  const int lane = threadIdx.x % LP, col = threadIdx.x / LP, px = col % N, py = col / N;
+  const cx<T>* in = reinterpret_cast<const cx<T>*>(a.in) + cube * V * a.inner + f0 + lane;
+  cx<T>* out = reinterpret_cast<cx<T>*>(a.out) + cube * V * a.inner + f0 + lane;
+  cx<T> R[FT][N];
   // every load issued before the first use
 #pragma unroll
   for (int z = 0; z < N; ++z)
 #pragma unroll
-    for (int f = 0; f < IB; ++f) R[f][z] = in[((long long)(z * N + py) * N + px) * a.inner + f];
+    for (int j = 0; j < FT; ++j) R[j][z] = in[((long long)(z * N + py) * N + px) * a.inner + j * LP];
 #pragma unroll
   for (int b = 0; b < N / ZB; ++b) {
 #pragma unroll
     for (int k = 0; k < ZB; ++k)
 #pragma unroll
-      for (int f = 0; f < IB; ++f) buf[(k * IB + f) * SP + py * SY + px] = R[f][b * ZB + k];
+      for (int j = 0; j < FT; ++j) buf[(k * IB + lane + j * LP) * SP + py * SY + px] = R[j][b * ZB + k];
     __syncthreads();
     // x lines: (plane and field, y)
     for (int l = threadIdx.x; l < LINES; l += NT) {
@@ -452,35 +455,35 @@ __global__ __launch_bounds__(N * N) void k_fft_cube(FftPlaneArgs a) {
     __syncthreads();
     // y lines: (plane and field, x)
     for (int l = threadIdx.x; l < LINES; l += NT) {
-      cx<T>* col = buf + (l / N) * SP + (l % N);
+      cx<T>* cl = buf + (l / N) * SP + (l % N);
       cd v[N];
 #pragma unroll
-      for (int y = 0; y < N; ++y) v[y] = conv<double>(col[y * SY]);
+      for (int y = 0; y < N; ++y) v[y] = conv<double>(cl[y * SY]);
       fft_reg<N, -1>(v);
 #pragma unroll
-      for (int y = 0; y < N; ++y) col[y * SY] = conv<T>(v[y]);
+      for (int y = 0; y < N; ++y) cl[y * SY] = conv<T>(v[y]);
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < ZB; ++k)
 #pragma unroll
-      for (int f = 0; f < IB; ++f) R[f][b * ZB + k] = buf[(k * IB + f) * SP + py * SY + px];
+      for (int j = 0; j < FT; ++j) R[j][b * ZB + k] = buf[(k * IB + lane + j * LP) * SP + py * SY + px];
     if (b + 1 < N / ZB) __syncthreads();
   }
   // z lines in registers
 #pragma unroll
-  for (int f = 0; f < IB; ++f) {
+  for (int j = 0; j < FT; ++j) {
     cd v[N];
 #pragma unroll
-    for (int z = 0; z < N; ++z) v[z] = conv<double>(R[f][z]);
+    for (int z = 0; z < N; ++z) v[z] = conv<double>(R[j][z]);
     fft_reg<N, -1>(v);
 #pragma unroll
-    for (int z = 0; z < N; ++z) R[f][z] = conv<T>(v[z]);
+    for (int z = 0; z < N; ++z) R[j][z] = conv<T>(v[z]);
   }
 #pragma unroll
   for (int z = 0; z < N; ++z)
 #pragma unroll
-    for (int f = 0; f < IB; ++f) out[((long long)(z * N + py) * N + px) * a.inner + f] = R[f][z];
+    for (int j = 0; j < FT; ++j) out[((long long)(z * N + py) * N + px) * a.inner + j * LP] = R[j][z];
 }
 
 // ---------------------------------------------------------------------------
@@ -2461,19 +2464,22 @@ template <int N, typename T> hipError_t launch_plane_t(const FftPlaneArgs& a, hi
 }  // namespace
 
 namespace {
-// fields per cube workgroup: runs of 32 bytes per site, held in registers
-// (two workgroups per CU; 16-byte runs and 64-byte runs, which leave one
-// workgroup per CU, measured slower at 16^3)
+// Shape of the cube workgroups, measured at 16^3: runs of 32 bytes per site
+// (16-byte runs, and 64-byte runs that leave one workgroup per CU, measured
+// slower), LDS batches of 8 planes (all 16 measured slower); FP64 fields
+// shared by lane pairs (one field per thread measured faster than two);
+// complex64 fields four to a thread (lane teams of four, which need
+// 1024-thread workgroups, measured slower).
 template <typename T> constexpr int cube_ib() { return 32 / (int)sizeof(cx<T>); }
-// planes of z per LDS batch
-constexpr int cube_zb(int n) { return n < 8 ? n : 8; }
+template <typename T> constexpr int cube_lp() { return sizeof(T) == 8 ? 2 : 1; }
+template <typename T> constexpr int cube_zb(int n) { return n < 8 ? n : 8; }
 template <int N, typename T> constexpr size_t cube_lds() {
-  return sizeof(cx<T>) * (size_t)cube_zb(N) * cube_ib<T>() * N * (N + 1);
+  return sizeof(cx<T>) * (size_t)cube_zb<T>(N) * cube_ib<T>() * (N * (N + 1) + 8);
 }
 
 template <int N, typename T> hipError_t launch_cube_t(const FftPlaneArgs& a, hipStream_t st) {
-  constexpr int IB = cube_ib<T>();
-  constexpr int NT = N * N, ZB = cube_zb(N);
+  constexpr int IB = cube_ib<T>(), LP = cube_lp<T>(), ZB = cube_zb<T>(N);
+  constexpr int NT = N * N * LP;
   constexpr size_t lds = cube_lds<N, T>();
   if (a.IB != IB || a.inner % IB != 0) return hipErrorInvalidValue;
   const long long wgs = a.planes * (a.inner / IB);
@@ -2482,7 +2488,8 @@ template <int N, typename T> hipError_t launch_cube_t(const FftPlaneArgs& a, hip
     FftPlaneArgs c = a;
     c.unit0 = w0;
     c.n_units = wgs - w0 < chunk ? wgs - w0 : chunk;
-    hipLaunchKernelGGL((k_fft_cube<N, IB, ZB, T>), dim3((unsigned)((c.n_units + 7) / 8 * 8)), dim3(NT), lds, st, c);
+    hipLaunchKernelGGL((k_fft_cube<N, IB, LP, ZB, T>), dim3((unsigned)((c.n_units + 7) / 8 * 8)), dim3(NT), lds, st,
+                       c);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -2606,10 +2613,14 @@ hipError_t prepare_kernels(int prec, int waves, size_t contract_lds, int engine)
   set((const void*)k_fft_plane<24, plane_ib<float>(24), float, plane_threads<float>(24)>, 128 * 1024);
   set((const void*)k_fft_plane<32, plane_ib<float>(32), float, plane_threads<float>(32)>, 128 * 1024);
   set((const void*)k_fft_plane<40, plane_ib<float>(40), float, plane_threads<float>(40)>, 128 * 1024);
-  set((const void*)k_fft_cube<8, cube_ib<double>(), cube_zb(8), double>, (int)cube_lds<8, double>());
-  set((const void*)k_fft_cube<16, cube_ib<double>(), cube_zb(16), double>, (int)cube_lds<16, double>());
-  set((const void*)k_fft_cube<8, cube_ib<float>(), cube_zb(8), float>, (int)cube_lds<8, float>());
-  set((const void*)k_fft_cube<16, cube_ib<float>(), cube_zb(16), float>, (int)cube_lds<16, float>());
+  set((const void*)k_fft_cube<8, cube_ib<double>(), cube_lp<double>(), cube_zb<double>(8), double>,
+      (int)cube_lds<8, double>());
+  set((const void*)k_fft_cube<16, cube_ib<double>(), cube_lp<double>(), cube_zb<double>(16), double>,
+      (int)cube_lds<16, double>());
+  set((const void*)k_fft_cube<8, cube_ib<float>(), cube_lp<float>(), cube_zb<float>(8), float>,
+      (int)cube_lds<8, float>());
+  set((const void*)k_fft_cube<16, cube_ib<float>(), cube_lp<float>(), cube_zb<float>(16), float>,
+      (int)cube_lds<16, float>());
   if (engine == 1) {
     if (prec == 0) {
       set(waves == 16 ? (const void*)k_contract_seg<double, 1024> : (const void*)k_contract_seg<double, 512>,
