@@ -49,7 +49,7 @@ extern "C" {
 typedef enum {
   NBS_OK = 0,
   NBS_ERR_INVALID = 1,     /* bad argument (geometry, channel, pointer) */
-  NBS_ERR_UNSUPPORTED = 2, /* valid request this build does not handle */
+  NBS_ERR_UNSUPPORTED = 2, /* valid request the library does not handle */
   NBS_ERR_NOMEM = 3,       /* device workspace does not fit */
   NBS_ERR_DEVICE = 4,      /* a HIP call failed */
   NBS_ERR_STATE = 5        /* calls out of order, or compute on a host-only plan */

@@ -417,7 +417,7 @@ nbs_status enqueue_build(nbs_plan p, const void* const* pu, const void* const* p
   // first n_canon slots) are built and transformed (Sec. 4(i))
   p->iso = isospin_limit(p, pu, pd);
   const int n_build = p->iso ? p->comp.prog.n_canon : p->comp.prog.n_ops;
-  // the non-finite input flag of this build (a fill kernel, not a memset,
+  // the non-finite input flag of this block build (a fill kernel, not a memset,
   // so that the sequence can be captured into a graph)
   if ((s = hip_check(p, nbs::launch_fill_u32(p->nonfinite, 0u, 1, st), "fill")) != NBS_OK) return s;
   for (size_t i = 0; i < p->gw.size(); ++i) {
