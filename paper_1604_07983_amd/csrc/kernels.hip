@@ -486,6 +486,66 @@ __global__ __launch_bounds__(N * N * LP) void k_fft_cube(FftPlaneArgs a) {
     for (int j = 0; j < FT; ++j) out[((long long)(z * N + py) * N + px) * a.inner + j * LP] = R[j][z];
 }
 
+// The inverse transform of the relative sum (Eq. (6)) on a cubic lattice
+// in one pass: the fields are contiguous N^3 cubes (one per channel, slice
+// and spin pair), so a workgroup loads one cube into LDS in runs of N
+// entries, transforms every x line, then every y line, then every z line
+// (each by one thread in registers, FP64), and stores it scaled by
+// gscale oscale[cube / oscale_div] straight from the z lines.  Rows are
+// padded to N + 1 entries (the x lines' threads differ in y).  In place is
+// allowed: the cube is read whole before it is written.
+template <int N, typename Tin>
+__global__ __launch_bounds__(N * N) void k_fft_cube_inv(FftArgs a) {
+  constexpr int NT = N * N, SY = N + 1, SZ = N * SY;
+  constexpr long long V = (long long)N * N * N;
+  extern __shared__ __align__(16) char smem_cinv[];
+  cd* tile = reinterpret_cast<cd*>(smem_cinv);  // [z][y][x], x padded
+  const long long cube = a.unit0 + blockIdx.x;
+  if (cube >= a.outer) return;
+  const cx<Tin>* in = reinterpret_cast<const cx<Tin>*>(a.in) + cube * V;
+  cd* out = reinterpret_cast<cd*>(a.out) + cube * V;
+  for (int e = threadIdx.x; e < N * N * N; e += NT) {
+    const int x = e % N, yz = e / N;
+    tile[(yz / N) * SZ + (yz % N) * SY + x] = conv<double>(in[e]);
+  }
+  __syncthreads();
+  const int pp = threadIdx.x % N, qq = threadIdx.x / N;
+  {
+    // x lines (y, z) = (pp, qq)
+    cd* row = tile + qq * SZ + pp * SY;
+    cd v[N];
+#pragma unroll
+    for (int x = 0; x < N; ++x) v[x] = row[x];
+    fft_reg<N, 1>(v);
+#pragma unroll
+    for (int x = 0; x < N; ++x) row[x] = v[x];
+  }
+  __syncthreads();
+  {
+    // y lines (x, z) = (pp, qq)
+    cd* cl = tile + qq * SZ + pp;
+    cd v[N];
+#pragma unroll
+    for (int y = 0; y < N; ++y) v[y] = cl[y * SY];
+    fft_reg<N, 1>(v);
+#pragma unroll
+    for (int y = 0; y < N; ++y) cl[y * SY] = v[y];
+  }
+  __syncthreads();
+  {
+    // z lines (x, y) = (pp, qq), scaled and stored
+    cd* cl = tile + qq * SY + pp;
+    cd v[N];
+#pragma unroll
+    for (int z = 0; z < N; ++z) v[z] = cl[z * SZ];
+    fft_reg<N, 1>(v);
+    double f = a.gscale;
+    if (a.oscale) f *= a.oscale[cube / a.oscale_div];
+#pragma unroll
+    for (int z = 0; z < N; ++z) out[(z * N + qq) * N + pp] = cd{v[z].re * f, v[z].im * f};
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Effective blocks and their products (Sec. 4(ii)-(iii), Eqs. (9)-(10)).
 //
@@ -2526,6 +2586,33 @@ int fft_plane_fields(int n, long long inner, int kind) {
   return inner % ib == 0 && ib * el >= 64 ? ib : 0;
 }
 
+namespace {
+template <int N> constexpr size_t cube_inv_lds() { return sizeof(cd) * (size_t)N * N * (N + 1); }
+
+template <int N, typename Tin> hipError_t launch_cube_inv_t(const FftArgs& a, hipStream_t st) {
+  constexpr int NT = N * N;
+  constexpr size_t lds = cube_inv_lds<N>();
+  const long long chunk = kMaxLaunchItems / NT;
+  for (long long c0 = 0; c0 < a.outer; c0 += chunk) {
+    FftArgs c = a;
+    c.unit0 = c0;
+    const long long n = a.outer - c0 < chunk ? a.outer - c0 : chunk;
+    hipLaunchKernelGGL((k_fft_cube_inv<N, Tin>), dim3((unsigned)n), dim3(NT), lds, st, c);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+}  // namespace
+
+bool fft_cube_inv_supported(int n, int kind) { return (n == 8 || n == 16) && (kind == 0 || kind == 2); }
+
+hipError_t launch_fft_cube_inv(int kind, const FftArgs& a, hipStream_t st) {
+  if (a.inner != 1 || a.sign < 0 || !fft_cube_inv_supported(a.n, kind)) return hipErrorInvalidValue;
+  if (kind == 0) return a.n == 8 ? launch_cube_inv_t<8, double>(a, st) : launch_cube_inv_t<16, double>(a, st);
+  return a.n == 8 ? launch_cube_inv_t<8, float>(a, st) : launch_cube_inv_t<16, float>(a, st);
+}
+
 hipError_t launch_fft_plane(int kind, int n, const FftPlaneArgs& a, hipStream_t st) {
   if (kind == 0) {
     switch (n) {
@@ -2613,6 +2700,8 @@ hipError_t prepare_kernels(int prec, int waves, size_t contract_lds, int engine)
   set((const void*)k_fft_plane<24, plane_ib<float>(24), float, plane_threads<float>(24)>, 128 * 1024);
   set((const void*)k_fft_plane<32, plane_ib<float>(32), float, plane_threads<float>(32)>, 128 * 1024);
   set((const void*)k_fft_plane<40, plane_ib<float>(40), float, plane_threads<float>(40)>, 128 * 1024);
+  set((const void*)k_fft_cube_inv<16, double>, (int)cube_inv_lds<16>());
+  set((const void*)k_fft_cube_inv<16, float>, (int)cube_inv_lds<16>());
   set((const void*)k_fft_cube<8, cube_ib<double>(), cube_lp<double>(), cube_zb<double>(8), double>,
       (int)cube_lds<8, double>());
   set((const void*)k_fft_cube<16, cube_ib<double>(), cube_lp<double>(), cube_zb<double>(16), double>,

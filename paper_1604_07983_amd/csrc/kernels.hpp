@@ -186,6 +186,10 @@ int fft_plane_fields(int n, long long inner, int kind);
 // kernel for this length, storage kind or field count)
 int fft_cube_fields(int n, long long inner, int kind);
 hipError_t launch_fft_cube(int kind, int n, const FftPlaneArgs& a, hipStream_t st);
+// the inverse transform of contiguous n^3 cubes (inner 1, sign +1) in one
+// pass, kind 0 (complex128 in) or 2 (complex64 in), complex128 out
+bool fft_cube_inv_supported(int n, int kind);
+hipError_t launch_fft_cube_inv(int kind, const FftArgs& a, hipStream_t st);
 hipError_t launch_fft_plane(int kind, int n, const FftPlaneArgs& a, hipStream_t st);
 hipError_t launch_fft_line(int kind, const FftArgs& a, hipStream_t st);
 size_t contract_lds_bytes(int prec, int max_gprod, int max_gcontrib, int max_gch, int max_gtask);

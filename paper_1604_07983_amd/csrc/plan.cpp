@@ -211,6 +211,21 @@ nbs_status fft3d(nbs_plan p, int kind_first, int kind_rest, const void* in, void
                  double gscale, hipStream_t st) {
   const long long V = (long long)L[0] * L[1] * L[2];
   int ax0 = 0;
+  // contiguous cubic fields of the inverse transform: all three axes in one pass
+  if (p->tune.fft_cube && sign > 0 && inner0 == 1 && L[0] == L[1] && L[1] == L[2] && kind_rest == 0 &&
+      nbs::fft_cube_inv_supported(L[0], kind_first)) {
+    nbs::FftArgs a{};
+    a.in = in;
+    a.out = out;
+    a.outer = batch;
+    a.inner = 1;
+    a.n = L[0];
+    a.sign = sign;
+    a.gscale = gscale;
+    a.oscale = oscale;
+    a.oscale_div = oscale_div;
+    return hip_check(p, nbs::launch_fft_cube_inv(kind_first, a, st), "fft cube inverse");
+  }
   // cubic lattices of a forward block transform: all three axes in one pass
   const int cib = p->tune.fft_cube && L[0] == L[1] && L[1] == L[2] && sign < 0 && oscale == nullptr &&
                           gscale == 1.0 && kind_first == kind_rest

@@ -16,6 +16,8 @@ bool fft_line_supported(int, int) { return false; }
 int fft_plane_fields(int, long long, int) { return 0; }
 int fft_cube_fields(int, long long, int) { return 0; }
 hipError_t launch_fft_cube(int, int, const FftPlaneArgs&, hipStream_t) { return hipErrorNotSupported; }
+bool fft_cube_inv_supported(int, int) { return false; }
+hipError_t launch_fft_cube_inv(int, const FftArgs&, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_fft_plane(int, int, const FftPlaneArgs&, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_fft_line(int, const FftArgs&, hipStream_t) { return hipErrorNotSupported; }
 size_t contract_lds_bytes(int, int, int, int, int) { return 0; }
