@@ -185,8 +185,10 @@ nbs_status nbs_plan_autotune(nbs_plan plan, const void* const* prop_u, const voi
 
 /* The plan's launch shapes: out[0] bit 0 register line FFT on/off, bit 1
  * fused x-y pass for square planes on/off, bit 2 one pass for all three
- * axes of 8^3 and 16^3 lattices on/off (on by default; the three choices
- * give the same values bit for bit); out[1] LDS FFT tile elements;
+ * axes of 8^3 and 16^3 lattices on/off, forward and inverse (on by
+ * default; the forward choices give the same blocks bit for bit, the
+ * inverse ones the same F up to FP64 rounding order); out[1] LDS FFT tile
+ * elements;
  * out[2] wavefronts per contraction workgroup of the selected engine;
  * out[3] bit 4 the contraction engine (1: matrix-core segments, the
  * default in both forms; 0: lane teams), bits 2-3 the contraction
