@@ -3,9 +3,16 @@
 //   k_nbb       normal baryon blocks, Eq. (5) / Sec. 4(i) Eq. (8)
 //   k_fft_line  one axis of the in-house batched 3-D FFT (Eq. (6)), one line
 //               per thread in registers
+//   k_fft_line2 the same for 64, 80 and 96 points, two threads per line
 //   k_fft_pass  the same through LDS tiles, for the lengths k_fft_line lacks
+//   k_fft_plane the x and y axes of square planes of block fields together
+//   k_fft_cube  all three axes of 8^3 and 16^3 block fields in one pass;
+//               k_fft_cube_inv the inverse of contiguous 8^3 and 16^3 fields
 //   k_contract  effective blocks and their products, Sec. 4(ii)-(iii),
-//               Eqs. (9)-(10), driven by the compiled SoA program
+//               Eqs. (9)-(10), driven by the compiled SoA program (lane
+//               teams); k_contract_seg the same as segments on the matrix
+//               cores
+//   k_two_point zero-momentum single-baryon correlators from the blocks
 //   k_absmax / k_scale_exps / k_channel_scale   per-slice power-of-two
 //               scale of the precision form and its exact undo
 #include <hip/hip_runtime.h>
