@@ -48,6 +48,17 @@ def test_static_path_matches_plan_path_twice(prec):
         assert err.max() <= TOL[prec], (k, err.max())
 
 
+@pytest.mark.parametrize("prec", [binding.NBS_FP64, binding.NBS_FP32_MFMA])
+def test_static_path_cubic_lattice(prec):
+    """An 8^3 lattice (the one-pass forward and inverse transforms) through
+    the workspace, pp only so that its blocks fit."""
+    L, T, tc = (8, 8, 8), 2, 1
+    announce("static path cubic prec=%d L=%s" % (prec, L))
+    Fs, Fp = _both(L, T, [("p", "p", "p", "p")], prec, tc)
+    assert np.isfinite(Fs).all()
+    assert rel_err_per_channel(Fs, Fp).max() <= TOL[prec]
+
+
 def test_static_path_rejects_too_large():
     import torch
     announce("static path size limit")
