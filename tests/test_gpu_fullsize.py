@@ -81,13 +81,19 @@ def test_config3_fp32_32c64_windows(t_begin):
 def test_config3_fp32_32c64_bench_window():
     """The benchmark's exact launch: 32^3 x 64, one 16-slice window (10.5 M
     contraction workgroups, more work-items than one dispatch can address, so
-    the launch is split); the first and the last slice at sampled momenta."""
+    the launch is split); the first and the last slice at sampled momenta,
+    and the first slice over every r for a channel of the first and of the
+    last strangeness sector."""
     announce("32^3 x 64 precision form, 16-slice window")
     L, T = (32, 32, 32), 64
     chans = channels.r52()
     props, Fg = run_window(L, T, binding.NBS_FP32_MFMA, 0, 16, chans)
     assert np.isfinite(Fg).all()
     check_sampled_momenta(L, props, Fg, chans, slices=(0, 15), qs=((0, 0, 0), (31, 5, 17)), tol=1e-5)
+    sub = [0, 51]
+    Fo = oracle.correlators(L, flat_props(props, 0), [chans[c] for c in sub], mode="fft")
+    err = rel_err_per_channel(Fg[sub][:, 0:1], Fo[:, None])
+    assert err.max() <= 1e-5, err
 
 
 def test_config5_96cubed_slice_closed_form():
